@@ -1,0 +1,224 @@
+"""CPU oracle for the Cholesky solver -- TEST INFRASTRUCTURE, NOT PRODUCT CODE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU-baseline
+leg may import this package.  It wraps ``oracle.c`` (plain FP64 C, built by
+``oracle/build.sh`` / ``__graft_entry__.build()``) through ctypes and shares
+nothing with the GPU library.
+
+Every function takes numpy arrays with (row, column) semantics and converts
+them to column-major (Fortran) order before the C call; results come back in
+Fortran order with the same semantics.  Only the lower triangle of ``A`` is
+read, so a full symmetric array or one whose upper triangle holds garbage give
+the same answer.
+
+What each routine computes (definitions, paper: JAXMg "Software design",
+potrs bullet -- a Cholesky solve of a symmetric positive-definite system,
+optionally with log det):
+
+* ``potrf``     -- lower L with positive diagonal, A = L L^T; info = first
+                   1-based column whose pivot is not > 0 (0 on success).
+* ``potrs``     -- X = A^{-1} B by forward then back substitution.
+* ``residual``  -- R = B - A X in extended precision and the per-column
+                   normwise backward error eta_j = |r_j|inf / (|A|inf |x_j|inf
+                   + |b_j|inf).
+* ``logdet``    -- 2 sum log L_jj.
+* ``posv_ir``   -- single-precision (or bfloat16-operand) factor plus FP64
+                   iterative refinement; falls back to FP64 when it stalls.
+* ``posv_backward`` -- gB = A^{-1} gX, gA = -1/2 (gB X^T + X gB^T).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_i64 = ctypes.c_int64
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build() -> str:
+    """Compile oracle.c with gcc into liboracle.so (always recompiles)."""
+    src = os.path.join(_HERE, "oracle.c")
+    cmd = ["gcc", "-O3", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+           "-o", _LIB_PATH, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.or_potrf.argtypes = [_i64, _dp, _i64]
+    lib.or_potrf.restype = _i64
+    lib.or_potrs.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64]
+    lib.or_potrs.restype = None
+    lib.or_posv.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64]
+    lib.or_posv.restype = _i64
+    lib.or_logdet.argtypes = [_i64, _dp, _i64]
+    lib.or_logdet.restype = ctypes.c_double
+    lib.or_sym_norm_inf.argtypes = [_i64, _dp, _i64]
+    lib.or_sym_norm_inf.restype = ctypes.c_double
+    lib.or_residual.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64, _dp, _i64, _dp]
+    lib.or_residual.restype = ctypes.c_double
+    lib.or_potrf_lo.argtypes = [_i64, _fp, _i64, ctypes.c_int]
+    lib.or_potrf_lo.restype = _i64
+    lib.or_potrs_lo.argtypes = [_i64, _i64, _fp, _i64, _fp, _i64]
+    lib.or_potrs_lo.restype = None
+    lib.or_posv_ir.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64,
+                               ctypes.c_int, ctypes.c_double, ctypes.c_int, _ip, _ip, _dp]
+    lib.or_posv_ir.restype = _i64
+    lib.or_posv_backward.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64,
+                                     _dp, _i64, _dp, _i64, ctypes.c_int]
+    lib.or_posv_backward.restype = None
+    lib.or_num_threads.argtypes = []
+    lib.or_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.asfortranarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: np.ndarray, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+def _ld(a: np.ndarray) -> int:
+    return max(1, a.shape[0])
+
+
+def _as2d(b):
+    b = np.asarray(b)
+    return (b.reshape(-1, 1), True) if b.ndim == 1 else (b, False)
+
+
+def num_threads() -> int:
+    return int(_load().or_num_threads())
+
+
+def potrf(A):
+    """Return (L, info).  L is lower triangular (strict upper set to 0)."""
+    lib = _load()
+    W = _f64(A).copy(order="F")
+    n = W.shape[0]
+    info = lib.or_potrf(n, _ptr(W), _ld(W))
+    return np.tril(W), int(info)
+
+
+def potrs(L, B):
+    """X with L L^T X = B (L lower; only its lower triangle is read)."""
+    lib = _load()
+    Lf = _f64(L)
+    B2, flat = _as2d(B)
+    X = _f64(B2).copy(order="F")
+    n, nrhs = X.shape
+    lib.or_potrs(n, nrhs, _ptr(Lf), _ld(Lf), _ptr(X), _ld(X))
+    return X.ravel() if flat else X
+
+
+def posv(A, B):
+    """Return (X, info) for A X = B."""
+    lib = _load()
+    W = _f64(A).copy(order="F")
+    B2, flat = _as2d(B)
+    X = _f64(B2).copy(order="F")
+    n, nrhs = X.shape
+    info = lib.or_posv(n, nrhs, _ptr(W), _ld(W), _ptr(X), _ld(X))
+    return (X.ravel() if flat else X), int(info)
+
+
+def logdet(L) -> float:
+    Lf = _f64(L)
+    return float(_load().or_logdet(Lf.shape[0], _ptr(Lf), _ld(Lf)))
+
+
+def sym_norm_inf(A) -> float:
+    Af = _f64(A)
+    return float(_load().or_sym_norm_inf(Af.shape[0], _ptr(Af), _ld(Af)))
+
+
+def residual(A, X, B):
+    """Return (R, eta, anorm): R = B - A X in extended precision (rounded to
+    FP64 on output), eta per column, |A|inf of the symmetric matrix."""
+    lib = _load()
+    Af = _f64(A)
+    X2, flat = _as2d(X)
+    B2, _ = _as2d(B)
+    Xf, Bf = _f64(X2), _f64(B2)
+    n, nrhs = Xf.shape
+    R = np.zeros((n, nrhs), dtype=np.float64, order="F")
+    eta = np.zeros(nrhs, dtype=np.float64)
+    anorm = lib.or_residual(n, nrhs, _ptr(Af), _ld(Af), _ptr(Xf), _ld(Xf),
+                            _ptr(Bf), _ld(Bf), _ptr(R), _ld(R), _ptr(eta))
+    return (R.ravel() if flat else R), eta, float(anorm)
+
+
+def backward_error(A, X, B) -> np.ndarray:
+    """Per-column normwise backward error eta_j (extended-precision residual)."""
+    return residual(A, X, B)[1]
+
+
+def potrf_lo(A, lo: int = 1):
+    """Low-precision factor of fl32(A): lo=1 binary32, lo=2 bfloat16 operands."""
+    lib = _load()
+    W = np.asfortranarray(np.asarray(A, dtype=np.float64).astype(np.float32))
+    n = W.shape[0]
+    info = lib.or_potrf_lo(n, _ptr(W, _fp), _ld(W), int(lo))
+    return np.tril(W), int(info)
+
+
+def posv_ir(A, B, lo: int = 1, tol: float = 1e-12, max_iter: int = 30):
+    """Mixed-precision solve with FP64 iterative refinement.
+
+    Returns (X, dict(iters, fell_back, eta, info))."""
+    lib = _load()
+    Af = _f64(A)
+    B2, flat = _as2d(B)
+    Bf = _f64(B2)
+    n, nrhs = Bf.shape
+    X = np.zeros((n, nrhs), dtype=np.float64, order="F")
+    iters, fb = ctypes.c_int(0), ctypes.c_int(0)
+    eta = ctypes.c_double(0.0)
+    info = lib.or_posv_ir(n, nrhs, _ptr(Af), _ld(Af), _ptr(Bf), _ld(Bf), _ptr(X), _ld(X),
+                          int(lo), float(tol), int(max_iter),
+                          ctypes.byref(iters), ctypes.byref(fb), ctypes.byref(eta))
+    stats = dict(iters=iters.value, fell_back=bool(fb.value), eta=eta.value, info=int(info))
+    return (X.ravel() if flat else X), stats
+
+
+def posv_backward(L, X, GX, mode: int = 0):
+    """Return (gB, gA) for X = A^{-1} B, A = L L^T, upstream gradient gX."""
+    lib = _load()
+    Lf = _f64(L)
+    X2, flat = _as2d(X)
+    G2, _ = _as2d(GX)
+    Xf, Gf = _f64(X2), _f64(G2)
+    n, nrhs = Xf.shape
+    GB = np.zeros((n, nrhs), dtype=np.float64, order="F")
+    GA = np.zeros((n, n), dtype=np.float64, order="F")
+    lib.or_posv_backward(n, nrhs, _ptr(Lf), _ld(Lf), _ptr(Xf), _ld(Xf), _ptr(Gf), _ld(Gf),
+                         _ptr(GB), _ld(GB), _ptr(GA), _ld(GA), int(mode))
+    return (GB.ravel() if flat else GB), GA
+
+
+def posv_batched(As, Bs):
+    """Loop of independent posv calls; returns (list of X, list of info)."""
+    xs, infos = [], []
+    for A, B in zip(As, Bs):
+        x, info = posv(A, B)
+        xs.append(x)
+        infos.append(info)
+    return xs, infos

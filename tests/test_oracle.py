@@ -1,0 +1,361 @@
+"""Pins for the CPU oracle: every check here is fixed by mathematics or by the
+paper's own benchmark recipe, never by re-running the oracle's formula.
+
+Paper: JAXMg, "Software design" (potrs: Cholesky solve of an SPD system,
+optionally log det) and "Performance and scaling" (A = diag(1..N), b = ones).
+"""
+import ctypes
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import synth
+from golden_io import as_float, worked_examples
+
+EPS = np.finfo(np.float64).eps
+
+
+# ---------------------------------------------------------- worked examples
+@pytest.mark.parametrize("name", ["2x2", "3x3", "diag_1_to_8"])
+def test_worked_examples_exact(orc, name):
+    case = worked_examples()[name]
+    A = as_float(case["A"])
+    L, info = orc.potrf(A)
+    assert info == 0
+    if "L" in case:
+        assert np.array_equal(L, as_float(case["L"]))
+    else:  # diag(1..N): L = diag(sqrt(i))
+        assert np.allclose(L, np.diag(np.sqrt(np.diag(A))), rtol=0, atol=0)
+    x = orc.potrs(L, as_float(case["b"]))
+    xt = as_float(case["x"])
+    assert np.allclose(x, xt, rtol=4 * EPS, atol=0)
+    assert math.isclose(orc.logdet(L), case["logdet"], rel_tol=1e-14)
+
+
+# ---------------------------------------------------- integer-exact family
+@pytest.mark.parametrize("n,seed", [(1, 0), (7, 1), (64, 2), (200, 3), (333, 4)])
+def test_integer_family_bitwise(orc, n, seed):
+    L0, A = synth.integer_exact(n, seed)
+    L, info = orc.potrf(A)
+    assert info == 0
+    assert np.array_equal(L, L0)
+    xt = synth.integer_vector((n, 3), seed + 10)
+    B = A @ xt  # exact: integers well below 2^53
+    X = orc.potrs(L, B)
+    assert np.array_equal(X, xt)
+    assert orc.logdet(L) == pytest.approx(2 * np.sum(np.log(np.diag(L0))), rel=1e-14, abs=1e-14)
+
+
+# ----------------------------------------------------------- closed forms
+@pytest.mark.parametrize("n", [1, 2, 5, 64, 300])
+def test_lehmer_closed_form(orc, n):
+    A = synth.lehmer(n)
+    L, info = orc.potrf(A)
+    assert info == 0
+    i = np.arange(1, n + 1, dtype=np.float64)
+    # L_ij = sqrt(2j-1)/i for i >= j (1-based)
+    Lx = np.tril(np.sqrt(2 * i - 1)[None, :] / i[:, None])
+    assert np.allclose(L, Lx, rtol=8 * EPS * n, atol=0)
+    ld = np.sum(np.log((2 * i - 1) / i ** 2))
+    assert orc.logdet(L) == pytest.approx(ld, rel=1e-12, abs=1e-12)
+    # inverse is tridiagonal with a closed form
+    Ainv = orc.potrs(L, np.eye(n))
+    T = np.zeros((n, n))
+    for k in range(1, n + 1):
+        T[k - 1, k - 1] = 4 * k ** 3 / (4 * k ** 2 - 1) if k < n else n ** 2 / (2 * n - 1)
+        if k < n:
+            T[k - 1, k] = T[k, k - 1] = -k * (k + 1) / (2 * k + 1)
+    if n == 1:
+        T[0, 0] = 1.0
+    assert np.allclose(Ainv, T, rtol=0, atol=1e-9 * max(1.0, np.abs(T).max()))
+
+
+@pytest.mark.parametrize("n", [1, 3, 50, 400])
+def test_laplacian_closed_form(orc, n):
+    A = synth.laplacian_1d(n)
+    L, info = orc.potrf(A)
+    assert info == 0
+    j = np.arange(1, n + 1, dtype=np.float64)
+    # the pivots follow a length-n recurrence, one rounding per step
+    assert np.allclose(np.diag(L), np.sqrt((j + 1) / j), rtol=4 * n * EPS, atol=0)
+    if n > 1:
+        jj = j[:-1]
+        assert np.allclose(np.diag(L, -1), -np.sqrt(jj / (jj + 1)), rtol=4 * n * EPS, atol=0)
+        assert np.count_nonzero(np.tril(L, -2)) == 0
+    assert orc.logdet(L) == pytest.approx(math.log(n + 1), rel=1e-12)
+    Ainv = orc.potrs(L, np.eye(n))
+    I, J = np.meshgrid(j, j, indexing="ij")
+    Tinv = np.minimum(I, J) * (n + 1 - np.maximum(I, J)) / (n + 1)
+    cond = (2 + 2 * np.cos(np.pi / (n + 1))) / (2 - 2 * np.cos(np.pi / (n + 1)))
+    assert np.allclose(Ainv, Tinv, rtol=0, atol=16 * cond * EPS * np.abs(Tinv).max())
+
+
+@pytest.mark.parametrize("n", [1, 10, 1000])
+def test_paper_benchmark_matrix(orc, n):
+    """A = diag(1..N), b = ones (paper, 'Performance and scaling')."""
+    A = synth.diag_1_to_n(n)
+    x, info = orc.posv(A, np.ones(n))
+    assert info == 0
+    assert np.allclose(x, 1.0 / np.arange(1, n + 1), rtol=4 * EPS, atol=0)
+    L, _ = orc.potrf(A)
+    assert orc.logdet(L) == pytest.approx(math.lgamma(n + 1), rel=1e-13)
+
+
+# --------------------------------------------------- library cross-checks
+@pytest.mark.parametrize("n,seed", [(17, 0), (256, 1), (700, 2)])
+def test_scipy_cross_check(orc, n, seed):
+    A = synth.gram_spd(n, seed)
+    L, info = orc.potrf(A)
+    assert info == 0
+    Ls = sla.cholesky(A, lower=True)
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(L - Ls) / np.linalg.norm(Ls) <= 10 * kappa * n * EPS
+    B = synth.normal((n, 4), seed + 1)
+    X = orc.potrs(L, B)
+    Xs = sla.cho_solve((Ls, True), B)
+    assert np.linalg.norm(X - Xs) / np.linalg.norm(Xs) <= 10 * kappa * n * EPS
+    # reconstruction
+    assert np.linalg.norm(A - L @ L.T) / np.linalg.norm(A) <= 4 * n * EPS
+
+
+def test_metamorphic_power_of_two_scaling(orc):
+    n = 150
+    A = synth.gram_spd(n, 5)
+    d = 2.0 ** synth.rng(6).integers(-6, 7, size=n)
+    L, _ = orc.potrf(A)
+    LD, _ = orc.potrf(d[:, None] * A * d[None, :])
+    assert np.array_equal(LD, d[:, None] * L)
+
+
+def test_only_lower_triangle_read_and_written(orc):
+    n = 40
+    A = synth.gram_spd(n, 7)
+    W = np.asfortranarray(A.copy())
+    W[np.triu_indices(n, 1)] = np.nan  # poison the strict upper triangle
+    lib = orc._load()
+    info = lib.or_potrf(n, W.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n)
+    assert info == 0
+    assert np.all(np.isnan(W[np.triu_indices(n, 1)]))
+    L, _ = orc.potrf(A)
+    assert np.array_equal(np.tril(W), L)
+    # lda > n: guard rows never touched
+    lda = n + 5
+    G = np.full((lda, n), -7.0, order="F")
+    G[:n, :] = A
+    info = lib.or_potrf(n, G.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), lda)
+    assert info == 0 and np.all(G[n:, :] == -7.0)
+    assert np.array_equal(np.tril(G[:n]), L)
+
+
+# --------------------------------------------------------- failure / edges
+@pytest.mark.parametrize("k", [1, 5, 64])
+def test_not_spd_info(orc, k):
+    n = 64
+    d = np.ones(n)
+    d[k - 1] = -1.0
+    _, info = orc.potrf(np.diag(d))
+    assert info == k
+
+
+def test_nan_info(orc):
+    n = 30
+    A = synth.gram_spd(n, 3)
+    A[9, 9] = np.nan
+    assert orc.potrf(A)[1] == 10
+    A = synth.gram_spd(n, 3)
+    A[20, 4] = A[4, 20] = np.nan     # poisons L[20,4]; pivot 21 is the first NaN pivot
+    assert orc.potrf(A)[1] == 21
+
+
+def test_edge_sizes(orc):
+    L, info = orc.potrf(np.zeros((0, 0)))
+    assert info == 0 and L.shape == (0, 0)
+    L, info = orc.potrf(np.array([[9.0]]))
+    assert info == 0 and L[0, 0] == 3.0
+    X = orc.potrs(np.array([[3.0]]), np.zeros((1, 0)))
+    assert X.shape == (1, 0)
+
+
+# ----------------------------------------------------------- residual / eta
+def test_residual_against_exact_rationals(orc):
+    n, nrhs = 6, 2
+    g = synth.rng(11)
+    A = synth.symmetrize_lower(g.standard_normal((n, n)))
+    X = g.standard_normal((n, nrhs))
+    B = g.standard_normal((n, nrhs))
+    R, eta, anorm = orc.residual(A, X, B)
+    Af = [[Fraction(A[i, j]) for j in range(n)] for i in range(n)]
+    for r in range(nrhs):
+        rex = [Fraction(B[i, r]) - sum(Af[i][j] * Fraction(X[j, r]) for j in range(n))
+               for i in range(n)]
+        for i in range(n):
+            assert R[i, r] == float(rex[i])     # correctly rounded within 1 rounding
+        an = max(sum(abs(Af[i][j]) for j in range(n)) for i in range(n))
+        assert anorm == float(an)
+        den = an * max(abs(Fraction(X[i, r])) for i in range(n)) + max(abs(Fraction(B[i, r])) for i in range(n))
+        assert eta[r] == pytest.approx(float(max(abs(v) for v in rex) / den), rel=1e-15)
+
+
+def test_eta_zero_for_exact_solution_and_scale_invariant(orc):
+    L0, A = synth.integer_exact(50, 9)
+    xt = synth.integer_vector((50, 2), 1)
+    B = A @ xt
+    _, eta, _ = orc.residual(A, xt, B)
+    assert np.all(eta == 0.0)
+    x = xt + 1e-3
+    _, e1, _ = orc.residual(A, x, B)
+    _, e2, _ = orc.residual(8.0 * A, x, 8.0 * B)
+    assert np.array_equal(e1, e2) and np.all(e1 > 0)
+
+
+def test_posv_backward_error_random(orc):
+    n = 500
+    A = synth.gram_spd_cond(n, 21, 1e4)
+    xt = synth.normal((n, 5), 22)
+    B = A @ xt
+    X, info = orc.posv(A, B)
+    assert info == 0
+    eta = orc.backward_error(A, X, B)
+    assert np.all(eta <= 1e-15)
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(X - xt) / np.linalg.norm(xt) <= kappa * 1e-13
+
+
+# ------------------------------------------------------------ generators
+def test_generators_shape_symmetry_cond():
+    A = synth.gram_spd_cond(512, 3, 1e4)
+    assert np.array_equal(A, A.T)
+    w = np.linalg.eigvalsh(A)
+    assert 0.9e4 <= w[-1] / w[0] <= 1.1e4
+    H = synth.haar_spd(256, 1e6, 4)
+    assert np.array_equal(H, H.T)
+    w = np.linalg.eigvalsh(H)
+    assert w[-1] / w[0] == pytest.approx(1e6, rel=1e-6)
+    assert np.array_equal(synth.gram_spd(64, 1), synth.gram_spd(64, 1))
+    s = synth.batch_sizes(4096, 0)
+    assert s.min() >= 16 and s.max() <= 512 and len(s) == 4096
+
+
+# ------------------------------------------------------ mixed precision IR
+@pytest.mark.parametrize("lo", [1, 2])
+def test_ir_integer_family_is_exact(orc, lo):
+    L0, A = synth.integer_exact(120, 3)
+    Lw, info = orc.potrf_lo(A, lo)
+    assert info == 0 and np.array_equal(Lw.astype(np.float64), L0)
+    xt = synth.integer_vector((120, 2), 4)
+    X, st = orc.posv_ir(A, A @ xt, lo=lo)
+    assert st["iters"] == 0 and not st["fell_back"]
+    assert np.array_equal(X, xt)
+
+
+@pytest.mark.parametrize("cond", [1e2, 1e4, 1e6])
+def test_ir_fp32_converges(orc, cond):
+    n = 256
+    A = synth.haar_spd(n, cond, 5)
+    xt = synth.normal((n, 3), 6)
+    B = A @ xt
+    X, st = orc.posv_ir(A, B, lo=1)
+    assert not st["fell_back"]
+    assert 1 <= st["iters"] <= 6
+    assert np.all(orc.backward_error(A, X, B) <= 1e-12)
+    # forward error <= ~2 kappa eta (Higham, Thm 7.2) with eta <= tol at exit
+    assert np.linalg.norm(X - xt) / np.linalg.norm(xt) <= 4 * cond * 1e-12
+
+
+def test_ir_bf16_low_cond_and_fallback(orc):
+    n = 128
+    A = synth.haar_spd(n, 1e2, 7)
+    xt = synth.normal((n, 2), 8)
+    B = A @ xt
+    X, st = orc.posv_ir(A, B, lo=2)
+    assert np.all(orc.backward_error(A, X, B) <= 1e-12)
+    # max_iter = 0 forces the FP64 fallback on an inexact first solve
+    X, st = orc.posv_ir(A, B, lo=1, max_iter=0)
+    assert st["fell_back"] and st["info"] == 0
+    assert np.all(orc.backward_error(A, X, B) <= 1e-12)
+    # an indefinite matrix fails in both precisions
+    D = np.diag(np.r_[np.ones(10), -1.0, np.ones(5)])
+    X, st = orc.posv_ir(D, np.ones(16), lo=1)
+    assert st["fell_back"] and st["info"] == 11
+
+
+# ----------------------------------------------------------------- adjoint
+def _loss_and_grad(orc, A, B, W):
+    X, info = orc.posv(A, B)
+    assert info == 0
+    L, _ = orc.potrf(A)
+    gB, gA = orc.posv_backward(L, X, W, mode=0)
+    return float(np.sum(W * X)), gB, gA
+
+
+def test_adjoint_central_differences(orc):
+    n, nrhs = 9, 3
+    A = synth.gram_spd(n, 13)
+    B = synth.normal((n, nrhs), 14)
+    W = synth.normal((n, nrhs), 15)
+    _, gB, gA = _loss_and_grad(orc, A, B, W)
+    h = 1e-6
+    for i in range(n):
+        for j in range(i + 1):
+            E = np.zeros((n, n))
+            E[i, j] = E[j, i] = 1.0
+            fp = np.sum(W * orc.posv(A + h * E, B)[0])
+            fm = np.sum(W * orc.posv(A - h * E, B)[0])
+            fd = (fp - fm) / (2 * h)
+            an = np.sum(gA * E)
+            assert an == pytest.approx(fd, rel=1e-6, abs=1e-8)
+    for i in range(n):
+        for r in range(nrhs):
+            E = np.zeros((n, nrhs))
+            E[i, r] = 1.0
+            fd = (np.sum(W * orc.posv(A, B + h * E)[0]) - np.sum(W * orc.posv(A, B - h * E)[0])) / (2 * h)
+            assert gB[i, r] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+def test_adjoint_special_cases(orc):
+    n, nrhs = 12, 2
+    B = synth.normal((n, nrhs), 1)
+    W = synth.normal((n, nrhs), 2)
+    _, gB, gA = _loss_and_grad(orc, np.eye(n), B, W)
+    assert np.array_equal(gB, W)
+    assert np.allclose(gA, -0.5 * (W @ B.T + B @ W.T), rtol=0, atol=1e-15)
+    d = 4.0 ** np.arange(n)  # perfect squares: L = diag(2^i) exactly
+    _, gB, _ = _loss_and_grad(orc, np.diag(d), B, W)
+    assert np.array_equal(gB, W / d[:, None])
+    # lower-parameter mode: off-diagonal entries are twice the symmetric ones
+    A = synth.gram_spd(n, 3)
+    X, _ = orc.posv(A, B)
+    L, _ = orc.potrf(A)
+    _, g0 = orc.posv_backward(L, X, W, mode=0)
+    _, g1 = orc.posv_backward(L, X, W, mode=1)
+    il = np.tril_indices(n, -1)
+    assert np.allclose(g1[il], 2 * g0[il], rtol=1e-15, atol=0)
+    assert np.allclose(np.diag(g1), np.diag(g0), rtol=1e-15, atol=1e-300)
+    assert np.all(g1[np.triu_indices(n, 1)] == 0)
+
+
+def test_planted_mistakes_are_caught():
+    """A plausible slip in a Cholesky routine (a transposed operand, a dropped
+    term, a sign) breaks at least one of the pins above.  Implemented on a
+    throw-away Python copy of the column algorithm, never the oracle itself."""
+    def chol(A, variant):
+        n = A.shape[0]
+        L = np.tril(A).astype(np.float64)
+        for j in range(n):
+            for k in range(j if variant != "drop_last" else max(j - 1, 0)):
+                if variant == "transpose":
+                    L[j:, j] -= L[j:, k] * L[k, j]
+                elif variant == "sign":
+                    L[j:, j] += L[j:, k] * L[j, k]
+                else:
+                    L[j:, j] -= L[j:, k] * L[j, k]
+            L[j:, j] /= np.sqrt(L[j, j]) if L[j, j] > 0 else np.nan
+        return L
+    L0, A = synth.integer_exact(20, 1)
+    assert np.array_equal(chol(A, "ok"), L0)
+    for v in ("transpose", "sign", "drop_last"):
+        with np.errstate(all="ignore"):
+            assert not np.array_equal(chol(A, v), L0)
