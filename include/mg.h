@@ -1,0 +1,155 @@
+/*
+ * mg.h -- C ABI of the MI355X (gfx950) dense SPD solver library (libmg.so).
+ *
+ * The operation is the one the paper (JAXMg, "Software design", the potrs
+ * bullet) exposes: solve A X = B for a symmetric positive-definite A through
+ * a Cholesky factorisation A = L L^T (potrf) followed by the two triangular
+ * solves (potrs), optionally returning log det A.  The paper's tile-size
+ * knob T_A ("Software design"; larger tiles help once N is large,
+ * "Performance and scaling") is the potrf block size (mg_set_block_size).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are column-major with a leading dimension: element (i, j) of A
+ *   is A[i + j*lda].  Only the LOWER triangle (diagonal included) of A is
+ *   read; potrf writes L over it and never reads or writes the strict upper
+ *   triangle.  Rows n..lda-1 of every column are never touched.
+ * - All matrix/vector pointers are DEVICE pointers owned by the caller.  The
+ *   library allocates no device memory on these paths; scratch space comes
+ *   from the caller through `work` arguments sized by *_buffer_size.
+ * - Work is enqueued on the handle's HIP stream (hipStream_t passed as
+ *   void*); calls return without synchronising unless stated otherwise.
+ * - Return value (host): MG_OK, a negative value -k when the k-th argument
+ *   (1-based, in C-signature order) is invalid -- checked before anything is
+ *   enqueued -- or a positive MG_ERR_* code for runtime failures.
+ * - `info` (device int32): 0 on success; k > 0 when the leading minor of
+ *   order k is not positive definite (pivot <= 0 or NaN).  Factorisation
+ *   stops there; columns >= k of the result are unspecified.  Kernels
+ *   enqueued after a failure see the non-zero info and do nothing.
+ */
+#ifndef MG_H_
+#define MG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mg_status;
+typedef struct mg_handle_s *mg_handle_t;
+
+#define MG_OK 0
+#define MG_ERR_HIP 1          /* a HIP runtime call or kernel launch failed */
+#define MG_ERR_UNSUPPORTED 2  /* dtype, precision or option not supported */
+#define MG_ERR_INTERNAL 3     /* inconsistent internal state */
+
+typedef enum { MG_F64 = 0, MG_F32 = 1 } mg_dtype;
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t mg_version(void);
+
+/* Create a handle bound to the current HIP device and to `stream`
+ * (a hipStream_t; NULL = the default stream).  *handle receives the handle.
+ * Errors: -1 if handle is NULL; MG_ERR_HIP if the device query fails. */
+mg_status mg_create(mg_handle_t *handle, void *stream);
+/* Destroy a handle (NULL is accepted).  Releases profiling events only. */
+mg_status mg_destroy(mg_handle_t handle);
+/* Rebind the handle to another stream.  Errors: -1 if handle is NULL. */
+mg_status mg_set_stream(mg_handle_t handle, void *stream);
+
+/* potrf block size nb (the paper's tile size T_A).  0 selects the built-in
+ * default for the problem size; otherwise nb must be one of 64, 128, 256.
+ * Errors: -1 NULL handle, -2 unsupported nb. */
+mg_status mg_set_block_size(mg_handle_t handle, int64_t nb);
+/* Block size potrf would use for (dtype, n).  Errors: -1, -2, -3 (n < 0), -4 NULL. */
+mg_status mg_get_block_size(mg_handle_t handle, mg_dtype dtype, int64_t n, int64_t *nb);
+
+/*
+ * potrf: Cholesky factorisation A = L L^T in place (paper: "Software design",
+ * potrs bullet; LAPACK xPOTRF semantics, lower).
+ *   dtype  MG_F64 or MG_F32 (storage and arithmetic type).
+ *   n      order, n >= 0 (n = 0: info is set to 0 and nothing else happens).
+ *   A      device, lda x n column-major; lower triangle in, L out.
+ *   lda    >= max(1, n).
+ *   info   device int32, written (0 or k > 0).
+ * Errors: -1 NULL handle, -2 bad dtype, -3 n < 0, -4 A NULL with n > 0,
+ *         -5 lda < max(1,n), -6 info NULL.
+ */
+mg_status mg_potrf(mg_handle_t handle, mg_dtype dtype, int64_t n, void *A, int64_t lda,
+                   int32_t *info);
+
+/* Bytes of device workspace mg_potrs / mg_posv need for (dtype, n, nrhs).
+ * Errors: -1 NULL handle, -2 bad dtype, -3 n < 0, -4 nrhs < 0, -5 NULL out. */
+mg_status mg_potrs_buffer_size(mg_handle_t handle, mg_dtype dtype, int64_t n, int64_t nrhs,
+                               size_t *bytes);
+
+/*
+ * potrs: X = A^{-1} B from the factor L of mg_potrf: forward substitution
+ * L Y = B, then back substitution L^T X = Y (paper: "Software design",
+ * potrs bullet; b is N x N_RHS).
+ *   L      device, lda x n, the factor in its lower triangle (strict upper
+ *          never read).
+ *   B      device, ldb x nrhs, overwritten with X.
+ *   work   device scratch of mg_potrs_buffer_size bytes (may be NULL when
+ *          that size is 0).
+ *   info   optional device int32 from a preceding mg_potrf (NULL = absent);
+ *          when it holds a non-zero value B is left unmodified.
+ * Errors: -1 NULL handle, -2 dtype, -3 n < 0, -4 nrhs < 0, -5 L NULL,
+ *         -6 lda, -7 B NULL, -8 ldb < max(1,n), -9 work NULL, -10 work too small.
+ */
+mg_status mg_potrs(mg_handle_t handle, mg_dtype dtype, int64_t n, int64_t nrhs, const void *L,
+                   int64_t lda, void *B, int64_t ldb, void *work, size_t work_bytes,
+                   const int32_t *info);
+
+/*
+ * posv: factor then solve (potrf + potrs) with no host synchronisation.
+ * A is overwritten by L; B by X unless info > 0, in which case B is left
+ * unmodified.  Workspace: mg_potrs_buffer_size bytes.
+ * Errors: -1 handle, -2 dtype, -3 n, -4 nrhs, -5 A, -6 lda, -7 B, -8 ldb,
+ *         -9 work NULL, -10 work too small, -11 info NULL.
+ */
+mg_status mg_posv(mg_handle_t handle, mg_dtype dtype, int64_t n, int64_t nrhs, void *A,
+                  int64_t lda, void *B, int64_t ldb, void *work, size_t work_bytes,
+                  int32_t *info);
+
+/*
+ * logdet: log det A = 2 sum_j log L_jj from the factor (paper: "Software
+ * design", potrs bullet: the factorisation can optionally return log det A;
+ * used by the Gaussian-process likelihood in "Scientific applications").
+ *   out    device double, receives the value (NaN when info != 0).
+ *   info   optional device int32 from mg_potrf (NULL = absent).
+ * Errors: -1 handle, -2 dtype, -3 n < 0, -4 L NULL, -5 lda, -6 out NULL.
+ */
+mg_status mg_logdet(mg_handle_t handle, mg_dtype dtype, int64_t n, const void *L, int64_t lda,
+                    double *out, const int32_t *info);
+
+/*
+ * Profiling.  When enabled, every launch of the kernel kinds below is
+ * bracketed by a pair of HIP events on the handle's stream, and the
+ * algorithmic work of each launch is accumulated.
+ *   MG_PROF_TRAILING  -- trailing update lower(C) -= P P^T; flops = k m (m+1)
+ *   MG_PROF_DIAG      -- diagonal-block factor; flops = b^3/3 + b^2/2 + b/6
+ *   MG_PROF_TRSM      -- panel triangular solve; flops = m b^2
+ *   MG_PROF_SOLVE     -- potrs steps; flops = 2 n^2 nrhs in total
+ * mg_profile_query synchronises on the last recorded event, returns the
+ * summed event time (ms), the number of launches and the summed flops and
+ * algorithmic bytes, and resets the counter when reset != 0.
+ */
+#define MG_PROF_TRAILING 0
+#define MG_PROF_DIAG 1
+#define MG_PROF_TRSM 2
+#define MG_PROF_SOLVE 3
+#define MG_PROF_KINDS 4
+/* Errors: -1 NULL handle. */
+mg_status mg_set_profiling(mg_handle_t handle, int32_t enable);
+/* Errors: -1 NULL handle, -2 bad kind, -3..-6 NULL outputs. */
+mg_status mg_profile_query(mg_handle_t handle, int32_t kind, double *total_ms, int64_t *launches,
+                           double *flops, double *bytes, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MG_H_ */

@@ -1,0 +1,89 @@
+"""ctypes view of libmg.so: one Python callable per C entry point, same names.
+
+Argument marshalling only; every step of the computation runs in the HIP
+kernels of libmg.so.  Loading fails loudly when the library is missing: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmg.so")
+
+MG_OK = 0
+MG_ERR_HIP = 1
+MG_ERR_UNSUPPORTED = 2
+MG_ERR_INTERNAL = 3
+MG_F64 = 0
+MG_F32 = 1
+MG_PROF_TRAILING = 0
+MG_PROF_DIAG = 1
+MG_PROF_TRSM = 2
+MG_PROF_SOLVE = 3
+
+i32 = ctypes.c_int32
+i64 = ctypes.c_int64
+vp = ctypes.c_void_p
+sz = ctypes.c_size_t
+dbl = ctypes.c_double
+
+# name -> (restype, argtypes); the order follows include/mg.h
+SIGNATURES = {
+    "mg_version": (i32, []),
+    "mg_create": (i32, [ctypes.POINTER(vp), vp]),
+    "mg_destroy": (i32, [vp]),
+    "mg_set_stream": (i32, [vp, vp]),
+    "mg_set_block_size": (i32, [vp, i64]),
+    "mg_get_block_size": (i32, [vp, i32, i64, ctypes.POINTER(i64)]),
+    "mg_potrf": (i32, [vp, i32, i64, vp, i64, vp]),
+    "mg_potrs_buffer_size": (i32, [vp, i32, i64, i64, ctypes.POINTER(sz)]),
+    "mg_potrs": (i32, [vp, i32, i64, i64, vp, i64, vp, i64, vp, sz, vp]),
+    "mg_posv": (i32, [vp, i32, i64, i64, vp, i64, vp, i64, vp, sz, vp]),
+    "mg_logdet": (i32, [vp, i32, i64, vp, i64, vp, vp]),
+    "mg_set_profiling": (i32, [vp, i32]),
+    "mg_profile_query": (i32, [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl),
+                               ctypes.POINTER(dbl), i32]),
+}
+
+_lib = None
+
+
+class MgError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        kind = ("invalid argument %d" % -code) if code < 0 else {
+            MG_ERR_HIP: "HIP runtime error", MG_ERR_UNSUPPORTED: "unsupported",
+            MG_ERR_INTERNAL: "internal error"}.get(code, "error %d" % code)
+        super().__init__(f"{fn}: {kind} (status {code})")
+        self.code = code
+
+
+def load():
+    """Load libmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2601_14466_amd.build.build() "
+                          "(hipcc, gfx950); there is no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def call(name: str, *args) -> int:
+    """Call an entry point; raise MgError on a non-zero status."""
+    rc = getattr(load(), name)(*args)
+    if rc != MG_OK:
+        raise MgError(name, rc)
+    return rc
+
+
+def raw(name: str, *args) -> int:
+    """Call an entry point and return its status unchanged."""
+    return getattr(load(), name)(*args)

@@ -1,0 +1,221 @@
+// api.hip -- C ABI entry points: argument validation, handle, profiling,
+// posv and logdet.  Every check runs on the host before anything is enqueued.
+#include <algorithm>
+#include <cmath>
+
+#include "mg_internal.h"
+#include "tile16.h"
+
+using namespace mg;
+
+namespace mg {
+
+mg_status prof_begin(mg_handle_t h, int kind) {
+    if (!h->profiling) return MG_OK;
+    mg_prof_counter& pc = h->prof[kind];
+    if (pc.used == pc.start.size()) {
+        hipEvent_t a, b;
+        MG_HIP(hipEventCreate(&a));
+        MG_HIP(hipEventCreate(&b));
+        pc.start.push_back(a);
+        pc.stop.push_back(b);
+    }
+    MG_HIP(hipEventRecord(pc.start[pc.used], h->stream));
+    return MG_OK;
+}
+
+mg_status prof_end(mg_handle_t h, int kind, double flops, double bytes) {
+    if (!h->profiling) return MG_OK;
+    mg_prof_counter& pc = h->prof[kind];
+    MG_HIP(hipEventRecord(pc.stop[pc.used], h->stream));
+    ++pc.used;
+    pc.flops += flops;
+    pc.bytes += bytes;
+    return MG_OK;
+}
+
+// log det = 2 sum_j log L_jj, one workgroup, fixed-order tree reduction.
+template <typename T>
+__global__ __launch_bounds__(256) void k_logdet(const T* L, int64_t lda, int64_t n, double* out,
+                                                const int32_t* info) {
+    __shared__ double part[256];
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) s += log((double)L[idx(j, j, lda)]);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) part[threadIdx.x] += part[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = (info && *info != 0) ? (double)NAN : 2.0 * part[0];
+}
+
+}  // namespace mg
+
+static inline int es_of(mg_dtype dt) { return dt == MG_F64 ? 8 : 4; }
+static inline bool dtype_ok(mg_dtype dt) { return dt == MG_F64 || dt == MG_F32; }
+
+extern "C" {
+
+int32_t mg_version(void) { return 10000; }
+
+mg_status mg_create(mg_handle_t* handle, void* stream) {
+    if (!handle) return -1;
+    *handle = nullptr;
+    mg_handle_s* h = new mg_handle_s();
+    h->stream = (hipStream_t)stream;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return MG_ERR_HIP;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && cus > 0)
+        h->cu_count = cus;
+    *handle = h;
+    return MG_OK;
+}
+
+mg_status mg_destroy(mg_handle_t h) {
+    if (!h) return MG_OK;
+    for (int k = 0; k < MG_PROF_KINDS; ++k) {
+        for (hipEvent_t e : h->prof[k].start) (void)hipEventDestroy(e);
+        for (hipEvent_t e : h->prof[k].stop) (void)hipEventDestroy(e);
+    }
+    delete h;
+    return MG_OK;
+}
+
+mg_status mg_set_stream(mg_handle_t h, void* stream) {
+    if (!h) return -1;
+    h->stream = (hipStream_t)stream;
+    return MG_OK;
+}
+
+mg_status mg_set_block_size(mg_handle_t h, int64_t nb) {
+    if (!h) return -1;
+    if (!(nb == 0 || nb == 64 || nb == 128 || nb == 256)) return -2;
+    h->nb = nb;
+    return MG_OK;
+}
+
+mg_status mg_get_block_size(mg_handle_t h, mg_dtype dt, int64_t n, int64_t* nb) {
+    if (!h) return -1;
+    if (!dtype_ok(dt)) return -2;
+    if (n < 0) return -3;
+    if (!nb) return -4;
+    *nb = potrf_block_size(h, n, es_of(dt));
+    return MG_OK;
+}
+
+mg_status mg_potrf(mg_handle_t h, mg_dtype dt, int64_t n, void* A, int64_t lda, int32_t* info) {
+    if (!h) return -1;
+    if (!dtype_ok(dt)) return -2;
+    if (n < 0) return -3;
+    if (!A && n > 0) return -4;
+    if (lda < std::max<int64_t>(1, n)) return -5;
+    if (!info) return -6;
+    return dt == MG_F64 ? potrf_impl<double>(h, n, (double*)A, lda, info)
+                        : potrf_impl<float>(h, n, (float*)A, lda, info);
+}
+
+mg_status mg_potrs_buffer_size(mg_handle_t h, mg_dtype dt, int64_t n, int64_t nrhs, size_t* bytes) {
+    if (!h) return -1;
+    if (!dtype_ok(dt)) return -2;
+    if (n < 0) return -3;
+    if (nrhs < 0) return -4;
+    if (!bytes) return -5;
+    *bytes = potrs_work_bytes(n, nrhs, es_of(dt));
+    return MG_OK;
+}
+
+static mg_status check_solve_args(mg_handle_t h, mg_dtype dt, int64_t n, int64_t nrhs, const void* A,
+                                  int64_t lda, const void* B, int64_t ldb, const void* work, size_t work_bytes) {
+    if (!h) return -1;
+    if (!dtype_ok(dt)) return -2;
+    if (n < 0) return -3;
+    if (nrhs < 0) return -4;
+    if (!A && n > 0) return -5;
+    if (lda < std::max<int64_t>(1, n)) return -6;
+    if (!B && n > 0 && nrhs > 0) return -7;
+    if (ldb < std::max<int64_t>(1, n)) return -8;
+    const size_t need = potrs_work_bytes(n, nrhs, es_of(dt));
+    if (need > 0 && !work) return -9;
+    if (work_bytes < need) return -10;
+    return MG_OK;
+}
+
+mg_status mg_potrs(mg_handle_t h, mg_dtype dt, int64_t n, int64_t nrhs, const void* L, int64_t lda, void* B,
+                   int64_t ldb, void* work, size_t work_bytes, const int32_t* info) {
+    mg_status rc = check_solve_args(h, dt, n, nrhs, L, lda, B, ldb, work, work_bytes);
+    if (rc) return rc;
+    return dt == MG_F64
+               ? potrs_impl<double>(h, n, nrhs, (const double*)L, lda, (double*)B, ldb, (double*)work, info)
+               : potrs_impl<float>(h, n, nrhs, (const float*)L, lda, (float*)B, ldb, (float*)work, info);
+}
+
+mg_status mg_posv(mg_handle_t h, mg_dtype dt, int64_t n, int64_t nrhs, void* A, int64_t lda, void* B,
+                  int64_t ldb, void* work, size_t work_bytes, int32_t* info) {
+    mg_status rc = check_solve_args(h, dt, n, nrhs, A, lda, B, ldb, work, work_bytes);
+    if (rc) return rc;
+    if (!info) return -11;
+    if (dt == MG_F64) {
+        if ((rc = potrf_impl<double>(h, n, (double*)A, lda, info))) return rc;
+        return potrs_impl<double>(h, n, nrhs, (const double*)A, lda, (double*)B, ldb, (double*)work, info);
+    }
+    if ((rc = potrf_impl<float>(h, n, (float*)A, lda, info))) return rc;
+    return potrs_impl<float>(h, n, nrhs, (const float*)A, lda, (float*)B, ldb, (float*)work, info);
+}
+
+mg_status mg_logdet(mg_handle_t h, mg_dtype dt, int64_t n, const void* L, int64_t lda, double* out,
+                    const int32_t* info) {
+    if (!h) return -1;
+    if (!dtype_ok(dt)) return -2;
+    if (n < 0) return -3;
+    if (!L && n > 0) return -4;
+    if (lda < std::max<int64_t>(1, n)) return -5;
+    if (!out) return -6;
+    if (dt == MG_F64)
+        hipLaunchKernelGGL((k_logdet<double>), dim3(1), dim3(256), 0, h->stream, (const double*)L, lda, n, out, info);
+    else
+        hipLaunchKernelGGL((k_logdet<float>), dim3(1), dim3(256), 0, h->stream, (const float*)L, lda, n, out, info);
+    MG_LAUNCH_CHECK();
+    return MG_OK;
+}
+
+mg_status mg_set_profiling(mg_handle_t h, int32_t enable) {
+    if (!h) return -1;
+    h->profiling = enable ? 1 : 0;
+    return MG_OK;
+}
+
+mg_status mg_profile_query(mg_handle_t h, int32_t kind, double* total_ms, int64_t* launches, double* flops,
+                           double* bytes, int32_t reset) {
+    if (!h) return -1;
+    if (kind < 0 || kind >= MG_PROF_KINDS) return -2;
+    if (!total_ms) return -3;
+    if (!launches) return -4;
+    if (!flops) return -5;
+    if (!bytes) return -6;
+    mg_prof_counter& pc = h->prof[kind];
+    double ms = 0.0;
+    if (pc.used > 0) {
+        MG_HIP(hipEventSynchronize(pc.stop[pc.used - 1]));
+        for (size_t k = 0; k < pc.used; ++k) {
+            float t = 0.f;
+            MG_HIP(hipEventElapsedTime(&t, pc.start[k], pc.stop[k]));
+            ms += (double)t;
+        }
+    }
+    *total_ms = ms;
+    *launches = (int64_t)pc.used;
+    *flops = pc.flops;
+    *bytes = pc.bytes;
+    if (reset) {
+        pc.used = 0;
+        pc.flops = 0.0;
+        pc.bytes = 0.0;
+    }
+    return MG_OK;
+}
+
+}  // extern "C"

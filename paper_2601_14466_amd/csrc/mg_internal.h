@@ -1,0 +1,56 @@
+// mg_internal.h -- host-side internals shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <vector>
+
+#include "mg.h"
+
+struct mg_prof_counter {
+    std::vector<hipEvent_t> start, stop;
+    size_t used = 0;
+    double flops = 0.0;
+    double bytes = 0.0;
+};
+
+struct mg_handle_s {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int cu_count = 256;
+    int64_t nb = 0;          // potrf block size (the paper's tile size T_A); 0 = default
+    int profiling = 0;
+    mg_prof_counter prof[MG_PROF_KINDS];
+};
+
+namespace mg {
+
+#define MG_HIP(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return MG_ERR_HIP;       \
+    } while (0)
+
+#define MG_LAUNCH_CHECK() MG_HIP(hipGetLastError())
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Profiling: bracket one launch with an event pair when enabled.
+mg_status prof_begin(mg_handle_t h, int kind);
+mg_status prof_end(mg_handle_t h, int kind, double flops, double bytes);
+
+// Block size used by potrf for order n and element size es.
+int64_t potrf_block_size(mg_handle_t h, int64_t n, int es);
+
+// Drivers (enqueue on h->stream, no host synchronisation).
+template <typename T>
+mg_status potrf_impl(mg_handle_t h, int64_t n, T* A, int64_t lda, int32_t* info);
+template <typename T>
+mg_status potrs_impl(mg_handle_t h, int64_t n, int64_t nrhs, const T* L, int64_t lda, T* B,
+                     int64_t ldb, T* ywork, const int32_t* info);
+size_t potrs_work_bytes(int64_t n, int64_t nrhs, int es);
+
+mg_status set_info_zero(hipStream_t s, int32_t* info);
+
+}  // namespace mg

@@ -1,0 +1,172 @@
+// tile16.h -- wave-level building blocks on 16x16 tiles for gfx950 (CDNA4).
+//
+// A 16x16 tile Y is held by one 64-lane wave in "row-per-lane" layout:
+//   lane l = 16*g + i (i = l % 16, g = l / 16) holds, in register r = 0..3,
+//   Y[i][tcol<C>(g, r)].
+// Row i lives in the 4 lanes {i, 16+i, 32+i, 48+i}; a register r of the four
+// lane groups covers four columns.  Loading or storing a tile of a
+// column-major matrix in this layout is coalesced: each register moves four
+// 128-byte column segments (16 consecutive rows each).
+//
+// The layout is the transpose of the MFMA 16x16x4 result.  The instruction
+// computes D[row][col] += sum_k A[row][k] B[k][col] with lane l supplying
+// A[l%16][l/16] and B[l/16][l%16].  Lane l receives D[row][l%16] in register
+// r, where measured on gfx950
+//   f32 (v_mfma_f32_16x16x4_f32): row = 4*(l/16) + r
+//   f64 (v_mfma_f64_16x16x4_f64): row = 4*r + l/16
+// so tcol is 4g + r for float and 4r + g for double.  Reading D as Y^T gives
+//   Y += X Z^T   with lane l supplying x = X[l%16][k_l], z = Z[l%16][k_l]
+// where k_l is any bijection between (lane group, step) and the k range that
+// both operands share.  Everything below uses that form.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mg {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Vec4;
+template <> struct Vec4<double> { typedef f64x4 type; };
+template <> struct Vec4<float> { typedef f32x4 type; };
+template <typename T> using V4 = typename Vec4<T>::type;
+
+// Column held by register r of lane group g, and its inverse.
+template <typename C> __host__ __device__ constexpr int tcol(int g, int r);
+template <> __host__ __device__ constexpr int tcol<float>(int g, int r) { return 4 * g + r; }
+template <> __host__ __device__ constexpr int tcol<double>(int g, int r) { return 4 * r + g; }
+template <typename C> __host__ __device__ constexpr int tgrp(int c);   // lane group owning column c
+template <typename C> __host__ __device__ constexpr int treg(int c);   // register holding column c
+template <> __host__ __device__ constexpr int tgrp<float>(int c) { return c >> 2; }
+template <> __host__ __device__ constexpr int treg<float>(int c) { return c & 3; }
+template <> __host__ __device__ constexpr int tgrp<double>(int c) { return c & 3; }
+template <> __host__ __device__ constexpr int treg<double>(int c) { return c >> 2; }
+
+// Y (tile layout, accumulator) += X Z^T over one k-step: lane supplies
+// x = X[i][k_l] and z = Z[i][k_l].
+__device__ __forceinline__ f64x4 mma_xzt(f64x4 acc, double x, double z) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(z, x, acc, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mma_xzt(f32x4 acc, float x, float z) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(z, x, acc, 0, 0, 0);
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ double shfl(double v, int src) { return __shfl(v, src, 64); }
+__device__ __forceinline__ float shfl(float v, int src) { return __shfl(v, src, 64); }
+
+// Broadcast lane `src` (wave-uniform) through the scalar unit.
+__device__ __forceinline__ float readlane(float v, int src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+__device__ __forceinline__ double readlane(double v, int src) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+__host__ __device__ __forceinline__ size_t idx(int64_t i, int64_t j, int64_t ld) {
+    return (size_t)i + (size_t)j * (size_t)ld;
+}
+
+// Load the 16x16 tile at (r0, c0) of column-major M into tile layout.
+// Rows >= rmax or columns >= cmax read as 0, except that on the diagonal of a
+// diagonal tile (diag_pad) they read as 1, so padding behaves like identity.
+// With lower_only, entries strictly above the tile diagonal are not read (0).
+template <typename S, typename C>
+__device__ __forceinline__ void load_tile(V4<C>& y, const S* M, int64_t ld, int64_t r0, int64_t c0,
+                                          int64_t rmax, int64_t cmax, bool lower_only, bool diag_pad) {
+    const int l = lane_id(), i = l & 15, g = l >> 4;
+    const int64_t row = r0 + i;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int jj = tcol<C>(g, r);
+        const int64_t col = c0 + jj;
+        C v = 0;
+        if (row < rmax && col < cmax && (!lower_only || i >= jj))
+            v = (C)M[idx(row, col, ld)];
+        else if (diag_pad && i == jj)
+            v = 1;
+        y[r] = v;
+    }
+}
+
+// Store a tile; rows >= rmax / columns >= cmax are skipped; with lower_only
+// only entries on or below the tile diagonal are written.
+template <typename S, typename C>
+__device__ __forceinline__ void store_tile(const V4<C>& y, S* M, int64_t ld, int64_t r0, int64_t c0,
+                                           int64_t rmax, int64_t cmax, bool lower_only) {
+    const int l = lane_id(), i = l & 15, g = l >> 4;
+    const int64_t row = r0 + i;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int jj = tcol<C>(g, r);
+        const int64_t col = c0 + jj;
+        if (row < rmax && col < cmax && (!lower_only || i >= jj))
+            M[idx(row, col, ld)] = (S)y[r];
+    }
+}
+
+// In-register Cholesky of a 16x16 SPD tile (lower part significant).  Column
+// by column: the pivot is broadcast by a lane shuffle, column c is divided by
+// its square root, and the columns to its right receive the rank-1 update.
+// Returns 0, or c+1 for the first local column whose pivot is not > 0 (NaN
+// included); the decision is uniform across the wave.  Entries above the
+// diagonal are left unspecified.
+template <typename C>
+__device__ __forceinline__ int factor16(V4<C>& y) {
+    const int l = lane_id(), i = l & 15, g = l >> 4;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const int gc = tgrp<C>(c), rc = treg<C>(c);
+        const C p = shfl(y[rc], gc * 16 + c);
+        if (!(p > (C)0)) return c + 1;
+        const C s = sqrt(p);
+        const C v = shfl(y[rc], gc * 16 + i);   // Y[i][c]
+        const C lic = (i > c) ? v / s : (i == c ? s : (C)0);
+        if (g == gc) y[rc] = lic;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = tcol<C>(g, r);
+            const C ljc = shfl(lic, j);         // L[j][c] sits in lane j (group 0)
+            if (j > c) y[r] = y[r] - lic * ljc;
+        }
+    }
+    return 0;
+}
+
+// X = Y L^{-T} for a 16x16 lower-triangular L held in LDS as Ls[row*LDL+col]:
+// forward substitution over the columns of Y, each solved column broadcast
+// along its row by a lane shuffle.
+template <typename C, int LDL>
+__device__ __forceinline__ void solve16(V4<C>& y, const C* Ls) {
+    const int l = lane_id(), i = l & 15, g = l >> 4;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const int gc = tgrp<C>(c), rc = treg<C>(c);
+        if (g == gc) y[rc] = y[rc] / Ls[c * LDL + c];
+        const C xc = shfl(y[rc], gc * 16 + i);  // X[i][c]
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = tcol<C>(g, r);
+            if (j > c) y[r] = y[r] - xc * Ls[j * LDL + c];
+        }
+    }
+}
+
+// Write a factored diagonal tile (tile layout) into LDS as Ls[row*LDL+col],
+// zeroing the strict upper part.
+template <typename C, int LDL>
+__device__ __forceinline__ void tile_to_lds_lower(const V4<C>& y, C* Ls) {
+    const int l = lane_id(), i = l & 15, g = l >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int j = tcol<C>(g, r);
+        Ls[i * LDL + j] = (i >= j) ? y[r] : (C)0;
+    }
+}
+
+}  // namespace mg
