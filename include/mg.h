@@ -63,6 +63,15 @@ mg_status mg_set_stream(mg_handle_t handle, void *stream);
  * default for the problem size; otherwise nb must be one of 64, 128, 256.
  * Errors: -1 NULL handle, -2 unsupported nb. */
 mg_status mg_set_block_size(mg_handle_t handle, int64_t nb);
+/* Look-ahead schedule for potrf (default on): the trailing update of step k
+ * is split into the next block column, updated first on the handle's stream
+ * so that the next diagonal block and panel can be factored right away, and
+ * the remainder, run on a second stream owned by the handle; events order
+ * the two, and the handle's stream waits for the second one before potrf
+ * returns its work.  0 runs every step in sequence on one stream.
+ * Errors: -1 NULL handle. */
+mg_status mg_set_lookahead(mg_handle_t handle, int32_t enable);
+
 /* Block size potrf would use for (dtype, n).  Errors: -1, -2, -3 (n < 0), -4 NULL. */
 mg_status mg_get_block_size(mg_handle_t handle, mg_dtype dtype, int64_t n, int64_t *nb);
 
@@ -115,6 +124,84 @@ mg_status mg_posv(mg_handle_t handle, mg_dtype dtype, int64_t n, int64_t nrhs, v
                   int32_t *info);
 
 /*
+ * Mixed precision with iterative refinement.  The paper is silent on
+ * precision; this is the classic scheme for SPD systems (Langou et al.,
+ * SC'06; Carson & Higham 2018): factor a binary32 copy of A (diagonal blocks
+ * in FP64 arithmetic, trailing updates on the FP32 matrix pipe, or with
+ * MG_PREC_BF16 with trailing-update operands rounded to bfloat16), solve, then
+ * refine: r = b - A x in FP64 with the original A, d = solve_lo(r),
+ * x += d, until every column's normwise backward error
+ * eta_j = |r_j|inf / (|A|inf |x_j|inf + |b_j|inf) <= tol.  It stops after
+ * max_iter corrections or when the largest eta fails to halve twice in a
+ * row; then, or when the low-precision factor breaks down, it solves in FP64
+ * (fallback != 0) and reports fell_back = 1.
+ */
+typedef enum { MG_PREC_F32 = 1, MG_PREC_BF16 = 2 } mg_prec;
+typedef struct {
+    double tol;        /* backward-error target, default 1e-12 */
+    int32_t max_iter;  /* refinement steps, default 30 */
+    int32_t fallback;  /* 1: solve in FP64 when refinement does not converge (default) */
+} mg_ir_opts;
+typedef struct {
+    int32_t iters;     /* corrections applied */
+    int32_t fell_back; /* 1 when the FP64 fallback produced X */
+    int32_t lo_info;   /* info of the low-precision factor (0, or the failing column) */
+    int32_t reserved;
+    double eta;        /* largest per-column backward error of the returned X (FP64 residual) */
+} mg_ir_result;
+
+/* Workspace bytes for mg_posv_mixed.  Errors: -1 handle, -2 lo, -3 n < 0,
+ * -4 nrhs < 0, -5 NULL out.  The FP64 fallback needs an n x n FP64 copy of
+ * A, so the size depends on `fallback`. */
+mg_status mg_posv_mixed_buffer_size(mg_handle_t handle, mg_prec lo, int64_t n, int64_t nrhs, int32_t fallback,
+                                    size_t *bytes);
+/*
+ * X = A^{-1} B with a low-precision factor and FP64 refinement.
+ *   A      device, FP64, lda x n, lower triangle; NOT modified (the residual
+ *          needs it).  B device FP64 ldb x nrhs, not modified.
+ *   X      device FP64 ldx x nrhs, receives the solution.
+ *   opts   host pointer, NULL for the defaults.
+ *   work   device scratch of mg_posv_mixed_buffer_size bytes (it holds the
+ *          low-precision factor).
+ *   result host pointer, filled on return.
+ *   info   device int32: 0, or k > 0 when the FP64 fallback finds A itself
+ *          not positive definite.
+ * The call synchronises the handle's stream once per refinement step (the
+ * stopping test reads eta on the host) and returns after the solve.
+ * Errors: -1 handle, -2 lo, -3 n, -4 nrhs, -5 A, -6 lda, -7 B, -8 ldb, -9 X,
+ *         -10 ldx, -11 opts (tol < 0 or max_iter < 0), -12 work NULL,
+ *         -13 work too small, -14 result NULL, -15 info NULL.
+ */
+mg_status mg_posv_mixed(mg_handle_t handle, mg_prec lo, int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                        const double *B, int64_t ldb, double *X, int64_t ldx, const mg_ir_opts *opts, void *work,
+                        size_t work_bytes, mg_ir_result *result, int32_t *info);
+
+/*
+ * Adjoint of X = A^{-1} B (reverse mode).  The paper puts these solves inside
+ * differentiable programs ("Statement of need") without stating the adjoint;
+ * from dX = A^{-1}(dB - dA X):
+ *   gB = A^{-1} gX, from the stored factor L (no refactorisation);
+ *   MG_GRAD_SYM   : gA = -1/2 (gB X^T + X gB^T), full n x n symmetric;
+ *   MG_GRAD_LOWER : gradient with respect to the lower triangle the solver
+ *                   reads: gA(i,j) = -(gB X^T + X gB^T)(i,j) for i > j,
+ *                   gA(i,i) = -(gB X^T)(i,i); the strict upper triangle of
+ *                   gA is not written.
+ * FP64 only.  L: lda x n factor from mg_potrf; X: ldx x nrhs forward
+ * solution; gX: ldgx x nrhs upstream gradient (read only); gB: ldgb x nrhs
+ * output; gA: ldga x n output.  work: mg_potrs_buffer_size(MG_F64, n, nrhs)
+ * bytes.  info: optional device int32 of the factorisation; when non-zero
+ * nothing is written.
+ * Errors: -1 handle, -2 n, -3 nrhs, -4 L, -5 lda, -6 X, -7 ldx, -8 gX, -9 ldgx,
+ *         -10 gB, -11 ldgb, -12 gA, -13 ldga, -14 mode, -15 work NULL,
+ *         -16 work too small.
+ */
+typedef enum { MG_GRAD_SYM = 0, MG_GRAD_LOWER = 1 } mg_grad_mode;
+mg_status mg_posv_backward(mg_handle_t handle, int64_t n, int64_t nrhs, const double *L, int64_t lda,
+                           const double *X, int64_t ldx, const double *gX, int64_t ldgx, double *gB, int64_t ldgb,
+                           double *gA, int64_t ldga, mg_grad_mode mode, void *work, size_t work_bytes,
+                           const int32_t *info);
+
+/*
  * logdet: log det A = 2 sum_j log L_jj from the factor (paper: "Software
  * design", potrs bullet: the factorisation can optionally return log det A;
  * used by the Gaussian-process likelihood in "Scientific applications").
@@ -133,6 +220,7 @@ mg_status mg_logdet(mg_handle_t handle, mg_dtype dtype, int64_t n, const void *L
  *   MG_PROF_DIAG      -- diagonal-block factor; flops = b^3/3 + b^2/2 + b/6
  *   MG_PROF_TRSM      -- panel triangular solve; flops = m b^2
  *   MG_PROF_SOLVE     -- potrs steps; flops = 2 n^2 nrhs in total
+ *   MG_PROF_ADJOINT   -- gradient product of mg_posv_backward; flops = 4 n^2 nrhs
  * mg_profile_query synchronises on the last recorded event, returns the
  * summed event time (ms), the number of launches and the summed flops and
  * algorithmic bytes, and resets the counter when reset != 0.
@@ -141,7 +229,8 @@ mg_status mg_logdet(mg_handle_t handle, mg_dtype dtype, int64_t n, const void *L
 #define MG_PROF_DIAG 1
 #define MG_PROF_TRSM 2
 #define MG_PROF_SOLVE 3
-#define MG_PROF_KINDS 4
+#define MG_PROF_ADJOINT 4
+#define MG_PROF_KINDS 5
 /* Errors: -1 NULL handle. */
 mg_status mg_set_profiling(mg_handle_t handle, int32_t enable);
 /* Errors: -1 NULL handle, -2 bad kind, -3..-6 NULL outputs. */

@@ -19,7 +19,8 @@ from . import _lib
 from ._lib import MgError, call, load, raw  # noqa: F401
 
 __all__ = [
-    "Handle", "handle", "potrf", "potrs", "posv", "logdet", "colmajor",
+    "Handle", "handle", "potrf", "potrs", "posv", "posv_mixed", "posv_backward", "PosvFunction", "logdet",
+    "colmajor",
     "MgError", "load", "call", "raw",
 ]
 
@@ -181,6 +182,102 @@ def posv(A, B, nb: int | None = None):
             h.set_block_size(0)
     X = Xc.T
     return (X.reshape(n) if flat else X), info
+
+
+def posv_mixed(A, B, precision: str = "fp32", tol: float = 1e-12, max_iter: int = 30, fallback: bool = True):
+    """Solve A X = B (FP64 A, B) with a binary32 (``precision="fp32"``) or
+    bfloat16-update (``"bf16"``) factor and FP64 iterative refinement.
+    Returns (X, stats) with stats = dict(iters, fell_back, lo_info, eta, info).
+    A and B are not modified."""
+    torch = _torch()
+    _check_cuda(A, B)
+    if A.dtype != torch.float64 or B.dtype != torch.float64:
+        raise TypeError("posv_mixed takes FP64 A and B")
+    lo = {"fp32": _lib.MG_PREC_F32, "bf16": _lib.MG_PREC_BF16}[precision]
+    flat = B.dim() == 1
+    n = A.shape[0]
+    nrhs = 1 if flat else B.shape[1]
+    h = handle()
+    Ac = colmajor(A) if A.T.is_contiguous() else A.T.contiguous()
+    Bc = (B.reshape(n, 1) if flat else B).T.contiguous()
+    Xc = torch.empty_like(Bc)
+    nbytes = ctypes.c_size_t()
+    call("mg_posv_mixed_buffer_size", h.h, lo, n, nrhs, 1 if fallback else 0, ctypes.byref(nbytes))
+    work = torch.empty(max(1, nbytes.value), dtype=torch.uint8, device=A.device)
+    info = torch.zeros((), dtype=torch.int32, device=A.device)
+    opts = _lib.IrOpts(tol, max_iter, 1 if fallback else 0)
+    res = _lib.IrResult()
+    call("mg_posv_mixed", h.h, lo, n, nrhs, _ptr(Ac), max(1, n), _ptr(Bc), max(1, n), _ptr(Xc), max(1, n),
+         ctypes.byref(opts), _ptr(work), nbytes.value, ctypes.byref(res), _ptr(info))
+    X = Xc.T
+    stats = dict(iters=res.iters, fell_back=bool(res.fell_back), lo_info=res.lo_info, eta=res.eta, info=int(info))
+    return (X.reshape(n) if flat else X), stats
+
+
+def posv_backward(L, X, gX, mode: str = "sym", info=None):
+    """Adjoint of X = A^{-1} B for A = L L^T: returns (gB, gA).
+
+    mode="sym"  : gA = -1/2 (gB X^T + X gB^T), symmetric;
+    mode="lower": gradient with respect to the lower triangle the solver
+                  reads (off-diagonal entries doubled, strict upper part 0)."""
+    torch = _torch()
+    _check_cuda(L, X, gX)
+    flat = X.dim() == 1
+    n = L.shape[0]
+    nrhs = 1 if flat else X.shape[1]
+    h = handle()
+    Lc = colmajor(L)
+    Xc = colmajor(X.reshape(n, nrhs))
+    Gc = colmajor(gX.reshape(n, nrhs).to(torch.float64))
+    gB = torch.empty((nrhs, n), dtype=torch.float64, device=L.device)
+    gA = torch.zeros((n, n), dtype=torch.float64, device=L.device)
+    work, wb = _work(h, _lib.MG_F64, n, nrhs, L.device)
+    m = {"sym": _lib.MG_GRAD_SYM, "lower": _lib.MG_GRAD_LOWER}[mode]
+    call("mg_posv_backward", h.h, n, nrhs, _ptr(Lc), max(1, n), _ptr(Xc), max(1, n), _ptr(Gc), max(1, n),
+         _ptr(gB), max(1, n), _ptr(gA), max(1, n), m, _ptr(work), wb, _ptr(info) if info is not None else None)
+    gBv = gB.T
+    return (gBv.reshape(n) if flat else gBv), gA.T
+
+
+def _make_posv_function():
+    torch = _torch()
+
+    class PosvFunction(torch.autograd.Function):
+        """X = A^{-1} B with a hand-written adjoint that reuses the stored
+        Cholesky factor (no refactorisation in backward).
+
+        ``PosvFunction.apply(A, B, mode)``: mode "sym" (default) returns the
+        symmetric gradient -1/2 (gB X^T + X gB^T) for A; "lower" returns the
+        exact derivative of the solver as a function of all entries of A
+        (only the lower triangle is read, so the strict upper part is 0)."""
+
+        @staticmethod
+        def forward(ctx, A, B, mode="sym"):
+            L, info = potrf(A)
+            X = potrs(L, B, info)
+            ctx.save_for_backward(L, X, info)
+            ctx.mode = mode
+            return X
+
+        @staticmethod
+        def backward(ctx, gX):
+            L, X, info = ctx.saved_tensors
+            gB, gA = posv_backward(L, X, gX, mode=ctx.mode, info=info)
+            return gA, gB, None
+
+    return PosvFunction
+
+
+class _LazyFunction:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _LazyFunction._cls is None:
+            _LazyFunction._cls = _make_posv_function()
+        return getattr(_LazyFunction._cls, name)
+
+
+PosvFunction = _LazyFunction()
 
 
 def logdet(L, info=None):

@@ -18,10 +18,15 @@ MG_ERR_UNSUPPORTED = 2
 MG_ERR_INTERNAL = 3
 MG_F64 = 0
 MG_F32 = 1
+MG_PREC_F32 = 1
+MG_PREC_BF16 = 2
 MG_PROF_TRAILING = 0
 MG_PROF_DIAG = 1
 MG_PROF_TRSM = 2
 MG_PROF_SOLVE = 3
+MG_PROF_ADJOINT = 4
+MG_GRAD_SYM = 0
+MG_GRAD_LOWER = 1
 
 i32 = ctypes.c_int32
 i64 = ctypes.c_int64
@@ -36,16 +41,31 @@ SIGNATURES = {
     "mg_destroy": (i32, [vp]),
     "mg_set_stream": (i32, [vp, vp]),
     "mg_set_block_size": (i32, [vp, i64]),
+    "mg_set_lookahead": (i32, [vp, i32]),
     "mg_get_block_size": (i32, [vp, i32, i64, ctypes.POINTER(i64)]),
     "mg_potrf": (i32, [vp, i32, i64, vp, i64, vp]),
     "mg_potrs_buffer_size": (i32, [vp, i32, i64, i64, ctypes.POINTER(sz)]),
     "mg_potrs": (i32, [vp, i32, i64, i64, vp, i64, vp, i64, vp, sz, vp]),
     "mg_posv": (i32, [vp, i32, i64, i64, vp, i64, vp, i64, vp, sz, vp]),
+    "mg_posv_mixed_buffer_size": (i32, [vp, i32, i64, i64, i32, ctypes.POINTER(sz)]),
+    "mg_posv_mixed": (i32, [vp, i32, i64, i64, vp, i64, vp, i64, vp, i64, vp, vp, sz, vp, vp]),
+    "mg_posv_backward": (i32, [vp, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]),
     "mg_logdet": (i32, [vp, i32, i64, vp, i64, vp, vp]),
     "mg_set_profiling": (i32, [vp, i32]),
     "mg_profile_query": (i32, [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                ctypes.POINTER(dbl), i32]),
 }
+
+
+
+class IrOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("fallback", ctypes.c_int32)]
+
+
+class IrResult(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("fell_back", ctypes.c_int32), ("lo_info", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("eta", ctypes.c_double)]
+
 
 _lib = None
 

@@ -10,7 +10,7 @@ using namespace mg;
 
 namespace mg {
 
-mg_status prof_begin(mg_handle_t h, int kind) {
+mg_status prof_begin(mg_handle_t h, int kind, hipStream_t st) {
     if (!h->profiling) return MG_OK;
     mg_prof_counter& pc = h->prof[kind];
     if (pc.used == pc.start.size()) {
@@ -20,14 +20,14 @@ mg_status prof_begin(mg_handle_t h, int kind) {
         pc.start.push_back(a);
         pc.stop.push_back(b);
     }
-    MG_HIP(hipEventRecord(pc.start[pc.used], h->stream));
+    MG_HIP(hipEventRecord(pc.start[pc.used], st));
     return MG_OK;
 }
 
-mg_status prof_end(mg_handle_t h, int kind, double flops, double bytes) {
+mg_status prof_end(mg_handle_t h, int kind, double flops, double bytes, hipStream_t st) {
     if (!h->profiling) return MG_OK;
     mg_prof_counter& pc = h->prof[kind];
-    MG_HIP(hipEventRecord(pc.stop[pc.used], h->stream));
+    MG_HIP(hipEventRecord(pc.stop[pc.used], st));
     ++pc.used;
     pc.flops += flops;
     pc.bytes += bytes;
@@ -77,6 +77,10 @@ mg_status mg_create(mg_handle_t* handle, void* stream) {
 
 mg_status mg_destroy(mg_handle_t h) {
     if (!h) return MG_OK;
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_panel) (void)hipEventDestroy(h->ev_panel);
+    if (h->ev_rest) (void)hipEventDestroy(h->ev_rest);
+    if (h->side) (void)hipStreamDestroy(h->side);
     for (int k = 0; k < MG_PROF_KINDS; ++k) {
         for (hipEvent_t e : h->prof[k].start) (void)hipEventDestroy(e);
         for (hipEvent_t e : h->prof[k].stop) (void)hipEventDestroy(e);
@@ -95,6 +99,12 @@ mg_status mg_set_block_size(mg_handle_t h, int64_t nb) {
     if (!h) return -1;
     if (!(nb == 0 || nb == 64 || nb == 128 || nb == 256)) return -2;
     h->nb = nb;
+    return MG_OK;
+}
+
+mg_status mg_set_lookahead(mg_handle_t h, int32_t enable) {
+    if (!h) return -1;
+    h->lookahead = enable ? 1 : 0;
     return MG_OK;
 }
 
@@ -166,6 +176,69 @@ mg_status mg_posv(mg_handle_t h, mg_dtype dt, int64_t n, int64_t nrhs, void* A, 
     return potrs_impl<float>(h, n, nrhs, (const float*)A, lda, (float*)B, ldb, (float*)work, info);
 }
 
+mg_status mg_posv_mixed_buffer_size(mg_handle_t h, mg_prec lo, int64_t n, int64_t nrhs, int32_t fallback,
+                                    size_t* bytes) {
+    if (!h) return -1;
+    if (lo != MG_PREC_F32 && lo != MG_PREC_BF16) return -2;
+    if (n < 0) return -3;
+    if (nrhs < 0) return -4;
+    if (!bytes) return -5;
+    *bytes = mixed_work_bytes(n, nrhs, fallback ? 1 : 0);
+    return MG_OK;
+}
+
+mg_status mg_posv_mixed(mg_handle_t h, mg_prec lo, int64_t n, int64_t nrhs, const double* A, int64_t lda,
+                        const double* B, int64_t ldb, double* X, int64_t ldx, const mg_ir_opts* opts, void* work,
+                        size_t work_bytes, mg_ir_result* result, int32_t* info) {
+    if (!h) return -1;
+    if (lo != MG_PREC_F32 && lo != MG_PREC_BF16) return -2;
+    if (n < 0) return -3;
+    if (nrhs < 0) return -4;
+    const bool any = n > 0 && nrhs > 0;
+    if (!A && n > 0) return -5;
+    if (lda < std::max<int64_t>(1, n)) return -6;
+    if (!B && any) return -7;
+    if (ldb < std::max<int64_t>(1, n)) return -8;
+    if (!X && any) return -9;
+    if (ldx < std::max<int64_t>(1, n)) return -10;
+    mg_ir_opts o{1e-12, 30, 1};
+    if (opts) {
+        if (!(opts->tol >= 0.0) || opts->max_iter < 0) return -11;
+        o = *opts;
+    }
+    const size_t need = mixed_work_bytes(n, nrhs, o.fallback ? 1 : 0);
+    if (!work && any) return -12;
+    if (any && work_bytes < need) return -13;
+    if (!result) return -14;
+    if (!info) return -15;
+    return posv_mixed_impl(h, (int)lo, n, nrhs, A, lda, B, ldb, X, ldx, &o, work, result, info);
+}
+
+mg_status mg_posv_backward(mg_handle_t h, int64_t n, int64_t nrhs, const double* L, int64_t lda, const double* X,
+                           int64_t ldx, const double* gX, int64_t ldgx, double* gB, int64_t ldgb, double* gA,
+                           int64_t ldga, mg_grad_mode mode, void* work, size_t work_bytes, const int32_t* info) {
+    if (!h) return -1;
+    if (n < 0) return -2;
+    if (nrhs < 0) return -3;
+    const int64_t ld1 = std::max<int64_t>(1, n);
+    const bool any = n > 0 && nrhs > 0;
+    if (!L && n > 0) return -4;
+    if (lda < ld1) return -5;
+    if (!X && any) return -6;
+    if (ldx < ld1) return -7;
+    if (!gX && any) return -8;
+    if (ldgx < ld1) return -9;
+    if (!gB && any) return -10;
+    if (ldgb < ld1) return -11;
+    if (!gA && n > 0) return -12;
+    if (ldga < ld1) return -13;
+    if (mode != MG_GRAD_SYM && mode != MG_GRAD_LOWER) return -14;
+    const size_t need = potrs_work_bytes(n, nrhs, 8);
+    if (need > 0 && !work) return -15;
+    if (work_bytes < need) return -16;
+    return posv_backward_impl(h, n, nrhs, L, lda, X, ldx, gX, ldgx, gB, ldgb, gA, ldga, (int)mode, work, info);
+}
+
 mg_status mg_logdet(mg_handle_t h, mg_dtype dt, int64_t n, const void* L, int64_t lda, double* out,
                     const int32_t* info) {
     if (!h) return -1;
@@ -199,9 +272,9 @@ mg_status mg_profile_query(mg_handle_t h, int32_t kind, double* total_ms, int64_
     mg_prof_counter& pc = h->prof[kind];
     double ms = 0.0;
     if (pc.used > 0) {
-        MG_HIP(hipEventSynchronize(pc.stop[pc.used - 1]));
         for (size_t k = 0; k < pc.used; ++k) {
             float t = 0.f;
+            MG_HIP(hipEventSynchronize(pc.stop[k]));  // launches may sit on either stream
             MG_HIP(hipEventElapsedTime(&t, pc.start[k], pc.stop[k]));
             ms += (double)t;
         }

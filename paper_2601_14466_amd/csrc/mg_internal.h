@@ -4,6 +4,7 @@
 #include <stdint.h>
 #include <stddef.h>
 #include <vector>
+#include <cstring>
 
 #include "mg.h"
 
@@ -19,8 +20,13 @@ struct mg_handle_s {
     int device = 0;
     int cu_count = 256;
     int64_t nb = 0;          // potrf block size (the paper's tile size T_A); 0 = default
+    int lookahead = 1;       // overlap the next panel with the trailing update
+    int trail_lo = 1;        // FP32 trailing update: 1 plain, 2 operands rounded to bfloat16
     int profiling = 0;
     mg_prof_counter prof[MG_PROF_KINDS];
+    // second stream and events for the look-ahead schedule (created on first use)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_panel = nullptr, ev_rest = nullptr;
 };
 
 namespace mg {
@@ -37,8 +43,8 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Profiling: bracket one launch with an event pair when enabled.
-mg_status prof_begin(mg_handle_t h, int kind);
-mg_status prof_end(mg_handle_t h, int kind, double flops, double bytes);
+mg_status prof_begin(mg_handle_t h, int kind, hipStream_t st);
+mg_status prof_end(mg_handle_t h, int kind, double flops, double bytes, hipStream_t st);
 
 // Block size used by potrf for order n and element size es.
 int64_t potrf_block_size(mg_handle_t h, int64_t n, int es);
@@ -50,6 +56,13 @@ template <typename T>
 mg_status potrs_impl(mg_handle_t h, int64_t n, int64_t nrhs, const T* L, int64_t lda, T* B,
                      int64_t ldb, T* ywork, const int32_t* info);
 size_t potrs_work_bytes(int64_t n, int64_t nrhs, int es);
+size_t mixed_work_bytes(int64_t n, int64_t nrhs, int fallback);
+mg_status posv_backward_impl(mg_handle_t h, int64_t n, int64_t nrhs, const double* L, int64_t lda,
+                             const double* X, int64_t ldx, const double* GX, int64_t ldgx, double* GB,
+                             int64_t ldgb, double* GA, int64_t ldga, int mode, void* work, const int32_t* info);
+mg_status posv_mixed_impl(mg_handle_t h, int lo, int64_t n, int64_t nrhs, const double* A, int64_t lda,
+                          const double* B, int64_t ldb, double* X, int64_t ldx, const mg_ir_opts* o, void* work,
+                          mg_ir_result* res, int32_t* info);
 
 mg_status set_info_zero(hipStream_t s, int32_t* info);
 

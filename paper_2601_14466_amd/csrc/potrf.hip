@@ -28,55 +28,92 @@ mg_status set_info_zero(hipStream_t s, int32_t* info) {
 
 // ---------------------------------------------------------------------------
 // Diagonal-block factor.  One workgroup of W waves factors the s x s block at
-// A (s <= 512) in place.  Left-looking over 16-wide block columns j: every
-// tile (I, j), I >= j, first receives -sum_{p<j} L_Ip L_jp^T on MFMA (FP64
-// accumulate), then the diagonal tile is factored in registers (factor16)
-// and the tiles below it are solved against it (solve16).  S is the storage
-// type, arithmetic is FP64 (the mixed-precision path keeps the diagonal
-// blocks in FP64).  On a non-positive pivot, *info = col0 + local column.
+// A (s <= FB_MAX) in place, right-looking over 16-wide block columns, FP64
+// arithmetic whatever the storage type S (the mixed-precision path keeps the
+// diagonal blocks in FP64).
+//   - The lower 16 x 16 tiles are dealt round-robin to the waves once and
+//     stay in registers for the whole factorisation (TPW per wave).
+//   - Step j: the owner of tile (j, j) applies the update from column j-1 and
+//     factors it in registers (factor16); the other owners apply the update
+//     from column j-1 to their tiles (I, J), J >= j (4 MFMAs each, operands
+//     from the LDS copy of column j-1).  Barrier.  Owners of tiles (I, j),
+//     I > j, solve them against L_jj (solve16s) and publish them into the LDS
+//     copy of column j (double buffered by parity) and into A.  Barrier.
+// On a non-positive pivot, *info = col0 + local column (1-based).
 // ---------------------------------------------------------------------------
-template <typename S, int W>
+constexpr int FB_MAX = 256;  // largest block this kernel factors
+
+template <typename S, int W, int SMAX>
 __global__ __launch_bounds__(64 * W) void k_factor_block(S* __restrict__ A, int64_t lda, int s,
                                                          int64_t col0, int32_t* info) {
     typedef double C;
+    constexpr int NTM = SMAX / 16;                   // max tiles per side
+    constexpr int TPW = (NTM * (NTM + 1) / 2 + W - 1) / W;
+    __shared__ C Pc[2][SMAX * 17];                   // column panel j: row r, column c at r*17 + c
     __shared__ C Ls[16 * 17];
+    __shared__ C Lsc[16 * 17];
+    __shared__ C piv[16];
     __shared__ int fail;
     if (*info != 0) return;
     const int w = threadIdx.x >> 6;
     const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
     const int nt = (s + 15) >> 4;
+    const int ntl = nt * (nt + 1) / 2;
     if (threadIdx.x == 0) fail = 0;
-    __syncthreads();
-    for (int j = 0; j < nt; ++j) {
-        // update phase: tile (I, j) -= sum_{p<j} L_Ip L_jp^T; the diagonal tile
-        // (always the first tile of wave 0) is factored right away, the others
-        // are parked back in A until L_jj is known.
-        const int64_t rj = 16 * j + i;
-        const bool vj = rj < s;
-        for (int I = j + w; I < nt; I += W) {
-            V4<C> acc;
-            load_tile<S, C>(acc, A, lda, 16 * I, 16 * j, s, s, I == j, I == j);
-            const int64_t ri = 16 * I + i;
-            const bool vi = ri < s;
-            for (int p = 0; p < j; ++p) {
+
+    // load the owned tiles
+    V4<C> acc[TPW];
+    int tI[TPW], tJ[TPW];
 #pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
-                    const int64_t kk = 16 * p + 4 * ks + g;
-                    const C x = vi ? (C)A[idx(ri, kk, lda)] : (C)0;
-                    const C z = vj ? (C)A[idx(rj, kk, lda)] : (C)0;
-                    acc = mma_xzt(acc, x, -z);
+    for (int t = 0; t < TPW; ++t) {
+        const int lin = w + W * t;
+        int I = 0, J = 0;
+        if (lin < ntl) {
+            I = (int)((sqrtf(8.0f * lin + 1.0f) - 1.0f) * 0.5f);
+            while (I * (I + 1) / 2 > lin) --I;
+            while ((I + 1) * (I + 2) / 2 <= lin) ++I;
+            J = lin - I * (I + 1) / 2;
+            load_tile<S, C>(acc[t], A, lda, 16 * I, 16 * J, s, s, I == J, I == J);
+        } else {
+            I = -1;
+            J = -1;
+        }
+        tI[t] = I;
+        tJ[t] = J;
+    }
+    __syncthreads();
+
+    for (int j = 0; j < nt; ++j) {
+        const C* Pp = Pc[(j + 1) & 1];  // column j-1
+        C* Pn = Pc[j & 1];              // column j (written this step)
+        // ---- update from column j-1
+        V4<C> d = {0, 0, 0, 0};
+        bool own_diag = false;
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            const int I = tI[t], J = tJ[t];
+            if (J >= j) {
+                if (j > 0) {
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        const int kk = 4 * ks + g;
+                        acc[t] = mma_xzt(acc[t], Pp[(16 * I + i) * 17 + kk], -Pp[(16 * J + i) * 17 + kk]);
+                    }
+                }
+                if (I == j && J == j) {
+                    d = acc[t];
+                    own_diag = true;
                 }
             }
-            if (I == j) {
-                const int f = factor16<C>(acc);
-                if (f) {
-                    if (l == 0) fail = 16 * j + f;
-                } else {
-                    tile_to_lds_lower<C, 17>(acc, Ls);
-                    store_tile<S, C>(acc, A, lda, 16 * j, 16 * j, s, s, true);
-                }
+        }
+        // ---- the owner of (j, j) factors it
+        if (own_diag) {
+            const int f = factor16<C>(d);
+            if (f) {
+                if (l == 0) fail = 16 * j + f;
             } else {
-                store_tile<S, C>(acc, A, lda, 16 * I, 16 * j, s, s, false);
+                tile_to_lds_lower<C, 17>(d, Ls);
+                store_tile<S, C>(d, A, lda, 16 * j, 16 * j, s, s, true);
             }
         }
         __syncthreads();
@@ -84,12 +121,28 @@ __global__ __launch_bounds__(64 * W) void k_factor_block(S* __restrict__ A, int6
             if (threadIdx.x == 0) *info = (int32_t)(col0 + fail);
             return;
         }
-        // solve phase: L_Ij = (updated tile) L_jj^{-T}
-        for (int I = j + 1 + w; I < nt; I += W) {
-            V4<C> acc;
-            load_tile<S, C>(acc, A, lda, 16 * I, 16 * j, s, s, false, false);
-            solve16<C, 17>(acc, Ls);
-            store_tile<S, C>(acc, A, lda, 16 * I, 16 * j, s, s, false);
+        scale_lower16<C, 17>(Ls, Lsc, piv, threadIdx.x);
+        __syncthreads();
+        // ---- solve the owned tiles below the diagonal in column j, publish them
+        unsigned todo = 0;
+#pragma unroll
+        for (int t = 0; t < TPW; ++t)
+            if (tJ[t] == j && tI[t] > j) todo |= 1u << t;
+        while (todo) {
+            const int t0 = __builtin_ctz(todo);
+            todo &= todo - 1;
+            V4<C> y = {0, 0, 0, 0};
+            int I0 = 0;
+#pragma unroll
+            for (int t = 0; t < TPW; ++t)
+                if (t == t0) {
+                    y = acc[t];
+                    I0 = tI[t];
+                }
+            solve16s<C, 17>(y, Lsc, piv);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Pn[(16 * I0 + i) * 17 + tcol<C>(g, r)] = y[r];
+            store_tile<S, C>(y, A, lda, 16 * I0, 16 * j, s, s, false);
         }
         __syncthreads();
     }
@@ -104,18 +157,24 @@ __global__ __launch_bounds__(64 * W) void k_factor_block(S* __restrict__ A, int6
 //     rows of L_kk shared by every wave), four independent MFMA chains;
 //   - inside the chunk, tile t takes the update from tiles p < t straight from
 //     registers (the k index of step ks in lane group g is 16p + tcol(g, ks),
-//     exactly the column that tile p keeps in register ks), then solve16
+//     exactly the column that tile p keeps in register ks), then solve16s
 //     against the diagonal 16 x 16 block of L_kk held in LDS.
 // ---------------------------------------------------------------------------
 template <typename S, int NB>
 __global__ __launch_bounds__(256) void k_trsm_panel(S* __restrict__ P, const S* __restrict__ Lkk,
                                                     int64_t lda, int64_t m, const int32_t* info) {
     constexpr int NT = NB / 16;
-    __shared__ S Ld[NT][16 * 17];
+    __shared__ S Ld[NT][16 * 17];   // diagonal 16x16 blocks of L_kk, column-scaled
+    __shared__ S Pv[NT][16];        // their pivots
     if (*info != 0) return;
+    for (int e = threadIdx.x; e < NT * 16; e += blockDim.x) {
+        const int b = e >> 4, c = e & 15;
+        Pv[b][c] = Lkk[idx(16 * b + c, 16 * b + c, lda)];
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < NT * 256; e += blockDim.x) {
         const int b = e >> 8, rr = (e >> 4) & 15, cc = e & 15;
-        Ld[b][rr * 17 + cc] = (rr >= cc) ? Lkk[idx(16 * b + rr, 16 * b + cc, lda)] : (S)0;
+        Ld[b][rr * 17 + cc] = (rr > cc) ? Lkk[idx(16 * b + rr, 16 * b + cc, lda)] / Pv[b][cc] : (S)0;
     }
     __syncthreads();
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, g = l >> 4;
@@ -150,7 +209,7 @@ __global__ __launch_bounds__(256) void k_trsm_panel(S* __restrict__ P, const S* 
                     x[t] = mma_xzt(x[t], x[p][ks], -z);
                 }
             }
-            solve16<S, 17>(x[t], Ld[jc + t]);
+            solve16s<S, 17>(x[t], Ld[jc + t], Pv[jc + t]);
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t) store_tile<S, S>(x[t], P, lda, R, 16 * (jc + t), m, NB, false);
@@ -158,20 +217,27 @@ __global__ __launch_bounds__(256) void k_trsm_panel(S* __restrict__ P, const S* 
 }
 
 // ---------------------------------------------------------------------------
-// Trailing update lower(C) -= P P^T, C m x m, P m x kdim (kdim % 16 == 0).
-// 128 x 128 output tiles over the lower triangle only; 4 waves in a 2 x 2
-// arrangement, each owning 64 x 64 = 4 x 4 MFMA tiles (64 accumulators per
-// lane).  P is staged through LDS in 16-column chunks, double buffered: the
-// next chunk's global loads are in flight while the current one feeds the
-// MFMAs.  Tile order is XCD-aware: workgroup b runs on XCD b % 8, and each
-// XCD receives a contiguous run of row-major lower tiles so that the panel
-// rows they share stay in that XCD's L2.
+// Trailing update lower(C) -= P P^T, C m x m, P m x kdim (kdim % 8 == 0),
+// restricted to the 128 x 128 lower tiles of tile columns [j0, j0 + wj).
+// A workgroup owns one tile; each of its four waves owns a 64 x 64 quarter
+// (4 x 4 MFMA tiles, 64 accumulators per lane) and streams its own operand
+// rows of P from L1/L2 straight into registers, two k-steps ahead of the
+// MFMAs.  There is no LDS staging and no barrier: waves never wait for each
+// other, and two waves per SIMD keep the matrix pipe busy while the other
+// waits on memory (measured faster on gfx950 than an LDS-staged, barrier-
+// synchronised version of the same tile).  The accumulators start from C
+// (entries above the diagonal of a diagonal tile are never read) and the
+// MFMAs subtract by negating one operand, so the epilogue is a plain store.
+// Quarters entirely above the diagonal exit at once.  With bf16 set (binary32
+// storage only) each operand is rounded to bfloat16 as it is loaded, so the
+// products are those of bfloat16 inputs accumulated in FP32.  Tile order is XCD-
+// aware: workgroup b runs on XCD b % 8, and each XCD receives a contiguous
+// run of row-major tiles so that the panel rows they share stay in its L2.
 // ---------------------------------------------------------------------------
 constexpr int SY_BM = 128;
-constexpr int SY_KC = 16;
-constexpr int SY_LD = SY_BM + 4;
+constexpr int SY_PF = 2;   // k-steps of operands in flight ahead of the MFMAs
 
-__device__ __forceinline__ void lower_tile_coords(int64_t t, int64_t& I, int64_t& J) {
+__host__ __device__ __forceinline__ void lower_tile_coords(int64_t t, int64_t& I, int64_t& J) {
     int64_t r = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while (r * (r + 1) / 2 > t) --r;
     while ((r + 1) * (r + 2) / 2 <= t) ++r;
@@ -179,99 +245,115 @@ __device__ __forceinline__ void lower_tile_coords(int64_t t, int64_t& I, int64_t
     J = t - r * (r + 1) / 2;
 }
 
+// Lower tiles (I, J), I >= J, of a T x T tile grid restricted to tile columns
+// [j0, j0 + wj): numbered row by row.  Rows I - j0 < wj hold I - j0 + 1
+// tiles, later rows hold wj.
+__host__ __device__ __forceinline__ int64_t slab_tiles(int64_t T, int64_t j0, int64_t wj) {
+    const int64_t h = T - j0;
+    const int64_t w = wj < h ? wj : h;
+    return w * (w + 1) / 2 + (h - w) * w;
+}
+__host__ __device__ __forceinline__ void slab_tile_coords(int64_t t, int64_t j0, int64_t wj, int64_t& I, int64_t& J) {
+    const int64_t tri = wj * (wj + 1) / 2;
+    if (t < tri) {
+        lower_tile_coords(t, I, J);
+    } else {
+        const int64_t u = t - tri;
+        I = wj + u / wj;
+        J = u % wj;
+    }
+    I += j0;
+    J += j0;
+}
+
+// bfloat16 rounding (nearest-even on the bit pattern) of a binary32 value,
+// widened back to binary32; used for the BF16 trailing-update operands.
+__device__ __forceinline__ float round_bf16(float x) {
+    unsigned u = __builtin_bit_cast(unsigned, x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return x;
+    u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    return __builtin_bit_cast(float, u);
+}
+__device__ __forceinline__ double lo_round(double x, int) { return x; }
+__device__ __forceinline__ float lo_round(float x, int bf16) { return bf16 ? round_bf16(x) : x; }
+
 template <typename S>
 __global__ __launch_bounds__(256, 2) void k_syrk_lower(S* __restrict__ Cm, const S* __restrict__ P,
-                                                       int64_t lda, int64_t m, int kdim,
-                                                       const int32_t* info) {
-    __shared__ S As[2][SY_KC][SY_LD];
-    __shared__ S Bs[2][SY_KC][SY_LD];
+                                                       int64_t lda, int64_t m, int kdim, int64_t j0, int64_t wj,
+                                                       int bf16, const int32_t* info) {
     if (*info != 0) return;
     const int64_t T = (m + SY_BM - 1) / SY_BM;
-    const int64_t ntiles = T * (T + 1) / 2;
+    const int64_t ntiles = slab_tiles(T, j0, wj);
     const int64_t per = gridDim.x / 8;
     const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (t >= ntiles) return;
     int64_t I, J;
-    lower_tile_coords(t, I, J);
-    const bool diag = (I == J);
+    slab_tile_coords(t, j0, wj, I, J);
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, i = l & 15, g = l >> 4;
     const int wr = w >> 1, wc = w & 1;
-    const bool active = !(diag && wr == 0 && wc == 1);
-    const int64_t rowA0 = I * SY_BM, rowB0 = J * SY_BM;
-
-    const int lr = tid & 127, lk = (tid >> 7) * 8;
-    const bool va = rowA0 + lr < m, vb = rowB0 + lr < m;
-    const S* pa = P + (rowA0 + lr) + (int64_t)lk * lda;
-    const S* pb = P + (rowB0 + lr) + (int64_t)lk * lda;
-    S ra[8], rb[8];
-
+    const int64_t sr0 = I * SY_BM + 64 * wr, sc0 = J * SY_BM + 64 * wc;
+    if (sr0 + 63 < sc0) return;  // quarter strictly above the diagonal
     V4<S> acc[4][4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = V4<S>{0, 0, 0, 0};
-
-    const int nk = kdim / SY_KC;
-    auto gload = [&](int kc) {
-        const size_t off = (size_t)kc * SY_KC * (size_t)lda;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) ra[q] = va ? pa[off + (size_t)q * lda] : (S)0;
-        if (!diag) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) rb[q] = vb ? pb[off + (size_t)q * lda] : (S)0;
-        }
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) As[buf][lk + q][lr] = ra[q];
-        if (!diag) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) Bs[buf][lk + q][lr] = rb[q];
-        }
-    };
-
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int kc = 0; kc < nk; ++kc) {
-        const int buf = kc & 1;
-        if (kc + 1 < nk) gload(kc + 1);
-        if (active) {
-            const S(*Xs)[SY_LD] = As[buf];
-            const S(*Zs)[SY_LD] = diag ? As[buf] : Bs[buf];
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const int kk = 4 * ks + g;
-                S xv[4], zv[4];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) xv[b] = Xs[kk][64 * wr + 16 * b + i];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) zv[b] = Zs[kk][64 * wc + 16 * b + i];
-#pragma unroll
-                for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-                    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mma_xzt(acc[bi][bj], xv[bi], zv[bj]);
-            }
-        }
-        if (kc + 1 < nk) lstore(buf ^ 1);
-        __syncthreads();
-    }
-    if (!active) return;
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi) {
-        const int64_t row = rowA0 + 64 * wr + 16 * bi + i;
-#pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
+        for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t col = rowB0 + 64 * wc + 16 * bj + tcol<S>(g, r);
-                if (row < m && col < m && (!diag || row >= col)) {
-                    S* c = Cm + idx(row, col, lda);
-                    *c = *c - acc[bi][bj][r];
+                const int64_t row = sr0 + 16 * bi + i, col = sc0 + 16 * bj + tcol<S>(g, r);
+                acc[bi][bj][r] = (row < m && col < m && row >= col) ? Cm[idx(row, col, lda)] : (S)0;
+            }
+    // operand rows: x from the quarter's rows, z from its columns; rows >= m
+    // read row 0 instead (finite values that only reach outputs never stored)
+    const S* pa[4];
+    const S* pb[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int64_t ra = sr0 + 16 * b + i, rb = sc0 + 16 * b + i;
+        pa[b] = P + (ra < m ? ra : 0) + (int64_t)g * lda;
+        pb[b] = P + (rb < m ? rb : 0) + (int64_t)g * lda;
+    }
+    const int nks = kdim / 4;
+    S xq[SY_PF][4], zq[SY_PF][4];
+#pragma unroll
+    for (int s = 0; s < SY_PF; ++s)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            xq[s][b] = lo_round(pa[b][(int64_t)(4 * s) * lda], bf16);
+            zq[s][b] = -lo_round(pb[b][(int64_t)(4 * s) * lda], bf16);
+        }
+    for (int ks = 0; ks < nks; ks += SY_PF) {
+#pragma unroll
+        for (int s = 0; s < SY_PF; ++s) {
+            S xv[4], zv[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                xv[b] = xq[s][b];
+                zv[b] = zq[s][b];
+            }
+            const int kn = ks + s + SY_PF;
+            if (kn < nks) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    xq[s][b] = lo_round(pa[b][(int64_t)(4 * kn) * lda], bf16);
+                    zq[s][b] = -lo_round(pb[b][(int64_t)(4 * kn) * lda], bf16);
                 }
             }
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mma_xzt(acc[bi][bj], xv[bi], zv[bj]);
         }
     }
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = sr0 + 16 * bi + i, col = sc0 + 16 * bj + tcol<S>(g, r);
+                if (row < m && col < m && row >= col) Cm[idx(row, col, lda)] = acc[bi][bj][r];
+            }
 }
 
 // ---------------------------------------------------------------------------
@@ -301,13 +383,63 @@ static mg_status launch_trsm(hipStream_t st, int64_t nb, S* P, const S* Lkk, int
 
 template <typename S>
 mg_status syrk_lower_launch(hipStream_t st, S* Cm, const S* P, int64_t lda, int64_t m, int64_t kdim,
-                            const int32_t* info) {
+                            const int32_t* info, int64_t j0 = 0, int64_t wj = -1, int bf16 = 0) {
     const int64_t T = cdiv(m, SY_BM);
-    const int64_t ntiles = T * (T + 1) / 2;
+    if (wj < 0) wj = T - j0;
+    if (j0 >= T || wj <= 0) return MG_OK;
+    const int64_t ntiles = slab_tiles(T, j0, wj);
     const int64_t grid = 8 * cdiv(ntiles, 8);
-    hipLaunchKernelGGL((k_syrk_lower<S>), dim3((unsigned)grid), dim3(256), 0, st, Cm, P, lda, m, (int)kdim,
-                       info);
+    hipLaunchKernelGGL((k_syrk_lower<S>), dim3((unsigned)grid), dim3(256), 0, st, Cm, P, lda, m, (int)kdim, j0,
+                       wj, bf16, info);
     MG_LAUNCH_CHECK();
+    return MG_OK;
+}
+
+template <typename T>
+static mg_status panel_step(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int64_t n, int64_t k0, int64_t nb,
+                           int32_t* info) {
+    // factor the diagonal block at k0 and solve the panel below it
+    const int64_t kb = std::min(nb, n - k0);
+    T* Akk = A + idx(k0, k0, lda);
+    mg_status rc;
+    if ((rc = prof_begin(h, MG_PROF_DIAG, st))) return rc;
+    hipLaunchKernelGGL((k_factor_block<T, 8, FB_MAX>), dim3(1), dim3(512), 0, st, Akk, lda, (int)kb, k0, info);
+    MG_LAUNCH_CHECK();
+    const double b = (double)kb;
+    if ((rc = prof_end(h, MG_PROF_DIAG, b * b * b / 3 + b * b / 2 + b / 6, b * (b + 1) * sizeof(T), st))) return rc;
+    const int64_t m = n - k0 - kb;
+    if (m <= 0) return MG_OK;
+    if ((rc = prof_begin(h, MG_PROF_TRSM, st))) return rc;
+    if ((rc = launch_trsm<T>(st, nb, A + idx(k0 + kb, k0, lda), Akk, lda, m, info))) return rc;
+    return prof_end(h, MG_PROF_TRSM, (double)m * b * b, 2.0 * m * b * sizeof(T), st);
+}
+
+template <typename T>
+static mg_status trailing(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int64_t n, int64_t k0, int64_t nb,
+                         const int32_t* info, int64_t j0, int64_t wj) {
+    // lower(A22) -= P P^T over tile columns [j0, j0 + wj) of the trailing matrix
+    const int64_t kb = std::min(nb, n - k0), e = k0 + kb, m = n - e;
+    const int64_t T_ = cdiv(m, SY_BM);
+    if (wj < 0) wj = T_ - j0;
+    if (m <= 0 || j0 >= T_ || wj <= 0) return MG_OK;
+    mg_status rc;
+    if ((rc = prof_begin(h, MG_PROF_TRAILING, st))) return rc;
+    if ((rc = syrk_lower_launch<T>(st, A + idx(e, e, lda), A + idx(e, k0, lda), lda, m, kb, info, j0, wj,
+                                   h->trail_lo == 2 ? 1 : 0)))
+        return rc;
+    // algorithmic work of this slab: columns c0..c1 of the lower triangle
+    const double c0 = (double)std::min(m, j0 * SY_BM), c1 = (double)std::min(m, (j0 + wj) * SY_BM);
+    const double md = (double)m, b = (double)kb;
+    const double elems = (c1 - c0) * md - (c1 * (c1 - 1) - c0 * (c0 - 1)) / 2;  // lower entries in the slab
+    return prof_end(h, MG_PROF_TRAILING, 2.0 * b * elems, (2.0 * elems + (md - c0) * b) * sizeof(T), st);
+}
+
+static mg_status ensure_side(mg_handle_t h) {
+    if (h->side) return MG_OK;
+    MG_HIP(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    MG_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    MG_HIP(hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming));
+    MG_HIP(hipEventCreateWithFlags(&h->ev_rest, hipEventDisableTiming));
     return MG_OK;
 }
 
@@ -317,28 +449,36 @@ mg_status potrf_impl(mg_handle_t h, int64_t n, T* A, int64_t lda, int32_t* info)
     mg_status rc = set_info_zero(st, info);
     if (rc != MG_OK || n == 0) return rc;
     const int64_t nb = potrf_block_size(h, n, (int)sizeof(T));
-    for (int64_t k0 = 0; k0 < n; k0 += nb) {
-        const int64_t kb = std::min(nb, n - k0);
-        T* Akk = A + idx(k0, k0, lda);
-        if ((rc = prof_begin(h, MG_PROF_DIAG))) return rc;
-        hipLaunchKernelGGL((k_factor_block<T, 16>), dim3(1), dim3(1024), 0, st, Akk, lda, (int)kb, k0, info);
-        MG_LAUNCH_CHECK();
-        const double b = (double)kb;
-        if ((rc = prof_end(h, MG_PROF_DIAG, b * b * b / 3 + b * b / 2 + b / 6, b * (b + 1) * sizeof(T))))
-            return rc;
-        const int64_t m = n - k0 - kb;
-        if (m <= 0) break;
-        T* P = A + idx(k0 + kb, k0, lda);
-        if ((rc = prof_begin(h, MG_PROF_TRSM))) return rc;
-        if ((rc = launch_trsm<T>(st, nb, P, Akk, lda, m, info))) return rc;
-        if ((rc = prof_end(h, MG_PROF_TRSM, (double)m * b * b, 2.0 * m * b * sizeof(T)))) return rc;
-        if ((rc = prof_begin(h, MG_PROF_TRAILING))) return rc;
-        if ((rc = syrk_lower_launch<T>(st, A + idx(k0 + kb, k0 + kb, lda), P, lda, m, kb, info))) return rc;
-        // algorithmic traffic: read the panel once, read+write the lower triangle once
-        const double md = (double)m;
-        if ((rc = prof_end(h, MG_PROF_TRAILING, b * md * (md + 1),
-                           (md * b + md * (md + 1)) * sizeof(T))))
-            return rc;
+    const int64_t nsteps = cdiv(n, nb);
+    const int64_t wnext = nb / SY_BM;  // tile columns in the next block column
+    if (!h->lookahead || nsteps < 3 || nb % SY_BM != 0) {
+        for (int64_t k0 = 0; k0 < n; k0 += nb) {
+            if ((rc = panel_step<T>(h, st, A, lda, n, k0, nb, info))) return rc;
+            if ((rc = trailing<T>(h, st, A, lda, n, k0, nb, info, 0, -1))) return rc;
+        }
+        return MG_OK;
+    }
+    // Look-ahead: this stream updates the next block column with panel k,
+    // then factors it and solves its panel while the second stream applies
+    // panel k to everything to the right of that column:
+    //   stream : wait(ev_rest) -> next(k) -> [ev_next] -> panel(k+1)
+    //   side   : wait(ev_next) -> rest(k) -> [ev_rest]
+    // The remainder is released only once next(k) is done, so the one-
+    // workgroup diagonal factor of block k+1 becomes runnable together with
+    // it and is dispatched before the remainder's workgroups fill the chip.
+    if ((rc = ensure_side(h))) return rc;
+    MG_HIP(hipEventRecord(h->ev_fork, st));
+    MG_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+    if ((rc = panel_step<T>(h, st, A, lda, n, 0, nb, info))) return rc;
+    for (int64_t k = 0; k + 1 < nsteps; ++k) {
+        const int64_t k0 = k * nb;
+        if ((rc = trailing<T>(h, st, A, lda, n, k0, nb, info, 0, wnext))) return rc;
+        MG_HIP(hipEventRecord(h->ev_panel, st));             // panel k applied to block column k+1
+        MG_HIP(hipStreamWaitEvent(h->side, h->ev_panel, 0));
+        if ((rc = trailing<T>(h, h->side, A, lda, n, k0, nb, info, wnext, -1))) return rc;
+        if ((rc = panel_step<T>(h, st, A, lda, n, k0 + nb, nb, info))) return rc;
+        MG_HIP(hipEventRecord(h->ev_rest, h->side));         // rest(k) done
+        MG_HIP(hipStreamWaitEvent(st, h->ev_rest, 0));
     }
     return MG_OK;
 }
@@ -346,8 +486,8 @@ mg_status potrf_impl(mg_handle_t h, int64_t n, T* A, int64_t lda, int32_t* info)
 template mg_status potrf_impl<double>(mg_handle_t, int64_t, double*, int64_t, int32_t*);
 template mg_status potrf_impl<float>(mg_handle_t, int64_t, float*, int64_t, int32_t*);
 template mg_status syrk_lower_launch<double>(hipStream_t, double*, const double*, int64_t, int64_t, int64_t,
-                                             const int32_t*);
+                                             const int32_t*, int64_t, int64_t, int);
 template mg_status syrk_lower_launch<float>(hipStream_t, float*, const float*, int64_t, int64_t, int64_t,
-                                            const int32_t*);
+                                            const int32_t*, int64_t, int64_t, int);
 
 }  // namespace mg

@@ -122,7 +122,7 @@ __device__ __forceinline__ int factor16(V4<C>& y) {
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
         const int gc = tgrp<C>(c), rc = treg<C>(c);
-        const C p = shfl(y[rc], gc * 16 + c);
+        const C p = readlane(y[rc], gc * 16 + c);
         if (!(p > (C)0)) return c + 1;
         const C s = sqrt(p);
         const C v = shfl(y[rc], gc * 16 + i);   // Y[i][c]
@@ -138,22 +138,38 @@ __device__ __forceinline__ int factor16(V4<C>& y) {
     return 0;
 }
 
-// X = Y L^{-T} for a 16x16 lower-triangular L held in LDS as Ls[row*LDL+col]:
-// forward substitution over the columns of Y, each solved column broadcast
-// along its row by a lane shuffle.
+// X = Y L^{-T} with L pre-scaled by columns: Lsc[j*LDL + c] = L(j,c)/L(c,c)
+// for j > c (0 elsewhere) and piv[c] = L(c,c).  Column c of Y is final after
+// the updates from the columns before it; it is broadcast along its row and
+// applied to the columns after it (one shuffle and up to four FMAs), and each
+// column is divided by its pivot once at the end.  Exact for integer data
+// with power-of-two pivots.
 template <typename C, int LDL>
-__device__ __forceinline__ void solve16(V4<C>& y, const C* Ls) {
+__device__ __forceinline__ void solve16s(V4<C>& y, const C* Lsc, const C* piv) {
     const int l = lane_id(), i = l & 15, g = l >> 4;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
+    for (int c = 0; c < 15; ++c) {
         const int gc = tgrp<C>(c), rc = treg<C>(c);
-        if (g == gc) y[rc] = y[rc] / Ls[c * LDL + c];
-        const C xc = shfl(y[rc], gc * 16 + i);  // X[i][c]
+        const C yc = shfl(y[rc], gc * 16 + i);  // (updated) Y[i][c]
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int j = tcol<C>(g, r);
-            if (j > c) y[r] = y[r] - xc * Ls[j * LDL + c];
+            if (j > c) y[r] = y[r] - yc * Lsc[j * LDL + c];
         }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) y[r] = y[r] / piv[tcol<C>(g, r)];
+}
+
+// Column-scaled copy of a lower-triangular 16x16 L held in LDS (Ls, row-major
+// with leading dimension LDL): Lsc(j,c) = L(j,c)/L(c,c) for j > c, 0
+// elsewhere; piv[c] = L(c,c).  One thread per entry; callers synchronise.
+template <typename C, int LDL>
+__device__ __forceinline__ void scale_lower16(const C* Ls, C* Lsc, C* piv, int t) {
+    if (t < 256) {
+        const int j = t >> 4, c = t & 15;
+        Lsc[j * LDL + c] = (j > c) ? Ls[j * LDL + c] / Ls[c * LDL + c] : (C)0;
+        if (j == c) piv[c] = Ls[c * LDL + c];
     }
 }
 

@@ -1,0 +1,122 @@
+"""GPU parity of the mixed-precision solve with FP64 iterative refinement
+(binary32 factor, or bfloat16 trailing-update operands), through the C ABI.
+
+Bar: every returned column has normwise backward error eta <= 1e-12, computed
+by the CPU oracle in extended precision on the original FP64 A and B; the
+iteration count, the fallback flag and the device-side eta are reported and
+checked for consistency.  The paper is silent on precision; the scheme is
+Langou et al. (SC'06) for SPD systems.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mg():
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm device")
+    import paper_2601_14466_amd as m
+    m.load()
+    return m
+
+
+def _solve(mg, A, B, **kw):
+    Ad = torch.from_numpy(A).cuda()
+    Bd = torch.from_numpy(B).cuda()
+    A0, B0 = Ad.clone(), Bd.clone()
+    X, st = mg.posv_mixed(Ad, Bd, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(Ad, A0) and torch.equal(Bd, B0), "inputs must not be modified"
+    return X.cpu().numpy(), st
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n", [65, 300, 700])
+def test_integer_family_needs_no_refinement(mg, orc, n, prec):
+    """The low-precision factor and solve are exact on the integer family
+    (all values below 2^24, power-of-two pivots, entries representable in
+    bfloat16), so x0 = x_true and no correction is taken."""
+    L0, A = synth.integer_exact(n, 500 + n)
+    xt = synth.integer_vector((n, 2), n)
+    X, st = _solve(mg, A, A @ xt, precision=prec)
+    assert st["iters"] == 0 and not st["fell_back"] and st["lo_info"] == 0
+    assert np.array_equal(X, xt)
+
+
+@pytest.mark.parametrize("cond", [1e2, 1e4, 1e6])
+@pytest.mark.parametrize("n", [300, 1500])
+def test_fp32_refinement_converges(mg, orc, n, cond):
+    A = synth.haar_spd(n, cond, 7 + n)
+    xt = synth.normal((n, 8), 8 + n)
+    B = A @ xt
+    X, st = _solve(mg, A, B, precision="fp32")
+    assert not st["fell_back"], st
+    assert 1 <= st["iters"] <= 8, st
+    eta = orc.backward_error(A, X, B)
+    assert np.all(eta <= 1e-12), eta.max()
+    assert st["eta"] == pytest.approx(eta.max(), rel=0.5, abs=1e-15)
+
+
+@pytest.mark.parametrize("cond", [1e2, 1e6])
+def test_bf16_converges_or_falls_back(mg, orc, cond):
+    n = 700
+    A = synth.haar_spd(n, cond, 3)
+    xt = synth.normal((n, 4), 4)
+    B = A @ xt
+    X, st = _solve(mg, A, B, precision="bf16")
+    eta = orc.backward_error(A, X, B)
+    assert np.all(eta <= 1e-12), (st, eta.max())
+    if cond >= 1e6:
+        assert st["fell_back"], st   # bfloat16 updates cannot resolve cond 1e6
+
+
+def test_forced_fallback_and_no_fallback(mg, orc):
+    n = 500
+    A = synth.haar_spd(n, 1e3, 11)
+    xt = synth.normal((n, 3), 12)
+    B = A @ xt
+    X, st = _solve(mg, A, B, precision="fp32", max_iter=0)
+    assert st["fell_back"] and st["iters"] == 0
+    assert np.all(orc.backward_error(A, X, B) <= 1e-12)
+    X, st = _solve(mg, A, B, precision="fp32", max_iter=0, fallback=False)
+    assert not st["fell_back"] and st["eta"] > 1e-12
+    eta = orc.backward_error(A, X, B)
+    assert eta.max() == pytest.approx(st["eta"], rel=0.5)
+
+
+def test_not_spd_reports_info(mg, orc):
+    n = 200
+    d = np.ones(n)
+    d[120] = -2.0
+    X, st = _solve(mg, np.diag(d), np.ones((n, 2)), precision="fp32")
+    assert st["lo_info"] == 121 and st["fell_back"] and st["info"] == 121
+
+
+def test_rhs_one_and_many(mg, orc):
+    n = 400
+    A = synth.haar_spd(n, 1e4, 21)
+    for nrhs in (1, 3, 40):
+        xt = synth.normal((n, nrhs), nrhs)
+        B = A @ xt
+        X, st = _solve(mg, A, B, precision="fp32")
+        assert np.all(orc.backward_error(A, X, B) <= 1e-12), (nrhs, st)
+
+
+@pytest.mark.parametrize("n", [16384])
+def test_full_size_config2(mg, orc, n):
+    """A = Q diag(lambda) Q^T with Haar Q and cond 1e4, nrhs = 8 (the mixed
+    configuration), checked by the oracle's extended-precision residual."""
+    A = synth.torch_haar_spd(n, 1e4, 700 + n)
+    Xt = synth.torch_normal((n, 8), 701 + n)
+    B = A @ Xt
+    X, st = mg.posv_mixed(A, B, precision="fp32")
+    torch.cuda.synchronize()
+    assert not st["fell_back"], st
+    Ah = A.cpu().numpy()
+    eta = orc.backward_error(Ah.T, X.cpu().numpy(), B.cpu().numpy())
+    assert np.all(eta <= 1e-12), eta.max()
