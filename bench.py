@@ -13,7 +13,7 @@ The JSON line also carries
                  launch over its average launch duration from HIP events on
                  the streams it runs on, against the FP64 matrix peak;
   cpu_baseline : the CPU oracle on a bounded sample of the same workload
-                 (n = 6144, nrhs = 16), timed on this host's cores.
+                 (n = 8192, nrhs = 16), timed on this host's cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--nrhs R]
 """
@@ -113,7 +113,7 @@ def bench_fp64(torch, mg, synth, n: int, nrhs: int, steps: int, warmup: int, see
     return out
 
 
-def cpu_baseline(torch, synth, n: int = 6144, nrhs: int = 16, seed: int = 4242):
+def cpu_baseline(torch, synth, n: int = 8192, nrhs: int = 16, seed: int = 4242):
     import oracle  # CPU oracle: baseline leg only
     A = synth.torch_gram_spd_cond(n, seed, 1e4)
     Xt = synth.torch_normal((n, nrhs), seed + 1)

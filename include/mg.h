@@ -202,6 +202,49 @@ mg_status mg_posv_backward(mg_handle_t handle, int64_t n, int64_t nrhs, const do
                            const int32_t *info);
 
 /*
+ * Batched posv: many independent SPD systems of uneven order (0..512) solved
+ * in one persistent launch replayed from a HIP graph.  The paper's operation
+ * applied to a batch (it has no batched form).  A plan fixes the orders, the
+ * number of right-hand sides (1..8) and the launch shape:
+ *   - the systems are taken longest first (or in input order) from an atomic
+ *     counter by a persistent grid of grid_per_cu workgroups per CU;
+ *   - with autotune on (the default) the plan times the candidate launch
+ *     shapes on synthetic systems of the same orders once and keeps the
+ *     fastest; results are cached by (architecture, dtype, nrhs, batch, order
+ *     histogram) in cache_path (NULL: no cache file);
+ *   - the graph holds a counter reset and the persistent kernel; each call
+ *     copies the caller's pointer/leading-dimension arrays into the plan.
+ * Plan creation allocates device memory (descriptor arrays, tuning inputs);
+ * mg_posv_batched allocates nothing.
+ */
+typedef struct mg_batch_plan_s *mg_batch_plan_t;
+typedef struct {
+    int32_t autotune;     /* 1: time the candidates (default), 0: use the fields below */
+    int32_t grid_per_cu;  /* workgroups per CU (1 or 2); 0 = default */
+    int32_t order;        /* 0 longest first, 1 input order, -1 default */
+    const char *cache_path;  /* tuning cache file or NULL */
+} mg_tune_opts;
+/* Errors: -1 handle, -2 dtype, -3 batch < 0, -4 n_host NULL or an order
+ * outside [0, 512], -5 nrhs outside [1, 8], -7 plan NULL. */
+mg_status mg_batch_plan_create(mg_handle_t handle, mg_dtype dtype, int32_t batch, const int64_t *n_host,
+                               int32_t nrhs, const mg_tune_opts *opts, mg_batch_plan_t *plan);
+/* Chosen launch shape and the tuned replay time (ms, -1 if not tuned).  Errors: -1 NULL plan. */
+mg_status mg_batch_plan_info(mg_batch_plan_t plan, int32_t *grid_per_cu, int32_t *order, double *tuned_ms);
+/*
+ * Solve every system: A_dev[k] (device pointer, lda_dev[k] x n_k, lower
+ * triangle, overwritten by L_k) and B_dev[k] (ldb_dev[k] x nrhs, overwritten
+ * by X_k).  A_dev, lda_dev, B_dev, ldb_dev and info_dev are DEVICE arrays of
+ * length batch.  info_dev[k]: 0 or the failing column of system k (its B_k is
+ * then left unmodified; the other systems are unaffected).  Enqueued on the
+ * handle's stream, no host synchronisation.
+ * Errors: -1 handle, -2 plan, -3 A_dev, -4 lda_dev, -5 B_dev, -6 ldb_dev, -7 info_dev.
+ */
+mg_status mg_posv_batched(mg_handle_t handle, mg_batch_plan_t plan, void *const *A_dev, const int64_t *lda_dev,
+                          void *const *B_dev, const int64_t *ldb_dev, int32_t *info_dev);
+/* Release a plan (NULL accepted). */
+mg_status mg_batch_plan_destroy(mg_batch_plan_t plan);
+
+/*
  * logdet: log det A = 2 sum_j log L_jj from the factor (paper: "Software
  * design", potrs bullet: the factorisation can optionally return log det A;
  * used by the Gaussian-process likelihood in "Scientific applications").
@@ -221,6 +264,8 @@ mg_status mg_logdet(mg_handle_t handle, mg_dtype dtype, int64_t n, const void *L
  *   MG_PROF_TRSM      -- panel triangular solve; flops = m b^2
  *   MG_PROF_SOLVE     -- potrs steps; flops = 2 n^2 nrhs in total
  *   MG_PROF_ADJOINT   -- gradient product of mg_posv_backward; flops = 4 n^2 nrhs
+ *   MG_PROF_BATCHED   -- one batched replay; flops = nominal posv flops summed
+ *                        over the systems
  * mg_profile_query synchronises on the last recorded event, returns the
  * summed event time (ms), the number of launches and the summed flops and
  * algorithmic bytes, and resets the counter when reset != 0.
@@ -230,7 +275,8 @@ mg_status mg_logdet(mg_handle_t handle, mg_dtype dtype, int64_t n, const void *L
 #define MG_PROF_TRSM 2
 #define MG_PROF_SOLVE 3
 #define MG_PROF_ADJOINT 4
-#define MG_PROF_KINDS 5
+#define MG_PROF_BATCHED 5
+#define MG_PROF_KINDS 6
 /* Errors: -1 NULL handle. */
 mg_status mg_set_profiling(mg_handle_t handle, int32_t enable);
 /* Errors: -1 NULL handle, -2 bad kind, -3..-6 NULL outputs. */

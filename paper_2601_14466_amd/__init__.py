@@ -19,8 +19,8 @@ from . import _lib
 from ._lib import MgError, call, load, raw  # noqa: F401
 
 __all__ = [
-    "Handle", "handle", "potrf", "potrs", "posv", "posv_mixed", "posv_backward", "PosvFunction", "logdet",
-    "colmajor",
+    "Handle", "handle", "potrf", "potrs", "posv", "posv_mixed", "posv_backward", "PosvFunction", "BatchPlan",
+    "posv_batched", "logdet", "colmajor",
     "MgError", "load", "call", "raw",
 ]
 
@@ -278,6 +278,66 @@ class _LazyFunction:
 
 
 PosvFunction = _LazyFunction()
+
+
+class BatchPlan:
+    """A batched-posv plan (mg_batch_plan_create): fixed orders, nrhs and
+    dtype, launch shape picked by the library's autotuner, persistent kernel
+    replayed from a HIP graph on every solve."""
+
+    def __init__(self, sizes, nrhs: int = 1, dtype=None, autotune: bool = True, grid_per_cu: int = 0,
+                 order: int = -1, cache_path: str | None = None):
+        torch = _torch()
+        import numpy as np
+        self.dtype = dtype or torch.float64
+        self.sizes = np.asarray(sizes, dtype=np.int64)
+        self.nrhs = int(nrhs)
+        self.h = handle()
+        self._cache = cache_path.encode() if cache_path else None
+        opts = _lib.TuneOpts(1 if autotune else 0, int(grid_per_cu), int(order), self._cache)
+        p = ctypes.c_void_p()
+        call("mg_batch_plan_create", self.h.h, _dtype_code(torch.empty(0, dtype=self.dtype)), len(self.sizes),
+             self.sizes.ctypes.data_as(ctypes.c_void_p), self.nrhs, ctypes.byref(opts), ctypes.byref(p))
+        self.p = p
+
+    def info(self):
+        g, o, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        call("mg_batch_plan_info", self.p, ctypes.byref(g), ctypes.byref(o), ctypes.byref(t))
+        return dict(grid_per_cu=g.value, order=o.value, tuned_ms=t.value)
+
+    def solve_raw(self, A_ptrs, lda, B_ptrs, ldb, info):
+        """Device int64 tensors of pointers / leading dimensions, int32 info."""
+        call("mg_posv_batched", handle().h, self.p, _ptr(A_ptrs), _ptr(lda), _ptr(B_ptrs), _ptr(ldb), _ptr(info))
+
+    def solve(self, As, Bs):
+        """Solve every A_k X_k = B_k; returns (list of X_k, int32 info tensor)."""
+        torch = _torch()
+        dev = As[0].device if len(As) else torch.device("cuda")
+        Ab = [a.T.clone(memory_format=torch.contiguous_format) for a in As]
+        Xb = [b.reshape(b.shape[0], -1).T.clone(memory_format=torch.contiguous_format) for b in Bs]
+        ap = torch.tensor([t.data_ptr() for t in Ab], dtype=torch.int64, device=dev)
+        bp = torch.tensor([t.data_ptr() for t in Xb], dtype=torch.int64, device=dev)
+        ld = torch.tensor([max(1, int(a.shape[0])) for a in As], dtype=torch.int64, device=dev)
+        info = torch.zeros(len(As), dtype=torch.int32, device=dev)
+        self.solve_raw(ap, ld, bp, ld, info)
+        torch.cuda.current_stream().synchronize()
+        return [x.T for x in Xb], info
+
+    def __del__(self):
+        try:
+            if getattr(self, "p", None):
+                raw("mg_batch_plan_destroy", self.p)
+                self.p = None
+        except Exception:
+            pass
+
+
+def posv_batched(As, Bs, autotune: bool = True, cache_path: str | None = None):
+    """One-shot batched solve (builds a plan, solves, releases it)."""
+    sizes = [int(a.shape[0]) for a in As]
+    nrhs = 1 if Bs[0].dim() == 1 else int(Bs[0].shape[1])
+    plan = BatchPlan(sizes, nrhs=nrhs, dtype=As[0].dtype, autotune=autotune, cache_path=cache_path)
+    return plan.solve(As, Bs)
 
 
 def logdet(L, info=None):

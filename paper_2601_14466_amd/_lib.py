@@ -25,6 +25,7 @@ MG_PROF_DIAG = 1
 MG_PROF_TRSM = 2
 MG_PROF_SOLVE = 3
 MG_PROF_ADJOINT = 4
+MG_PROF_BATCHED = 5
 MG_GRAD_SYM = 0
 MG_GRAD_LOWER = 1
 
@@ -50,6 +51,10 @@ SIGNATURES = {
     "mg_posv_mixed_buffer_size": (i32, [vp, i32, i64, i64, i32, ctypes.POINTER(sz)]),
     "mg_posv_mixed": (i32, [vp, i32, i64, i64, vp, i64, vp, i64, vp, i64, vp, vp, sz, vp, vp]),
     "mg_posv_backward": (i32, [vp, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]),
+    "mg_batch_plan_create": (i32, [vp, i32, i32, vp, i32, vp, ctypes.POINTER(vp)]),
+    "mg_batch_plan_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
+    "mg_posv_batched": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+    "mg_batch_plan_destroy": (i32, [vp]),
     "mg_logdet": (i32, [vp, i32, i64, vp, i64, vp, vp]),
     "mg_set_profiling": (i32, [vp, i32]),
     "mg_profile_query": (i32, [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl),
@@ -65,6 +70,11 @@ class IrOpts(ctypes.Structure):
 class IrResult(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("fell_back", ctypes.c_int32), ("lo_info", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("eta", ctypes.c_double)]
+
+
+class TuneOpts(ctypes.Structure):
+    _fields_ = [("autotune", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("cache_path", ctypes.c_char_p)]
 
 
 _lib = None
