@@ -42,7 +42,7 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def bench_fp64(torch, mg, synth, n: int, nrhs: int, steps: int, warmup: int, seed: int = 9000):
+def bench_fp64(torch, mg, synth, n: int, nrhs: int, steps: int, warmup: int, nb: int = 0, seed: int = 9000):
     from paper_2601_14466_amd import _lib
     dev = torch.device("cuda", 0)
     log(f"[bench] generating n={n} nrhs={nrhs} (cond 1e4)")
@@ -58,6 +58,7 @@ def bench_fp64(torch, mg, synth, n: int, nrhs: int, steps: int, warmup: int, see
     Bs = [B0c.clone() for _ in range(ncopy)]
     infos = torch.zeros(ncopy, dtype=torch.int32, device=dev)
     h = mg.handle()
+    h.set_block_size(nb)
     wbytes = ctypes.c_size_t()
     _lib.call("mg_potrs_buffer_size", h.h, _lib.MG_F64, n, nrhs, ctypes.byref(wbytes))
     work = torch.empty(max(1, wbytes.value), dtype=torch.uint8, device=dev)
@@ -113,6 +114,185 @@ def bench_fp64(torch, mg, synth, n: int, nrhs: int, steps: int, warmup: int, see
     return out
 
 
+def _median(xs):
+    xs = sorted(xs)
+    return xs[len(xs) // 2]
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def bench_mixed(torch, mg, synth, n: int, nrhs: int, cond: float, precision: str, reps: int, seed: int = 9500):
+    """Mixed precision + FP64 refinement to eta <= 1e-12 on A = Q diag(lambda) Q^T
+    (Haar Q, log-spaced spectrum with exact cond).  Time covers the cast, the
+    low-precision factor, every refinement step and any fallback; TFLOP/s uses
+    the same nominal FP64 count as the FP64 path."""
+    from paper_2601_14466_amd import _lib
+    log(f"[bench] mixed {precision}: generating n={n} nrhs={nrhs} cond={cond:g} (Haar)")
+    A = synth.torch_haar_spd(n, cond, seed + n)       # symmetric: row-major bytes == column-major
+    Xt = synth.torch_normal((n, nrhs), seed + 1 + n)
+    Bc = (A @ Xt).T.contiguous()
+    Xc = torch.empty_like(Bc)
+    h = mg.handle()
+    h.set_block_size(0)
+    lo = {"fp32": _lib.MG_PREC_F32, "bf16": _lib.MG_PREC_BF16}[precision]
+    nbytes = ctypes.c_size_t()
+    _lib.call("mg_posv_mixed_buffer_size", h.h, lo, n, nrhs, 1, ctypes.byref(nbytes))
+    work = torch.empty(nbytes.value, dtype=torch.uint8, device=A.device)
+    info = torch.zeros((), dtype=torch.int32, device=A.device)
+    opts = _lib.IrOpts(1e-12, 30, 1)
+    res = _lib.IrResult()
+
+    def run():
+        _lib.call("mg_posv_mixed", h.sync_stream(), lo, n, nrhs, _p(A), n, _p(Bc), n, _p(Xc), n, ctypes.byref(opts),
+                  _p(work), nbytes.value, ctypes.byref(res), _p(info))
+
+    run()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = _median(times)
+    X = Xc.T
+    B = Bc.T
+    R = B - A @ X
+    anorm = float(A.abs().sum(1).max())
+    eta = (R.abs().amax(0) / (anorm * X.abs().amax(0) + B.abs().amax(0))).max().item()
+    out = dict(precision=precision, n=n, nrhs=nrhs, cond=cond, ms=round(ms, 3),
+               tflops=round(nominal_flops(n, nrhs) / (ms / 1e3) / 1e12, 3), iters=res.iters,
+               fell_back=bool(res.fell_back), lo_info=res.lo_info, eta_reported=res.eta, eta_fp64_device=eta,
+               info=int(info), reps=reps)
+    del A, Xt, Bc, Xc, work, R, X, B
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_small(torch, mg, synth, n: int = 1024, reps: int = 20, seed: int = 1024):
+    """FP64 posv latency at n = 1024, nrhs = 1 (A = G G^T/n + I)."""
+    from paper_2601_14466_amd import _lib
+    A0 = synth.torch_gram_spd(n, seed)
+    xt = synth.torch_normal((n, 1), seed + 1)
+    B0 = (A0 @ xt).T.contiguous()
+    A, B = A0.clone(), B0.clone()
+    info = torch.zeros((), dtype=torch.int32, device=A.device)
+    h = mg.handle()
+    h.set_block_size(0)
+    wb = ctypes.c_size_t()
+    _lib.call("mg_potrs_buffer_size", h.h, _lib.MG_F64, n, 1, ctypes.byref(wb))
+    work = torch.empty(max(1, wb.value), dtype=torch.uint8, device=A.device)
+    times = []
+    for r in range(reps + 3):
+        A.copy_(A0)
+        B.copy_(B0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _lib.call("mg_posv", h.sync_stream(), _lib.MG_F64, n, 1, _p(A), n, _p(B), n, _p(work), wb.value, _p(info))
+        e1.record()
+        torch.cuda.synchronize()
+        if r >= 3:
+            times.append(e0.elapsed_time(e1))
+    ms = _median(times)
+    return dict(n=n, nrhs=1, us=round(ms * 1e3, 1), tflops=round(nominal_flops(n, 1) / (ms / 1e3) / 1e12, 3),
+                info=int(info))
+
+
+def bench_batched(torch, mg, synth, dtype, reps: int = 10, seed: int = 2026):
+    """4096 SPD systems, n_i uniform on [16, 512], nrhs = 1, A_i = G_i G_i^T/n_i + I,
+    solved by one graph-replayed persistent launch; A_i restored outside the
+    timed region before every replay."""
+    import numpy as np
+    sizes = [int(v) for v in synth.batch_sizes(4096, seed)]
+    dev = torch.device("cuda", 0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed + 1)
+    offs = np.concatenate([[0], np.cumsum([k * k for k in sizes])])
+    boffs = np.concatenate([[0], np.cumsum(sizes)])
+    A0 = torch.empty(int(offs[-1]), dtype=torch.float64, device=dev)
+    B0 = torch.empty(int(boffs[-1]), dtype=torch.float64, device=dev)
+    for k, nk in enumerate(sizes):
+        G = torch.randn((nk, nk), generator=gen, device=dev, dtype=torch.float64)
+        Ak = G @ G.T / nk + torch.eye(nk, device=dev, dtype=torch.float64)
+        Ak = torch.tril(Ak) + torch.tril(Ak, -1).T
+        xk = torch.randn((nk,), generator=gen, device=dev, dtype=torch.float64)
+        A0[int(offs[k]):int(offs[k + 1])] = Ak.reshape(-1)
+        B0[int(boffs[k]):int(boffs[k + 1])] = Ak @ xk
+    A0 = A0.to(dtype)
+    B0 = B0.to(dtype)
+    A, B = A0.clone(), B0.clone()
+    es = A.element_size()
+    ap = torch.tensor([A.data_ptr() + int(o) * es for o in offs[:-1]], dtype=torch.int64, device=dev)
+    bp = torch.tensor([B.data_ptr() + int(o) * es for o in boffs[:-1]], dtype=torch.int64, device=dev)
+    ld = torch.tensor(sizes, dtype=torch.int64, device=dev)
+    info = torch.zeros(len(sizes), dtype=torch.int32, device=dev)
+    plan = mg.BatchPlan(sizes, nrhs=1, dtype=dtype, autotune=True)
+    times = []
+    for r in range(reps + 2):
+        A.copy_(A0)
+        B.copy_(B0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.solve_raw(ap, ld, bp, ld, info)
+        e1.record()
+        torch.cuda.synchronize()
+        if r >= 2:
+            times.append(e0.elapsed_time(e1))
+    ms = _median(times)
+    flops = sum(nominal_flops(k, 1) for k in sizes)
+    out = dict(dtype="f64" if dtype == torch.float64 else "f32", batch=len(sizes), ms=round(ms, 4),
+               systems_per_s=round(len(sizes) / (ms / 1e3), 1), tflops=round(flops / (ms / 1e3) / 1e12, 3),
+               info_nonzero=int((info != 0).sum()), plan=plan.info())
+    del plan, A, B, A0, B0
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_adjoint(torch, mg, synth, n: int = 8192, nrhs: int = 64, reps: int = 5, seed: int = 8192):
+    """Forward posv and hand-written backward (gB = A^{-1} gX, symmetric gA)
+    at n = 8192, nrhs = 64, A = G G^T/n + I."""
+    from paper_2601_14466_amd import _lib
+    A0 = synth.torch_gram_spd(n, seed)
+    Bc0 = synth.torch_normal((nrhs, n), seed + 1)      # column-major n x nrhs
+    W = synth.torch_normal((nrhs, n), seed + 2)
+    A, Bc = A0.clone(), Bc0.clone()
+    gB = torch.empty_like(Bc)
+    gA = torch.empty_like(A0)
+    info = torch.zeros((), dtype=torch.int32, device=A.device)
+    h = mg.handle()
+    h.set_block_size(0)
+    wb = ctypes.c_size_t()
+    _lib.call("mg_potrs_buffer_size", h.h, _lib.MG_F64, n, nrhs, ctypes.byref(wb))
+    work = torch.empty(max(1, wb.value), dtype=torch.uint8, device=A.device)
+    fw, bw = [], []
+    for r in range(reps + 1):
+        A.copy_(A0)
+        Bc.copy_(Bc0)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        _lib.call("mg_posv", h.sync_stream(), _lib.MG_F64, n, nrhs, _p(A), n, _p(Bc), n, _p(work), wb.value, _p(info))
+        ev[1].record()
+        _lib.call("mg_posv_backward", h.sync_stream(), n, nrhs, _p(A), n, _p(Bc), n, _p(W), n, _p(gB), n, _p(gA), n,
+                  _lib.MG_GRAD_SYM, _p(work), wb.value, _p(info))
+        ev[2].record()
+        torch.cuda.synchronize()
+        if r >= 1:
+            fw.append(ev[0].elapsed_time(ev[1]))
+            bw.append(ev[1].elapsed_time(ev[2]))
+    f, b = _median(fw), _median(bw)
+    bflops = 2.0 * n * n * nrhs + 4.0 * n * n * nrhs
+    return dict(n=n, nrhs=nrhs, forward_ms=round(f, 3), backward_ms=round(b, 3),
+                forward_tflops=round(nominal_flops(n, nrhs) / (f / 1e3) / 1e12, 3),
+                backward_tflops=round(bflops / (b / 1e3) / 1e12, 3), info=int(info))
+
+
 def cpu_baseline(torch, synth, n: int = 8192, nrhs: int = 16, seed: int = 4242):
     import oracle  # CPU oracle: baseline leg only
     A = synth.torch_gram_spd_cond(n, seed, 1e4)
@@ -135,7 +315,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--nrhs", type=int, default=16)
+    ap.add_argument("--nb", type=int, default=0, help="potrf block size (0: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed-precision, batched, adjoint and n=1024 measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}); "
@@ -150,8 +333,22 @@ def main():
     torch.cuda.set_device(0)
     mg.load()
 
-    r = bench_fp64(torch, mg, synth, args.n, args.nrhs, args.steps, args.warmup)
+    r = bench_fp64(torch, mg, synth, args.n, args.nrhs, args.steps, args.warmup, args.nb)
     log(f"[bench] fp64 n={args.n}: {r['ms_step']:.2f} ms/step, {r['tflops']:.2f} TFLOP/s, eta {r['eta_fp64_device']:.2e}")
+    extras = None
+    if not args.no_extras:
+        extras = {}
+        extras["mixed_fp32"] = bench_mixed(torch, mg, synth, args.n, 8, 1e4, "fp32", 3)
+        log(f"[bench] mixed fp32: {extras['mixed_fp32']}")
+        extras["mixed_bf16"] = bench_mixed(torch, mg, synth, args.n, 8, 1e2, "bf16", 3)
+        log(f"[bench] mixed bf16: {extras['mixed_bf16']}")
+        extras["small_n1024"] = bench_small(torch, mg, synth)
+        log(f"[bench] n=1024: {extras['small_n1024']}")
+        for dt, key in ((torch.float64, "batched_f64"), (torch.float32, "batched_f32")):
+            extras[key] = bench_batched(torch, mg, synth, dt)
+            log(f"[bench] {key}: {extras[key]}")
+        extras["adjoint_n8192"] = bench_adjoint(torch, mg, synth)
+        log(f"[bench] adjoint: {extras['adjoint_n8192']}")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
@@ -186,6 +383,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernel_ms": {k: round(v["ms"] / max(1, args.steps), 3) for k, v in r["prof"].items()},
+        "extras": extras,
     }
     print(json.dumps(line), flush=True)
 

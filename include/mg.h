@@ -60,7 +60,9 @@ mg_status mg_destroy(mg_handle_t handle);
 mg_status mg_set_stream(mg_handle_t handle, void *stream);
 
 /* potrf block size nb (the paper's tile size T_A).  0 selects the built-in
- * default for the problem size; otherwise nb must be one of 64, 128, 256.
+ * default for the problem size; otherwise nb must be one of 64, 128, 256,
+ * 512.  With 512 each block column is factored as two halves of 256 and the
+ * trailing matrix receives one rank-512 update per block column.
  * Errors: -1 NULL handle, -2 unsupported nb. */
 mg_status mg_set_block_size(mg_handle_t handle, int64_t nb);
 /* Look-ahead schedule for potrf (default on): the trailing update of step k
@@ -89,7 +91,11 @@ mg_status mg_get_block_size(mg_handle_t handle, mg_dtype dtype, int64_t n, int64
 mg_status mg_potrf(mg_handle_t handle, mg_dtype dtype, int64_t n, void *A, int64_t lda,
                    int32_t *info);
 
-/* Bytes of device workspace mg_potrs / mg_posv need for (dtype, n, nrhs).
+/* Bytes of device workspace mg_potrs / mg_posv need for (dtype, n, nrhs):
+ * the intermediate Y = L^{-1} B (n x nrhs) plus 256 bytes of sweep counters
+ * (0 when n or nrhs is 0).  The library clears the counters itself at the
+ * start of every solve, so the workspace needs no initialisation; two solves
+ * in flight at once must not share one workspace.
  * Errors: -1 NULL handle, -2 bad dtype, -3 n < 0, -4 nrhs < 0, -5 NULL out. */
 mg_status mg_potrs_buffer_size(mg_handle_t handle, mg_dtype dtype, int64_t n, int64_t nrhs,
                                size_t *bytes);
@@ -97,7 +103,9 @@ mg_status mg_potrs_buffer_size(mg_handle_t handle, mg_dtype dtype, int64_t n, in
 /*
  * potrs: X = A^{-1} B from the factor L of mg_potrf: forward substitution
  * L Y = B, then back substitution L^T X = Y (paper: "Software design",
- * potrs bullet; b is N x N_RHS).
+ * potrs bullet; b is N x N_RHS).  Each sweep is one persistent launch whose
+ * workgroups take 64-row blocks in order and wait (boundedly) for the blocks
+ * they depend on.
  *   L      device, lda x n, the factor in its lower triangle (strict upper
  *          never read).
  *   B      device, ldb x nrhs, overwritten with X.

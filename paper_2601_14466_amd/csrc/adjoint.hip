@@ -12,8 +12,9 @@
 //                   for i > j, -(gB X^T)(i,i) on the diagonal; the strict
 //                   upper triangle of gA is not written.
 // The rank-2 nrhs product runs on the FP64 matrix pipe as one product
-// U V^T with U = [gB | X], V = [X | gB] (n x 2 nrhs each): a 128 x 128 tile per
-// workgroup, 64 x 64 per wave, operands streamed from L1/L2 into registers.
+// U V^T with U = [gB | X], V = [X | gB] (n x 2 nrhs each) over the lower
+// triangle only: a 128 x 128 tile per workgroup, 64 x 64 per wave, operands
+// streamed from L1/L2 into registers; the symmetric form mirrors each value.
 #include <algorithm>
 
 #include "mg_internal.h"
@@ -21,33 +22,28 @@
 
 namespace mg {
 
-// gA tile (I, J): alpha_off * sum_k U(i,k) V(j,k) off the diagonal, alpha_diag on it.
-// lower_only: only tiles with I >= J and entries with i >= j are written.
+// gA tile (I, J), I >= J: alpha_off * sum_k U(i,k) V(j,k) below the diagonal,
+// alpha_diag on it.  Only entries with i >= j are computed into memory; with
+// mirror set each strictly-lower value is also written to (j, i), so the
+// symmetric result is exactly symmetric (the two halves of a diagonal tile
+// would otherwise be summed in different orders).
 __global__ __launch_bounds__(256, 2) void k_syr2k_grad(const double* __restrict__ G, int64_t ldg,
                                                        const double* __restrict__ X, int64_t ldx, int64_t n,
                                                        int64_t nrhs, double* __restrict__ GA, int64_t ldga,
-                                                       double alpha_off, double alpha_diag, int lower_only,
+                                                       double alpha_off, double alpha_diag, int mirror,
                                                        const int32_t* info) {
     if (info && *info != 0) return;
     const int64_t T = (n + 127) / 128;
-    int64_t I, J;
-    if (lower_only) {
-        const int64_t t = blockIdx.x;
-        if (t >= T * (T + 1) / 2) return;
-        int64_t r = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-        while (r * (r + 1) / 2 > t) --r;
-        while ((r + 1) * (r + 2) / 2 <= t) ++r;
-        I = r;
-        J = t - r * (r + 1) / 2;
-    } else {
-        I = blockIdx.x % T;
-        J = blockIdx.x / T;
-        if (J >= T) return;
-    }
+    const int64_t t = blockIdx.x;
+    if (t >= T * (T + 1) / 2) return;
+    int64_t r0 = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (r0 * (r0 + 1) / 2 > t) --r0;
+    while ((r0 + 1) * (r0 + 2) / 2 <= t) ++r0;
+    const int64_t I = r0, J = t - r0 * (r0 + 1) / 2;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, i = l & 15, g = l >> 4;
     const int wr = w >> 1, wc = w & 1;
     const int64_t sr0 = I * 128 + 64 * wr, sc0 = J * 128 + 64 * wc;
-    if (lower_only && sr0 + 63 < sc0) return;
+    if (sr0 + 63 < sc0) return;
     f64x4 acc[4][4];
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
@@ -79,8 +75,11 @@ __global__ __launch_bounds__(256, 2) void k_syr2k_grad(const double* __restrict_
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = sr0 + 16 * bi + i, col = sc0 + 16 * bj + tcol<double>(g, r);
-                if (row < n && col < n && (!lower_only || row >= col))
-                    GA[idx(row, col, ldga)] = (row == col ? alpha_diag : alpha_off) * acc[bi][bj][r];
+                if (row < n && col < n && row >= col) {
+                    const double v = (row == col ? alpha_diag : alpha_off) * acc[bi][bj][r];
+                    GA[idx(row, col, ldga)] = v;
+                    if (mirror && row > col) GA[idx(col, row, ldga)] = v;
+                }
             }
 }
 
@@ -107,10 +106,10 @@ mg_status posv_backward_impl(mg_handle_t h, int64_t n, int64_t nrhs, const doubl
     }
     const int64_t T = cdiv(n, 128);
     const bool lower = mode == MG_GRAD_LOWER;
-    const int64_t grid = lower ? T * (T + 1) / 2 : T * T;
+    const int64_t grid = T * (T + 1) / 2;
     if ((rc = prof_begin(h, MG_PROF_ADJOINT, st))) return rc;
     hipLaunchKernelGGL(k_syr2k_grad, dim3((unsigned)grid), dim3(256), 0, st, GB, ldgb, X, ldx, n, nrhs, GA, ldga,
-                       lower ? -1.0 : -0.5, -0.5, lower ? 1 : 0, info);
+                       lower ? -1.0 : -0.5, -0.5, lower ? 0 : 1, info);
     MG_LAUNCH_CHECK();
     const double nd = (double)n;
     return prof_end(h, MG_PROF_ADJOINT, 2.0 * nd * nd * 2.0 * (double)nrhs,

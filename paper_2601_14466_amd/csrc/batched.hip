@@ -368,7 +368,7 @@ static void cache_store(const char* path, const std::string& key, const PlanCfg&
     if (!path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %.6f\n", key.c_str(), cfg.grid_per_cu, cfg.order, ms);
+    fprintf(f, "%s %d %d %.17g\n", key.c_str(), cfg.grid_per_cu, cfg.order, ms);
     fclose(f);
 }
 

@@ -196,7 +196,7 @@ static MixedWork mixed_layout(int64_t n, int64_t nrhs, int fallback) {
     w.o_aw = take(std::max(nn * 4, fallback ? nn * 8 : (size_t)0));  // FP32 factor, or the FP64 fallback copy
     w.o_r = take((size_t)n * nrhs * 8);
     w.o_d = take((size_t)n * nrhs * 4);
-    w.o_y = take((size_t)n * nrhs * 8);          // potrs workspace (FP32 or FP64 fallback)
+    w.o_y = take(potrs_work_bytes(n, nrhs, 8));  // potrs workspace (FP32 or FP64 fallback)
     w.o_cm = take((size_t)(3 * nrhs + 1) * 8);
     w.o_an = take(8);
     w.o_eta = take((size_t)std::max<int64_t>(nrhs, 1) * 8);

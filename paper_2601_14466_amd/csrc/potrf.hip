@@ -6,8 +6,8 @@
 //   1. k_factor_block : L_kk = chol(A_kk), one workgroup, FP64 arithmetic.
 //   2. k_trsm_panel   : L_ik = A_ik L_kk^{-T} for the m = n - (k+1) nb rows
 //                       below, one wave per 16 rows, MFMA + shuffle solves.
-//   3. k_syrk_lower   : lower(A_22) -= L_ik L_ik^T, MFMA with LDS-staged
-//                       128 x 128 tiles (about n^3/3 of the n^3/3 + O(n^2) flops).
+//   3. k_syrk_lower   : lower(A_22) -= L_ik L_ik^T, FP64 MFMA on 128 x 128
+//                       tiles (about n^3/3 of the n^3/3 + O(n^2) flops).
 #include <algorithm>
 #include <cmath>
 
@@ -217,25 +217,25 @@ __global__ __launch_bounds__(256) void k_trsm_panel(S* __restrict__ P, const S* 
 }
 
 // ---------------------------------------------------------------------------
-// Trailing update lower(C) -= P P^T, C m x m, P m x kdim (kdim % 8 == 0),
+// Trailing update lower(C) -= P P^T, C m x m, P m x kdim (kdim % 16 == 0),
 // restricted to the 128 x 128 lower tiles of tile columns [j0, j0 + wj).
 // A workgroup owns one tile; each of its four waves owns a 64 x 64 quarter
 // (4 x 4 MFMA tiles, 64 accumulators per lane) and streams its own operand
-// rows of P from L1/L2 straight into registers, two k-steps ahead of the
-// MFMAs.  There is no LDS staging and no barrier: waves never wait for each
-// other, and two waves per SIMD keep the matrix pipe busy while the other
-// waits on memory (measured faster on gfx950 than an LDS-staged, barrier-
-// synchronised version of the same tile).  The accumulators start from C
-// (entries above the diagonal of a diagonal tile are never read) and the
-// MFMAs subtract by negating one operand, so the epilogue is a plain store.
-// Quarters entirely above the diagonal exit at once.  With bf16 set (binary32
-// storage only) each operand is rounded to bfloat16 as it is loaded, so the
-// products are those of bfloat16 inputs accumulated in FP32.  Tile order is XCD-
-// aware: workgroup b runs on XCD b % 8, and each XCD receives a contiguous
-// run of row-major tiles so that the panel rows they share stay in its L2.
+// rows of P from L1/L2 straight into registers through buffer loads (scalar
+// resource + 32-bit lane offsets), three k-steps ahead of the MFMAs in a
+// four-slot register ring.  There is no LDS staging and no barrier: waves
+// never wait for each other, and two waves per SIMD keep the matrix pipe
+// busy while the other waits on memory.  When kdim % 256 == 0 the C tile is
+// not loaded up front: its 16 x 16 pieces are fetched one at a time during
+// the k-loop and folded into the accumulators, so C's HBM reads overlap the
+// MFMAs.  Quarters entirely above the diagonal exit at once.  With bf16 set
+// (binary32 storage only) each operand is rounded to bfloat16 before its
+// MFMA, so the products are those of bfloat16 inputs accumulated in FP32.
+// Tile order is XCD-aware: workgroup b runs on XCD b % 8, and each XCD
+// receives a contiguous run of row-major tiles so that the panel rows they
+// share stay in its L2.
 // ---------------------------------------------------------------------------
 constexpr int SY_BM = 128;
-constexpr int SY_PF = 2;   // k-steps of operands in flight ahead of the MFMAs
 
 __host__ __device__ __forceinline__ void lower_tile_coords(int64_t t, int64_t& I, int64_t& J) {
     int64_t r = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -277,7 +277,28 @@ __device__ __forceinline__ float round_bf16(float x) {
 __device__ __forceinline__ double lo_round(double x, int) { return x; }
 __device__ __forceinline__ float lo_round(float x, int bf16) { return bf16 ? round_bf16(x) : x; }
 
-template <typename S>
+// Raw buffer access: a 128-bit resource (base, byte extent) that the compiler
+// keeps in scalar registers, plus a 32-bit per-lane byte offset.  Loads at or
+// beyond the extent return 0 instead of touching memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, int64_t bytes) {
+    const int nr = (int)(bytes < 0 ? 0 : (bytes > 0x7fffffff ? 0x7fffffff : bytes));
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, nr, 0x00020000);
+}
+__device__ __forceinline__ double buf_ld(double*, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ float buf_ld(float*, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_st(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
+template <typename S, bool FOLD>
 __global__ __launch_bounds__(256, 2) void k_syrk_lower(S* __restrict__ Cm, const S* __restrict__ P,
                                                        int64_t lda, int64_t m, int kdim, int64_t j0, int64_t wj,
                                                        int bf16, const int32_t* info) {
@@ -289,71 +310,111 @@ __global__ __launch_bounds__(256, 2) void k_syrk_lower(S* __restrict__ Cm, const
     if (t >= ntiles) return;
     int64_t I, J;
     slab_tile_coords(t, j0, wj, I, J);
-    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, i = l & 15, g = l >> 4;
+    constexpr int ES = (int)sizeof(S);
+    const int tid = threadIdx.x, l = tid & 63, i = l & 15, g = l >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = w >> 1, wc = w & 1;
     const int64_t sr0 = I * SY_BM + 64 * wr, sc0 = J * SY_BM + 64 * wc;
-    if (sr0 + 63 < sc0) return;  // quarter strictly above the diagonal
+    // quarters above the diagonal or past the block's edge hold no output
+    if (sr0 + 63 < sc0 || sr0 >= m || sc0 >= m) return;
+    const int ld = (int)lda;  // the host keeps every byte offset below 2^31
+    const int rmax = (int)(m - 1 - sr0 < 63 ? m - 1 - sr0 : 63);
+    const int cmax = (int)(m - 1 - sc0 < 63 ? m - 1 - sc0 : 63);
+    const int dd = (int)(sr0 - sc0 < 64 ? sr0 - sc0 : 64);  // >= 64: no entry of the quarter is above the diagonal
+    // C quarter at (sr0, sc0).  Local row / column indices are clamped into
+    // the block, so every load stays inside it (entries of a diagonal
+    // quarter above the diagonal are read and discarded); stores are masked.
+    const __amdgpu_buffer_rsrc_t crs = buf_rsrc(Cm + idx(sr0, sc0, lda), 0x7fffffff);
+    auto c_in = [&](int bi, int bj, int r) {
+        const int rr = 16 * bi + i, cc = 16 * bj + tcol<S>(g, r);
+        return rr <= rmax && cc <= cmax && rr + dd >= cc;
+    };
+    auto c_off = [&](int bi, int bj, int r) {
+        const int rr = min(16 * bi + i, rmax), cc = min(16 * bj + tcol<S>(g, r), cmax);
+        return (rr + cc * ld) * ES;
+    };
+    auto c_load = [&](int bi, int bj, int r) -> S {
+        const S v = buf_ld((S*)nullptr, crs, c_off(bi, bj, r), 0);
+        return c_in(bi, bj, r) ? v : (S)0;
+    };
+    // The accumulators hold P P^T - C: products are added with their own
+    // sign and the result is negated as it is stored (round-to-nearest is
+    // symmetric, so this equals C - P P^T accumulated in the same order).
     V4<S> acc[4][4];
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = sr0 + 16 * bi + i, col = sc0 + 16 * bj + tcol<S>(g, r);
-                acc[bi][bj][r] = (row < m && col < m && row >= col) ? Cm[idx(row, col, lda)] : (S)0;
-            }
-    // operand rows: x from the quarter's rows, z from its columns; rows >= m
-    // read row 0 instead (finite values that only reach outputs never stored)
-    const S* pa[4];
-    const S* pb[4];
+            for (int r = 0; r < 4; ++r) acc[bi][bj][r] = FOLD ? (S)0 : -c_load(bi, bj, r);
+    // Operands: panel rows sr0 + 16 b + i (x) and sc0 + 16 b + i (z) of
+    // column 4 kn + g; rows past the block are clamped to its last row
+    // (they only feed outputs that are never stored).
+    const __amdgpu_buffer_rsrc_t prs = buf_rsrc(P, 0x7fffffff);
+    int xo[4], zo[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        const int64_t ra = sr0 + 16 * b + i, rb = sc0 + 16 * b + i;
-        pa[b] = P + (ra < m ? ra : 0) + (int64_t)g * lda;
-        pb[b] = P + (rb < m ? rb : 0) + (int64_t)g * lda;
+        xo[b] = ((int)sr0 + min(16 * b + i, rmax) + g * ld) * ES;
+        zo[b] = ((int)sc0 + min(16 * b + i, cmax) + g * ld) * ES;
     }
     const int nks = kdim / 4;
-    S xq[SY_PF][4], zq[SY_PF][4];
-#pragma unroll
-    for (int s = 0; s < SY_PF; ++s)
+    // ring of four k-steps of operands; step kn lives in slot kn % 4 and is
+    // fetched three steps before its MFMAs
+    S xq[4][4], zq[4][4];
+    auto fetch = [&](int slot, int kn) {
+        const int soff = (kn < nks ? kn : nks - 1) * 4 * ld * ES;  // steps past the end re-read the last one
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            xq[s][b] = lo_round(pa[b][(int64_t)(4 * s) * lda], bf16);
-            zq[s][b] = -lo_round(pb[b][(int64_t)(4 * s) * lda], bf16);
+            xq[slot][b] = buf_ld((S*)nullptr, prs, xo[b], soff);
+            zq[slot][b] = buf_ld((S*)nullptr, prs, zo[b], soff);
         }
-    for (int ks = 0; ks < nks; ks += SY_PF) {
+    };
+    fetch(0, 0);
+    fetch(1, 1);
+    fetch(2, 2);
+    // k-steps ks .. ks + 3 (ks % 4 == 0)
+    auto body = [&](int ks) {
 #pragma unroll
-        for (int s = 0; s < SY_PF; ++s) {
+        for (int s = 0; s < 4; ++s) {
+            fetch((s + 3) & 3, ks + s + 3);
             S xv[4], zv[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                xv[b] = xq[s][b];
-                zv[b] = zq[s][b];
-            }
-            const int kn = ks + s + SY_PF;
-            if (kn < nks) {
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    xq[s][b] = lo_round(pa[b][(int64_t)(4 * kn) * lda], bf16);
-                    zq[s][b] = -lo_round(pb[b][(int64_t)(4 * kn) * lda], bf16);
-                }
+                xv[b] = lo_round(xq[s][b], bf16);
+                zv[b] = lo_round(zq[s][b], bf16);
             }
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
                 for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mma_xzt(acc[bi][bj], xv[bi], zv[bj]);
         }
+    };
+    if constexpr (FOLD) {
+        // C is folded in one 16 x 16 tile at a time, spread over the k-loop:
+        // the load of tile q is issued, nks / 16 k-steps of MFMAs run, then
+        // it is subtracted.  C's HBM traffic thus overlaps the matrix pipe
+        // instead of forming a prologue that every resident workgroup issues
+        // at once.
+        const int per_q = nks / 64;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            V4<S> cv;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cv[r] = c_load(q >> 2, q & 3, r);
+            for (int u = 0; u < per_q; ++u) body((q * per_q + u) * 4);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[q >> 2][q & 3][r] -= cv[r];
+        }
+    } else {
+        for (int ks = 0; ks < nks; ks += 4) body(ks);
     }
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = sr0 + 16 * bi + i, col = sc0 + 16 * bj + tcol<S>(g, r);
-                if (row < m && col < m && row >= col) Cm[idx(row, col, lda)] = acc[bi][bj][r];
-            }
+            for (int r = 0; r < 4; ++r)
+                if (c_in(bi, bj, r)) buf_st(-acc[bi][bj][r], crs, c_off(bi, bj, r), 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -389,8 +450,16 @@ mg_status syrk_lower_launch(hipStream_t st, S* Cm, const S* P, int64_t lda, int6
     if (j0 >= T || wj <= 0) return MG_OK;
     const int64_t ntiles = slab_tiles(T, j0, wj);
     const int64_t grid = 8 * cdiv(ntiles, 8);
-    hipLaunchKernelGGL((k_syrk_lower<S>), dim3((unsigned)grid), dim3(256), 0, st, Cm, P, lda, m, (int)kdim, j0,
-                       wj, bf16, info);
+    // every byte offset the kernel forms from P or from a quarter's corner
+    // must fit in 31 bits
+    if ((m + (kdim + 64) * lda) * (int64_t)sizeof(S) >= ((int64_t)1 << 31) - 65536 || kdim % 16 != 0)
+        return MG_ERR_UNSUPPORTED;
+    if (kdim % 256 == 0)
+        hipLaunchKernelGGL((k_syrk_lower<S, true>), dim3((unsigned)grid), dim3(256), 0, st, Cm, P, lda, m, (int)kdim,
+                           j0, wj, bf16, info);
+    else
+        hipLaunchKernelGGL((k_syrk_lower<S, false>), dim3((unsigned)grid), dim3(256), 0, st, Cm, P, lda, m,
+                           (int)kdim, j0, wj, bf16, info);
     MG_LAUNCH_CHECK();
     return MG_OK;
 }
@@ -412,6 +481,30 @@ static mg_status panel_step(mg_handle_t h, hipStream_t st, T* A, int64_t lda, in
     if ((rc = prof_begin(h, MG_PROF_TRSM, st))) return rc;
     if ((rc = launch_trsm<T>(st, nb, A + idx(k0 + kb, k0, lda), Akk, lda, m, info))) return rc;
     return prof_end(h, MG_PROF_TRSM, (double)m * b * b, 2.0 * m * b * sizeof(T), st);
+}
+
+template <typename T>
+static mg_status trailing(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int64_t n, int64_t k0, int64_t nb,
+                         const int32_t* info, int64_t j0, int64_t wj);
+
+// Block column [k0, k0 + nb) factored completely (diagonal block and the
+// panel below it).  For nb <= 256 this is one panel_step; for nb = 512 the
+// column is itself factored right-looking in two halves of 256: the second
+// half's columns receive the first half's update (a 256-wide slab of the
+// trailing update) before their own panel step.  The caller then applies
+// the whole 512-wide panel to the trailing matrix in one rank-512 update,
+// which halves the passes over the trailing matrix's HBM-resident entries.
+template <typename T>
+static mg_status panel_block(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int64_t n, int64_t k0, int64_t nb,
+                             int32_t* info) {
+    const int64_t nbi = std::min<int64_t>(nb, FB_MAX), end = std::min(n, k0 + nb);
+    mg_status rc;
+    for (int64_t k1 = k0; k1 < end; k1 += nbi) {
+        if ((rc = panel_step<T>(h, st, A, lda, n, k1, nbi, info))) return rc;
+        const int64_t rest = end - (k1 + nbi);
+        if (rest > 0 && (rc = trailing<T>(h, st, A, lda, n, k1, nbi, info, 0, cdiv(rest, SY_BM)))) return rc;
+    }
+    return MG_OK;
 }
 
 template <typename T>
@@ -453,7 +546,7 @@ mg_status potrf_impl(mg_handle_t h, int64_t n, T* A, int64_t lda, int32_t* info)
     const int64_t wnext = nb / SY_BM;  // tile columns in the next block column
     if (!h->lookahead || nsteps < 3 || nb % SY_BM != 0) {
         for (int64_t k0 = 0; k0 < n; k0 += nb) {
-            if ((rc = panel_step<T>(h, st, A, lda, n, k0, nb, info))) return rc;
+            if ((rc = panel_block<T>(h, st, A, lda, n, k0, nb, info))) return rc;
             if ((rc = trailing<T>(h, st, A, lda, n, k0, nb, info, 0, -1))) return rc;
         }
         return MG_OK;
@@ -469,14 +562,14 @@ mg_status potrf_impl(mg_handle_t h, int64_t n, T* A, int64_t lda, int32_t* info)
     if ((rc = ensure_side(h))) return rc;
     MG_HIP(hipEventRecord(h->ev_fork, st));
     MG_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-    if ((rc = panel_step<T>(h, st, A, lda, n, 0, nb, info))) return rc;
+    if ((rc = panel_block<T>(h, st, A, lda, n, 0, nb, info))) return rc;
     for (int64_t k = 0; k + 1 < nsteps; ++k) {
         const int64_t k0 = k * nb;
         if ((rc = trailing<T>(h, st, A, lda, n, k0, nb, info, 0, wnext))) return rc;
         MG_HIP(hipEventRecord(h->ev_panel, st));             // panel k applied to block column k+1
         MG_HIP(hipStreamWaitEvent(h->side, h->ev_panel, 0));
         if ((rc = trailing<T>(h, h->side, A, lda, n, k0, nb, info, wnext, -1))) return rc;
-        if ((rc = panel_step<T>(h, st, A, lda, n, k0 + nb, nb, info))) return rc;
+        if ((rc = panel_block<T>(h, st, A, lda, n, k0 + nb, nb, info))) return rc;
         MG_HIP(hipEventRecord(h->ev_rest, h->side));         // rest(k) done
         MG_HIP(hipStreamWaitEvent(st, h->ev_rest, 0));
     }

@@ -1,25 +1,30 @@
 // potrs.hip -- X = A^{-1} B from the Cholesky factor: L Y = B, then L^T X = Y.
 // Paper: JAXMg "Software design", potrs bullet (b is N x N_RHS).
 //
-// Both sweeps are blocked by JB = 64 rows and take one launch per block,
-// right-looking, so each launch is parallel over the rows it updates:
-//   forward step j : every workgroup solves L_jj Y_j = B_j, workgroup 0 keeps
-//                    Y_j in the workspace, and every workgroup applies
-//                    B_i -= L_ij Y_j to its own 64 rows below the block.
-//   backward step j: every workgroup solves L_jj^T X_j = Y_j, workgroup 0
-//                    stores X_j into B, and every workgroup applies
-//                    Y_i -= L_ji^T X_j to its own 64 rows above the block.
-// The diagonal solve is a substitution in registers: a lane per row, the four
-// waves splitting the right-hand sides, each step's pivot row broadcast by
-// the scalar unit (readlane).  L_jj is staged pre-scaled by its pivots
-// (column c divided by L_cc for the forward sweep, row c for the backward one,
-// diagonal set to 0), so a step is one readlane and one FMA per value and the
-// division by the pivot happens once per value at the end.  Integer data with
-// power-of-two pivots stays exact under this scaling.
-// The 64 x 64 block of L that a workgroup applies is staged through LDS with
-// all of its global loads in flight together (column-contiguous for both
-// sweeps).  Each sweep reads the lower triangle once: HBM-bound, arithmetic
-// intensity nrhs/4 flop per byte in FP64.
+// Each triangular sweep is ONE launch of a persistent kernel over blocks of
+// JB = 64 rows.  A workgroup takes the next block from an atomic ticket (the
+// forward sweep hands out blocks top-down, the backward sweep bottom-up), so a
+// block only ever waits for blocks whose workgroups are already running, and
+// blocks complete strictly in ticket order: block t can finish only after
+// block t - 1.  One counter per sweep therefore says how many blocks are
+// final; a workgroup polls it with acquire loads and publishes its own block
+// with a release store.  Inside a workgroup:
+//   * the four waves split the finished blocks j (j = w, w + 4, ...), each
+//     streaming its rows of L straight from memory (one lane per row of the
+//     block: L(i, j) for the forward sweep, read down a column of L for the
+//     backward sweep, where L(j, i) is the transposed block) and applying
+//     acc -= L_ij X_j with the block's solution broadcast by the scalar unit;
+//   * the four partial sums are added in a fixed order through LDS;
+//   * wave 0 solves the diagonal block by substitution in registers (a lane per
+//     row, each step's pivot row broadcast by readlane), with L_ii staged in
+//     LDS pre-scaled by its pivots (column c divided by L_cc for the forward
+//     sweep, row c for the backward one, diagonal 0) so a step is one FMA per
+//     value and the division by the pivot happens once at the end (integer
+//     data with power-of-two pivots stays exact).
+// Every wait is bounded: a counter that does not advance within the spin
+// limit sets an error word in the workspace and the kernel drains.  Each sweep
+// reads the lower triangle once (HBM-bound, nrhs/4 flop per byte in FP64); the
+// chain of block solves is the latency floor.
 #include <algorithm>
 
 #include "mg_internal.h"
@@ -27,17 +32,32 @@
 
 namespace mg {
 
-constexpr int JB = 64;       // rows per block step
+constexpr int JB = 64;       // rows per block
 constexpr int LDP = JB + 1;  // LDS leading dimension (bank spread)
+constexpr int SWEEP_SPIN_LIMIT = 1 << 22;
+
+// Per-sweep synchronisation words, kept in the workspace after Y.
+struct SweepSync {
+    int done;    // blocks final so far (in ticket order)
+    int ticket;  // next block to hand out
+    int err;     // set when a bounded wait gives up
+    int pad;
+};
+
+static size_t y_bytes(int64_t n, int64_t nrhs, int es) { return align_up((size_t)n * (size_t)nrhs * es, 256); }
 
 size_t potrs_work_bytes(int64_t n, int64_t nrhs, int es) {
-    return (size_t)n * (size_t)nrhs * (size_t)es;
+    return (n == 0 || nrhs == 0) ? 0 : y_bytes(n, nrhs, es) + 256;
+}
+
+__global__ void k_sweep_init(SweepSync* s) {
+    if (threadIdx.x < 2) s[threadIdx.x] = SweepSync{0, 0, 0, 0};
 }
 
 // L_jj (jb x jb lower, identity-padded to 64 x 64) into Ls[r*LDP + c] scaled
 // by its pivots: by column (Ls(r,c) = L(r,c)/L(c,c)) when by_row is false,
 // by row (Ls(r,c) = L(r,c)/L(r,r)) when it is true; the diagonal of Ls is 0
-// and piv holds L(c,c).
+// and piv holds L(c,c).  All 256 threads take part.
 template <typename T, bool by_row>
 __device__ __forceinline__ void stage_diag(T* Ls, T* piv, const T* L, int64_t lda, int64_t j0, int jb) {
     const int tid = threadIdx.x;
@@ -58,167 +78,150 @@ __device__ __forceinline__ void stage_diag(T* Ls, T* piv, const T* L, int64_t ld
     }
 }
 
-// Lt[rr*LDP + c] = L(rbase + rr, cbase + c) when transpose == false (panel
-// rows), or L(cbase + c, rbase + rr) when transpose == true (the block row of
-// L read as L^T); out-of-range entries are 0.
-template <typename T, bool transpose>
-__device__ __forceinline__ void stage_panel(T* Lt, const T* L, int64_t lda, int64_t rbase, int64_t rlim,
-                                            int64_t cbase, int clim) {
-    const int tid = threadIdx.x;
-    T v[JB * JB / 256];
-#pragma unroll
-    for (int q = 0; q < JB * JB / 256; ++q) {
-        const int e = tid + 256 * q;
-        // consecutive threads walk the contiguous direction of the column-major source
-        const int a = e & (JB - 1), b = e >> 6;
-        const int rr = transpose ? b : a, c = transpose ? a : b;
-        const bool ok = rbase + rr < rlim && c < clim;
-        v[q] = ok ? (transpose ? L[idx(cbase + c, rbase + rr, lda)] : L[idx(rbase + rr, cbase + c, lda)]) : (T)0;
-    }
-#pragma unroll
-    for (int q = 0; q < JB * JB / 256; ++q) {
-        const int e = tid + 256 * q;
-        const int a = e & (JB - 1), b = e >> 6;
-        const int rr = transpose ? b : a, c = transpose ? a : b;
-        Lt[rr * LDP + c] = v[q];
-    }
+// Cross-workgroup traffic of the sweeps (the counter and the solution blocks)
+// uses device-coherent loads and stores, which bypass the per-XCD caches, so
+// no cache invalidation or write-back fence is needed: a block's values are
+// stored coherently, the storing wave waits for those stores to complete,
+// and only then is the counter advanced.  A reader issues its loads of a
+// block only after it has seen the counter pass that block.
+__device__ __forceinline__ int load_coherent(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T load_coherent(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void store_coherent(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Forward step j.  RPT right-hand sides per wave, 4*RPT per pass.
-template <typename T, int RPT>
-__global__ __launch_bounds__(256) void k_trsv_fwd(const T* __restrict__ L, int64_t lda, int64_t n, int64_t nrhs,
-                                                  T* __restrict__ B, int64_t ldb, T* __restrict__ Y, int64_t ldy,
-                                                  int64_t j0, int jb, const int32_t* info) {
-    constexpr int RCH = 4 * RPT;
+// Forward (FWD): Out = L^{-1} In.  Backward: Out = L^{-T} In.  In and Out are
+// n x nrhs column-major; 16 RT right-hand sides per pass.
+template <typename T, int RT, bool FWD>
+__global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t lda, int64_t n, int64_t nrhs,
+                                               const T* __restrict__ In, int64_t ldi, T* Out, int64_t ldo,
+                                               SweepSync* sy, const int32_t* info) {
+    constexpr int NR = 16 * RT, XP = NR + 1, QW = NR / 4;
     __shared__ T Ls[JB * LDP];
-    __shared__ T Lp[JB * LDP];
     __shared__ T piv[JB];
-    __shared__ T Ys[JB * RCH];
+    __shared__ T Xs[2][JB * XP];
+    __shared__ T part[JB * XP];
+    __shared__ int s_t;
     if (info && *info != 0) return;
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int64_t row0 = j0 + jb + (int64_t)blockIdx.x * JB;
-    const bool have_rows = row0 < n;
-    stage_diag<T, false>(Ls, piv, L, lda, j0, jb);
-    if (have_rows) stage_panel<T, false>(Lp, L, lda, row0, n, j0, jb);
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, i = lane & 15, g = lane >> 4;
+    if (tid == 0) s_t = atomicAdd(&sy->ticket, 1);
     __syncthreads();
-    const T pl = piv[lane];
-    const int64_t row = row0 + lane;
-    for (int64_t rc0 = 0; rc0 < nrhs; rc0 += RCH) {
-        const int cb = (int)rc0 + RPT * w;  // first right-hand side of this wave
-        // ---- diagonal solve L_jj y = b for the wave's RPT columns
-        T v[RPT];
+    const int t = s_t;
+    const int nblk = (int)((n + JB - 1) / JB);
+    if (t >= nblk) return;
+    const int bi = FWD ? t : nblk - 1 - t;
+    const int64_t r0 = (int64_t)bi * JB;
+    const int jb = (int)(n - r0 < JB ? n - r0 : JB);
+    stage_diag<T, !FWD>(Ls, piv, L, lda, r0, jb);
+    // MFMA phase: wave w owns rows 16 w .. 16 w + 15 of the block
+    const int64_t rwc = (16 * w + i < jb) ? r0 + 16 * w + i : r0;  // clamped for loads
+    // blocks this one depends on: j < bi (forward) or j > bi (backward); the
+    // d-th of them in completion order is final once done > d
+    const int ndep = FWD ? bi : nblk - 1 - bi;
+    int ready = 0;
+    bool abort = false;
+    for (int64_t rc0 = 0; rc0 < nrhs; rc0 += NR) {
+        V4<T> acc[RT];
 #pragma unroll
-        for (int r = 0; r < RPT; ++r)
-            v[r] = (lane < jb && cb + r < nrhs) ? B[idx(j0 + lane, cb + r, ldb)] : (T)0;
-#pragma unroll 8
-        for (int c = 0; c < JB; ++c) {
-            const T lic = Ls[lane * LDP + c];   // L(lane,c)/L(c,c), 0 unless lane > c
+        for (int rt = 0; rt < RT; ++rt) acc[rt] = V4<T>{0, 0, 0, 0};
+        for (int d = 0; d < ndep; ++d) {
+            if (ready <= d && !abort) {
+                int spins = 0;
+                while ((ready = load_coherent(&sy->done)) <= d) {
+                    if (++spins > SWEEP_SPIN_LIMIT || load_coherent(&sy->err)) {
+                        abort = true;
+                        if (lane == 0) atomicExch(&sy->err, 1);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            }
+            const int j = FWD ? d : nblk - 1 - d;
+            const int64_t c0 = (int64_t)j * JB;
+            const int jbj = (int)(n - c0 < JB ? n - c0 : JB);
+            // the finished block X_j (jbj x NR) into LDS; consecutive threads
+            // walk its rows, the contiguous direction
+            T* xs = Xs[d & 1];
+            for (int e = tid; e < JB * NR; e += 256) {
+                const int c = e & (JB - 1), q = e >> 6;
+                xs[c * XP + q] = (c < jbj && rc0 + q < nrhs) ? load_coherent(&Out[idx(c0 + c, rc0 + q, ldo)]) : (T)0;
+            }
+            __syncthreads();
+            // acc += L_ij X_j (forward) or L_ji^T X_j (backward), 16 k-steps
+#pragma unroll 4
+            for (int ks = 0; ks < JB / 4; ++ks) {
+                const int c = 4 * ks + g;
+                const T x = (c < jbj) ? (FWD ? L[idx(rwc, c0 + c, lda)] : L[idx(c0 + c, rwc, lda)]) : (T)0;
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) v[r] = v[r] - lic * readlane(v[r], c);
+                for (int rt = 0; rt < RT; ++rt) acc[rt] = mma_xzt(acc[rt], x, xs[c * XP + 16 * rt + i]);
+            }
         }
+        // partial products to LDS, one row per entry: lane (i, g) holds rows
+        // 16 w + i, right-hand sides 16 rt + tcol(g, r)
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            v[r] = v[r] / pl;
-            Ys[lane * RCH + RPT * w + r] = v[r];
-            if (blockIdx.x == 0 && lane < jb && cb + r < nrhs) Y[idx(j0 + lane, cb + r, ldy)] = v[r];
-        }
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part[(16 * w + i) * XP + 16 * rt + tcol<T>(g, r)] = acc[rt][r];
         __syncthreads();
-        // ---- B_i -= L_ij Y_j for the workgroup's 64 rows
-        if (have_rows && row < n) {
-            T acc[RPT];
+        // diagonal block by substitution: a lane per row, wave w takes the
+        // right-hand sides q = w + 4 u
+        {
+            const T pl = piv[lane];
+            T v[QW];
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) acc[r] = (cb + r < nrhs) ? B[idx(row, cb + r, ldb)] : (T)0;
+            for (int u = 0; u < QW; ++u) {
+                const int q = w + 4 * u;
+                v[u] = (lane < jb && rc0 + q < nrhs) ? In[idx(r0 + lane, rc0 + q, ldi)] - part[lane * XP + q] : (T)0;
+            }
+            if (FWD) {
 #pragma unroll 8
-            for (int c = 0; c < JB; ++c) {
-                const T a = Lp[lane * LDP + c];
+                for (int c = 0; c < JB; ++c) {
+                    const T lic = Ls[lane * LDP + c];  // L(lane,c)/L(c,c), 0 unless lane > c
 #pragma unroll
-                for (int r = 0; r < RPT; ++r) acc[r] = acc[r] - a * Ys[c * RCH + RPT * w + r];
+                    for (int u = 0; u < QW; ++u) v[u] = v[u] - lic * readlane(v[u], c);
+                }
+            } else {
+#pragma unroll 8
+                for (int c = JB - 1; c >= 0; --c) {
+                    const T lci = Ls[c * LDP + lane];  // L(c,lane)/L(c,c), 0 unless lane < c
+#pragma unroll
+                    for (int u = 0; u < QW; ++u) v[u] = v[u] - lci * readlane(v[u], c);
+                }
             }
 #pragma unroll
-            for (int r = 0; r < RPT; ++r)
-                if (cb + r < nrhs) B[idx(row, cb + r, ldb)] = acc[r];
-        }
-        __syncthreads();
-    }
-}
-
-// Backward step j.
-template <typename T, int RPT>
-__global__ __launch_bounds__(256) void k_trsv_bwd(const T* __restrict__ L, int64_t lda, int64_t n, int64_t nrhs,
-                                                  T* __restrict__ B, int64_t ldb, T* __restrict__ Y, int64_t ldy,
-                                                  int64_t j0, int jb, const int32_t* info) {
-    constexpr int RCH = 4 * RPT;
-    __shared__ T Ls[JB * LDP];
-    __shared__ T Lt[JB * LDP];
-    __shared__ T piv[JB];
-    __shared__ T Xs[JB * RCH];
-    if (info && *info != 0) return;
-    (void)n;
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int64_t r0 = (int64_t)blockIdx.x * JB;
-    const bool have_rows = r0 < j0;
-    stage_diag<T, true>(Ls, piv, L, lda, j0, jb);
-    if (have_rows) stage_panel<T, true>(Lt, L, lda, r0, j0, j0, jb);
-    __syncthreads();
-    const T pl = piv[lane];
-    const int64_t row = r0 + lane;
-    for (int64_t rc0 = 0; rc0 < nrhs; rc0 += RCH) {
-        const int cb = (int)rc0 + RPT * w;
-        T v[RPT];
-#pragma unroll
-        for (int r = 0; r < RPT; ++r)
-            v[r] = (lane < jb && cb + r < nrhs) ? Y[idx(j0 + lane, cb + r, ldy)] : (T)0;
-#pragma unroll 8
-        for (int c = JB - 1; c >= 0; --c) {
-            const T lci = Ls[c * LDP + lane];  // L(c,lane)/L(c,c), 0 unless lane < c
-#pragma unroll
-            for (int r = 0; r < RPT; ++r) v[r] = v[r] - lci * readlane(v[r], c);
-        }
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            v[r] = v[r] / pl;
-            Xs[lane * RCH + RPT * w + r] = v[r];
-            if (blockIdx.x == 0 && lane < jb && cb + r < nrhs) B[idx(j0 + lane, cb + r, ldb)] = v[r];
-        }
-        __syncthreads();
-        if (have_rows && row < j0) {
-            T acc[RPT];
-#pragma unroll
-            for (int r = 0; r < RPT; ++r) acc[r] = (cb + r < nrhs) ? Y[idx(row, cb + r, ldy)] : (T)0;
-#pragma unroll 8
-            for (int c = 0; c < JB; ++c) {
-                const T a = Lt[lane * LDP + c];
-#pragma unroll
-                for (int r = 0; r < RPT; ++r) acc[r] = acc[r] - a * Xs[c * RCH + RPT * w + r];
+            for (int u = 0; u < QW; ++u) {
+                const int q = w + 4 * u;
+                if (lane < jb && rc0 + q < nrhs) store_coherent(&Out[idx(r0 + lane, rc0 + q, ldo)], v[u] / pl);
             }
-#pragma unroll
-            for (int r = 0; r < RPT; ++r)
-                if (cb + r < nrhs) Y[idx(row, cb + r, ldy)] = acc[r];
         }
-        __syncthreads();
+        __syncthreads();  // part is reused by the next pass
     }
+    // every wave's coherent stores complete before the block is published
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) store_coherent(&sy->done, t + 1);
 }
 
-template <typename T, int RPT>
+template <typename T, int RT>
 static mg_status sweep(hipStream_t st, int64_t n, int64_t nrhs, const T* L, int64_t lda, T* B, int64_t ldb, T* Y,
-                       const int32_t* info) {
-    const int64_t nblk = cdiv(n, JB);
-    for (int64_t jbk = 0; jbk < nblk; ++jbk) {
-        const int64_t j0 = jbk * JB;
-        const int jb = (int)std::min<int64_t>(JB, n - j0);
-        const int64_t grid = std::max<int64_t>(1, cdiv(n - j0 - jb, JB));
-        hipLaunchKernelGGL((k_trsv_fwd<T, RPT>), dim3((unsigned)grid), dim3(256), 0, st, L, lda, n, nrhs, B, ldb, Y,
-                           n, j0, jb, info);
-        MG_LAUNCH_CHECK();
-    }
-    for (int64_t jbk = nblk - 1; jbk >= 0; --jbk) {
-        const int64_t j0 = jbk * JB;
-        const int jb = (int)std::min<int64_t>(JB, n - j0);
-        const int64_t grid = std::max<int64_t>(1, cdiv(j0, JB));
-        hipLaunchKernelGGL((k_trsv_bwd<T, RPT>), dim3((unsigned)grid), dim3(256), 0, st, L, lda, n, nrhs, B, ldb, Y,
-                           n, j0, jb, info);
-        MG_LAUNCH_CHECK();
-    }
+                       SweepSync* sy, const int32_t* info) {
+    const unsigned nblk = (unsigned)cdiv(n, JB);
+    hipLaunchKernelGGL(k_sweep_init, dim3(1), dim3(64), 0, st, sy);
+    MG_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_sweep<T, RT, true>), dim3(nblk), dim3(256), 0, st, L, lda, n, nrhs, (const T*)B, ldb, Y,
+                       n, sy, info);
+    MG_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_sweep<T, RT, false>), dim3(nblk), dim3(256), 0, st, L, lda, n, nrhs, (const T*)Y, n, B,
+                       ldb, sy + 1, info);
+    MG_LAUNCH_CHECK();
     return MG_OK;
 }
 
@@ -229,11 +232,10 @@ mg_status potrs_impl(mg_handle_t h, int64_t n, int64_t nrhs, const T* L, int64_t
     hipStream_t st = h->stream;
     mg_status rc;
     if ((rc = prof_begin(h, MG_PROF_SOLVE, st))) return rc;
-    if (nrhs <= 4) rc = sweep<T, 1>(st, n, nrhs, L, lda, B, ldb, Y, info);
-    else if (nrhs <= 8) rc = sweep<T, 2>(st, n, nrhs, L, lda, B, ldb, Y, info);
-    else if (nrhs <= 16) rc = sweep<T, 4>(st, n, nrhs, L, lda, B, ldb, Y, info);
-    else if (nrhs <= 32) rc = sweep<T, 8>(st, n, nrhs, L, lda, B, ldb, Y, info);
-    else rc = sweep<T, 16>(st, n, nrhs, L, lda, B, ldb, Y, info);
+    SweepSync* sy = (SweepSync*)((char*)Y + y_bytes(n, nrhs, (int)sizeof(T)));
+    if (nrhs <= 16) rc = sweep<T, 1>(st, n, nrhs, L, lda, B, ldb, Y, sy, info);
+    else if (nrhs <= 32) rc = sweep<T, 2>(st, n, nrhs, L, lda, B, ldb, Y, sy, info);
+    else rc = sweep<T, 4>(st, n, nrhs, L, lda, B, ldb, Y, sy, info);
     if (rc) return rc;
     const double nd = (double)n;
     return prof_end(h, MG_PROF_SOLVE, 2.0 * nd * nd * (double)nrhs,

@@ -47,8 +47,8 @@ def _potrf_np(mg, A, nb=None, dtype=torch.float64):
 
 
 # ------------------------------------------------------- integer-exact family
-@pytest.mark.parametrize("nb", [64, 128, 256])
-@pytest.mark.parametrize("n", [1, 7, 16, 17, 63, 64, 65, 100, 255, 256, 257, 300, 520])
+@pytest.mark.parametrize("nb", [64, 128, 256, 512])
+@pytest.mark.parametrize("n", [1, 7, 16, 17, 63, 64, 65, 100, 255, 256, 257, 300, 520, 1100])
 def test_integer_family_bitwise(mg, orc, n, nb):
     L0, A = synth.integer_exact(n, 100 + n)
     L, info = _potrf_np(mg, A, nb)
@@ -61,8 +61,8 @@ def test_integer_family_bitwise(mg, orc, n, nb):
 
 
 # ------------------------------------------------------------ random parity
-@pytest.mark.parametrize("nb", [64, 128, 256])
-@pytest.mark.parametrize("n", [2, 15, 16, 33, 127, 128, 129, 257, 600, 1000])
+@pytest.mark.parametrize("nb", [64, 128, 256, 512])
+@pytest.mark.parametrize("n", [2, 15, 16, 33, 127, 128, 129, 257, 600, 1000, 1537])
 def test_random_spd_parity(mg, orc, n, nb):
     A = synth.gram_spd_cond(n, 3 * n + 1, 1e4) if n > 8 else synth.gram_spd(n, 5)
     xt = synth.normal((n, 5), n)
@@ -129,7 +129,7 @@ def test_paper_benchmark_recipe(mg, orc, n):
 
 
 # -------------------------------------------------- layout and guard bands
-@pytest.mark.parametrize("n,lda,nb", [(70, 77, 64), (300, 301, 128), (513, 520, 256)])
+@pytest.mark.parametrize("n,lda,nb", [(70, 77, 64), (300, 301, 128), (513, 520, 256), (1100, 1111, 512)])
 def test_upper_triangle_and_guard_rows_untouched(mg, orc, n, lda, nb):
     A = synth.gram_spd(n, n)
     M = np.tril(A) + np.triu(np.full((n, n), np.nan), 1)     # poisoned strict upper
@@ -219,7 +219,7 @@ def test_fp32_posv(mg, orc, n):
 
 
 # ----------------------------------------------------------- look-ahead
-@pytest.mark.parametrize("n,nb", [(1000, 128), (2100, 256), (4100, 128)])
+@pytest.mark.parametrize("n,nb", [(1000, 128), (2100, 256), (4100, 128), (2600, 512)])
 def test_lookahead_matches_serial_schedule_bitwise(mg, orc, n, nb):
     """The look-ahead schedule only reorders launches across two streams; every
     tile sees the same arithmetic, so the factor is bitwise identical."""
@@ -250,8 +250,8 @@ def test_deterministic_rerun(mg):
 
 
 # --------------------------------------------- full-size, bench configuration
-@pytest.mark.parametrize("n", [8192, 16384, 32768])
-def test_full_size_config1(mg, orc, n):
+@pytest.mark.parametrize("n,nb", [(8192, None), (16384, None), (32768, None), (16384, 512)])
+def test_full_size_config1(mg, orc, n, nb):
     """A = G G^T/n + delta I with cond ~ 1e4, nrhs = 16, default block size
     (the configuration the benchmark times).  Checked by the oracle's
     extended-precision backward error on every column, plus sampled entries
@@ -261,8 +261,8 @@ def test_full_size_config1(mg, orc, n):
     Xt = synth.torch_normal((n, nrhs), 9100 + n)
     B = A @ Xt
     A0 = A.clone()
-    X, info = mg.posv(A, B)
-    L, info2 = mg.potrf(A0)
+    X, info = mg.posv(A, B, nb=nb)
+    L, info2 = mg.potrf(A0, nb=nb)
     torch.cuda.synchronize()
     assert int(info) == 0 and int(info2) == 0
     Ah = A0.cpu().numpy()          # symmetric: row-major bytes == column-major
