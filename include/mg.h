@@ -66,11 +66,12 @@ mg_status mg_set_stream(mg_handle_t handle, void *stream);
  * Errors: -1 NULL handle, -2 unsupported nb. */
 mg_status mg_set_block_size(mg_handle_t handle, int64_t nb);
 /* Look-ahead schedule for potrf (default on): the trailing update of step k
- * is split into the next block column, updated first on the handle's stream
- * so that the next diagonal block and panel can be factored right away, and
- * the remainder, run on a second stream owned by the handle; events order
- * the two, and the handle's stream waits for the second one before potrf
- * returns its work.  0 runs every step in sequence on one stream.
+ * is split into the next block column, updated first so that the next
+ * diagonal block and panel can be factored right away, and the remainder,
+ * applied concurrently.  The two run on two non-blocking streams owned by the
+ * handle, which fork from and join into the handle's stream by events.  0
+ * runs every step in sequence on the handle's stream.  The result is bitwise
+ * the same either way.
  * Errors: -1 NULL handle. */
 mg_status mg_set_lookahead(mg_handle_t handle, int32_t enable);
 

@@ -81,6 +81,8 @@ mg_status mg_destroy(mg_handle_t h) {
     if (h->ev_panel) (void)hipEventDestroy(h->ev_panel);
     if (h->ev_rest) (void)hipEventDestroy(h->ev_rest);
     if (h->side) (void)hipStreamDestroy(h->side);
+    if (h->chain) (void)hipStreamDestroy(h->chain);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     for (int k = 0; k < MG_PROF_KINDS; ++k) {
         for (hipEvent_t e : h->prof[k].start) (void)hipEventDestroy(e);
         for (hipEvent_t e : h->prof[k].stop) (void)hipEventDestroy(e);

@@ -25,8 +25,9 @@ struct mg_handle_s {
     int profiling = 0;
     mg_prof_counter prof[MG_PROF_KINDS];
     // second stream and events for the look-ahead schedule (created on first use)
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_panel = nullptr, ev_rest = nullptr;
+    hipStream_t side = nullptr;   // look-ahead: bulk trailing update
+    hipStream_t chain = nullptr;  // look-ahead: next block column and panel chain
+    hipEvent_t ev_fork = nullptr, ev_panel = nullptr, ev_rest = nullptr, ev_join = nullptr;
 };
 
 namespace mg {

@@ -27,193 +27,216 @@ mg_status set_info_zero(hipStream_t s, int32_t* info) {
 }
 
 // ---------------------------------------------------------------------------
-// Diagonal-block factor.  One workgroup of W waves factors the s x s block at
-// A (s <= FB_MAX) in place, right-looking over 16-wide block columns, FP64
-// arithmetic whatever the storage type S (the mixed-precision path keeps the
-// diagonal blocks in FP64).
-//   - The lower 16 x 16 tiles are dealt round-robin to the waves once and
-//     stay in registers for the whole factorisation (TPW per wave).
-//   - Step j: the owner of tile (j, j) applies the update from column j-1 and
-//     factors it in registers (factor16); the other owners apply the update
-//     from column j-1 to their tiles (I, J), J >= j (4 MFMAs each, operands
-//     from the LDS copy of column j-1).  Barrier.  Owners of tiles (I, j),
-//     I > j, solve them against L_jj (solve16s) and publish them into the LDS
-//     copy of column j (double buffered by parity) and into A.  Barrier.
+// Diagonal-block factor.  One workgroup of W = 4 waves factors the s x s block
+// at A (s <= FB_MAX = 128) in place, right-looking over 16-wide block columns,
+// FP64 arithmetic whatever the storage type S (the mixed-precision path keeps
+// the diagonal blocks in FP64).
+//   - Wave w owns tile rows ra = w and rb = 7 - w of the lower triangle: 9
+//     tiles of 16 x 16 held in registers for the whole factorisation.  Slot t
+//     holds tile (ra, t) for t <= ra and tile (rb, 8 - t) otherwise, so in
+//     the unrolled slot loops every tile column is a compile-time constant and
+//     only the two row bases are run-time values (this keeps the LDS operand
+//     addresses in immediates and the kernel free of register spills).
+//   - Step j: the owner of (j, j) has factored it (factor16) and published
+//     L_jj pre-scaled by its pivots.  Barrier.  Owners of tiles (I, j), I > j,
+//     solve them (solve16s) and publish them to the LDS copy of block column
+//     j.  Barrier.  Every wave applies column j to its tiles (I, J), J > j
+//     (4 MFMAs each, both operands from LDS), starting with column j + 1; the
+//     owner of (j + 1, j + 1) factors it as soon as its own update is in,
+//     while the other waves are still updating.
+//   - The tiles are written back to A once, at the end.
 // On a non-positive pivot, *info = col0 + local column (1-based).
 // ---------------------------------------------------------------------------
-constexpr int FB_MAX = 256;  // largest block this kernel factors
+constexpr int FB_MAX = 128;  // largest block this kernel factors
+
+// Factor the diagonal tile d (tile (j, j) of the block) in registers and
+// publish it to LDS scaled by its pivots; returns 0 or the failing local
+// column (1-based, within the block).
+template <typename C>
+__device__ __forceinline__ int factor_publish(V4<C>& d, int j, C* Lsc, C* piv) {
+    const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+    const int f = factor16<C>(d);
+    if (f) return 16 * j + f;
+    C pv[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) pv[c] = readlane(d[treg<C>(c)], tgrp<C>(c) * 16 + c);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int col = tcol<C>(g, r);
+        C p = pv[tcol<C>(0, r)];
+#pragma unroll
+        for (int gg = 1; gg < 4; ++gg)
+            if (g == gg) p = pv[tcol<C>(gg, r)];
+        Lsc[i * 17 + col] = (i > col) ? d[r] / p : (C)0;
+        if (i == col) piv[col] = p;
+    }
+    return 0;
+}
 
 template <typename S, int W, int SMAX>
-__global__ __launch_bounds__(64 * W) void k_factor_block(S* __restrict__ A, int64_t lda, int s,
-                                                         int64_t col0, int32_t* info) {
+__global__ __launch_bounds__(64 * W) void k_factor_block(S* __restrict__ A, int64_t lda, int s, int64_t col0,
+                                                         int32_t* info) {
     typedef double C;
-    constexpr int NTM = SMAX / 16;                   // max tiles per side
-    constexpr int TPW = (NTM * (NTM + 1) / 2 + W - 1) / W;
-    __shared__ C Pc[2][SMAX * 17];                   // column panel j: row r, column c at r*17 + c
-    __shared__ C Ls[16 * 17];
-    __shared__ C Lsc[16 * 17];
+    constexpr int NTM = SMAX / 16;  // tile rows at most
+    static_assert(2 * W == NTM, "two tile rows per wave");
+    constexpr int TPW = NTM + 1;    // tiles per wave
+    __shared__ C Pc[SMAX * 17];     // block column j: row r, column c at r*17 + c
+    __shared__ C Lsc[16 * 17];      // L_jj scaled by columns (0 on and above the diagonal)
     __shared__ C piv[16];
     __shared__ int fail;
     if (*info != 0) return;
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
     const int nt = (s + 15) >> 4;
-    const int ntl = nt * (nt + 1) / 2;
+    const int ra = w, rb = NTM - 1 - w;
+    const C* xa = Pc + (16 * ra + i) * 17 + g;  // LDS row bases of the two owned tile rows
+    const C* xb = Pc + (16 * rb + i) * 17 + g;
+    const C* zc = Pc + i * 17 + g;
     if (threadIdx.x == 0) fail = 0;
 
-    // load the owned tiles
     V4<C> acc[TPW];
-    int tI[TPW], tJ[TPW];
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
-        const int lin = w + W * t;
-        int I = 0, J = 0;
-        if (lin < ntl) {
-            I = (int)((sqrtf(8.0f * lin + 1.0f) - 1.0f) * 0.5f);
-            while (I * (I + 1) / 2 > lin) --I;
-            while ((I + 1) * (I + 2) / 2 <= lin) ++I;
-            J = lin - I * (I + 1) / 2;
-            load_tile<S, C>(acc[t], A, lda, 16 * I, 16 * J, s, s, I == J, I == J);
+        if (t <= ra) {
+            if (ra < nt) load_tile<S, C>(acc[t], A, lda, 16 * ra, 16 * t, s, s, ra == t, ra == t);
+            else acc[t] = V4<C>{0, 0, 0, 0};
         } else {
-            I = -1;
-            J = -1;
+            if (rb < nt) load_tile<S, C>(acc[t], A, lda, 16 * rb, 16 * (NTM - t), s, s, rb == NTM - t, rb == NTM - t);
+            else acc[t] = V4<C>{0, 0, 0, 0};
         }
-        tI[t] = I;
-        tJ[t] = J;
     }
-    __syncthreads();
 
-    for (int j = 0; j < nt; ++j) {
-        const C* Pp = Pc[(j + 1) & 1];  // column j-1
-        C* Pn = Pc[j & 1];              // column j (written this step)
-        // ---- update from column j-1
-        V4<C> d = {0, 0, 0, 0};
-        bool own_diag = false;
+    // the owner of (jj, jj) factors it: slot jj (row ra) or NTM - jj (row rb)
+#define MG_FACTOR_OWNED(jj)                                                                  \
+    do {                                                                                     \
+        const int td_ = ((jj) == ra) ? (jj) : NTM - (jj);                                     \
+        V4<C> d_ = acc[0];                                                                   \
+        _Pragma("unroll") for (int t = 1; t < TPW; ++t) if (t == td_) d_ = acc[t];           \
+        const int f_ = factor_publish<C>(d_, (jj), Lsc, piv);                                \
+        if (f_ && l == 0) fail = f_;                                                         \
+        _Pragma("unroll") for (int t = 0; t < TPW; ++t) if (t == td_) acc[t] = d_;           \
+    } while (0)
+    // acc[t] -= L(I, j) L(J, j)^T, operands from the LDS copy of column j
+#define MG_APPLY(t, xr, J)                                                                   \
+    _Pragma("unroll") for (int ks = 0; ks < 4; ++ks)                                         \
+        acc[t] = mma_xzt(acc[t], (xr)[4 * ks], -zc[(16 * (J)) * 17 + 4 * ks])
+
+    // step j = -1 only factors tile (0, 0)
+    for (int j = -1; j < nt; ++j) {
+        if (j >= 0) {
+            __syncthreads();  // L_jj published (or failure flagged)
+            if (fail) {
+                if (threadIdx.x == 0) *info = (int32_t)(col0 + fail);
+                return;
+            }
+            // ---- solve the owned tiles (I, j), I > j, and publish them (one
+            // code path for both owned rows)
+            for (int h = 0; h < 2; ++h) {
+                const int I = h ? rb : ra;
+                if (I <= j || I >= nt) continue;
+                const int ts = h ? NTM - j : j;
+                V4<C> y = acc[0];
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) {
-            const int I = tI[t], J = tJ[t];
-            if (J >= j) {
-                if (j > 0) {
+                for (int t = 1; t < TPW; ++t)
+                    if (t == ts) y = acc[t];
+                solve16s<C, 17>(y, Lsc, piv);
 #pragma unroll
-                    for (int ks = 0; ks < 4; ++ks) {
-                        const int kk = 4 * ks + g;
-                        acc[t] = mma_xzt(acc[t], Pp[(16 * I + i) * 17 + kk], -Pp[(16 * J + i) * 17 + kk]);
-                    }
-                }
-                if (I == j && J == j) {
-                    d = acc[t];
-                    own_diag = true;
+                for (int r = 0; r < 4; ++r) Pc[(16 * I + i) * 17 + tcol<C>(g, r)] = y[r];
+#pragma unroll
+                for (int t = 0; t < TPW; ++t)
+                    if (t == ts) acc[t] = y;
+            }
+            __syncthreads();  // block column j in LDS; L_jj no longer read
+            // ---- apply column j to column j + 1
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                if (t <= ra) {
+                    if (ra < nt && t == j + 1) MG_APPLY(t, xa, t);
+                } else {
+                    if (rb < nt && NTM - t == j + 1) MG_APPLY(t, xb, NTM - t);
                 }
             }
         }
-        // ---- the owner of (j, j) factors it
-        if (own_diag) {
-            const int f = factor16<C>(d);
-            if (f) {
-                if (l == 0) fail = 16 * j + f;
-            } else {
-                tile_to_lds_lower<C, 17>(d, Ls);
-                store_tile<S, C>(d, A, lda, 16 * j, 16 * j, s, s, true);
+        // ---- factor (j+1, j+1) if owned, while the others keep updating
+        if (j + 1 < nt && (j + 1 == ra || j + 1 == rb)) MG_FACTOR_OWNED(j + 1);
+        if (j >= 0) {
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                if (t <= ra) {
+                    if (ra < nt && t > j + 1) MG_APPLY(t, xa, t);
+                } else {
+                    if (rb < nt && NTM - t > j + 1) MG_APPLY(t, xb, NTM - t);
+                }
+                __builtin_amdgcn_sched_barrier(0);  // one tile's operands live at a time
             }
         }
-        __syncthreads();
-        if (fail) {
-            if (threadIdx.x == 0) *info = (int32_t)(col0 + fail);
-            return;
+    }
+#undef MG_APPLY
+#undef MG_FACTOR_OWNED
+    // ---- write the factor back (diagonal tiles: lower part only)
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        if (t <= ra) {
+            if (ra < nt) store_tile<S, C>(acc[t], A, lda, 16 * ra, 16 * t, s, s, ra == t);
+        } else {
+            if (rb < nt) store_tile<S, C>(acc[t], A, lda, 16 * rb, 16 * (NTM - t), s, s, rb == NTM - t);
         }
-        scale_lower16<C, 17>(Ls, Lsc, piv, threadIdx.x);
-        __syncthreads();
-        // ---- solve the owned tiles below the diagonal in column j, publish them
-        unsigned todo = 0;
-#pragma unroll
-        for (int t = 0; t < TPW; ++t)
-            if (tJ[t] == j && tI[t] > j) todo |= 1u << t;
-        while (todo) {
-            const int t0 = __builtin_ctz(todo);
-            todo &= todo - 1;
-            V4<C> y = {0, 0, 0, 0};
-            int I0 = 0;
-#pragma unroll
-            for (int t = 0; t < TPW; ++t)
-                if (t == t0) {
-                    y = acc[t];
-                    I0 = tI[t];
-                }
-            solve16s<C, 17>(y, Lsc, piv);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) Pn[(16 * I0 + i) * 17 + tcol<C>(g, r)] = y[r];
-            store_tile<S, C>(y, A, lda, 16 * I0, 16 * j, s, s, false);
-        }
-        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
 // Panel TRSM: X = P L^{-T} in place for the m x NB panel P, L = L_kk (NB x NB
-// lower).  Each wave owns 16 panel rows and walks the NB columns in chunks of
-// four 16-wide tiles held in registers:
-//   - the chunk first receives -X_p L_jp^T for every earlier tile p (the
-//     wave's own solved tiles, re-read from L1/L2 where it stored them, and
-//     rows of L_kk shared by every wave), four independent MFMA chains;
-//   - inside the chunk, tile t takes the update from tiles p < t straight from
-//     registers (the k index of step ks in lane group g is 16p + tcol(g, ks),
-//     exactly the column that tile p keeps in register ks), then solve16s
-//     against the diagonal 16 x 16 block of L_kk held in LDS.
+// lower, NB <= FB_MAX).  The NB/16 (NB/16 + 1)/2 lower 16 x 16 tiles of L_kk
+// are staged once per workgroup in LDS (diagonal tiles pre-scaled by their
+// pivots), laid out so that each MFMA operand is one conflict-free LDS read.
+// Each wave owns 16 panel rows and keeps their NB/16 tiles in registers:
+// tile t receives -X_p L_tp^T from every solved tile p < t (the k index of
+// step ks in lane group g is tcol(g, ks), exactly the column tile p keeps in
+// its register ks, so that operand comes straight from registers), then is
+// solved against L_tt by substitution (solve16s).  Exact for integer data
+// with power-of-two pivots.
 // ---------------------------------------------------------------------------
 template <typename S, int NB>
 __global__ __launch_bounds__(256) void k_trsm_panel(S* __restrict__ P, const S* __restrict__ Lkk,
                                                     int64_t lda, int64_t m, const int32_t* info) {
-    constexpr int NT = NB / 16;
-    __shared__ S Ld[NT][16 * 17];   // diagonal 16x16 blocks of L_kk, column-scaled
-    __shared__ S Pv[NT][16];        // their pivots
+    constexpr int NT = NB / 16, NTT = NT * (NT + 1) / 2;
+    __shared__ S Lt[NTT][16 * 17];  // tile (t, p), p <= t, at t (t + 1) / 2 + p: row r, column c at r*17 + c
+    __shared__ S Pv[NT][16];        // pivots of the diagonal tiles
     if (*info != 0) return;
     for (int e = threadIdx.x; e < NT * 16; e += blockDim.x) {
         const int b = e >> 4, c = e & 15;
         Pv[b][c] = Lkk[idx(16 * b + c, 16 * b + c, lda)];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < NT * 256; e += blockDim.x) {
-        const int b = e >> 8, rr = (e >> 4) & 15, cc = e & 15;
-        Ld[b][rr * 17 + cc] = (rr > cc) ? Lkk[idx(16 * b + rr, 16 * b + cc, lda)] / Pv[b][cc] : (S)0;
+    for (int e = threadIdx.x; e < NTT * 256; e += blockDim.x) {
+        const int tt = e >> 8, rr = (e >> 4) & 15, cc = e & 15;
+        int t = 0;
+        while ((t + 1) * (t + 2) / 2 <= tt) ++t;
+        const int p = tt - t * (t + 1) / 2;
+        S v;
+        if (p < t) v = Lkk[idx(16 * t + rr, 16 * p + cc, lda)];
+        else v = (rr > cc) ? Lkk[idx(16 * t + rr, 16 * t + cc, lda)] / Pv[t][cc] : (S)0;
+        Lt[tt][rr * 17 + cc] = v;
     }
     __syncthreads();
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, g = l >> 4;
     const int64_t R = ((int64_t)blockIdx.x * 4 + w) * 16;
     if (R >= m) return;
-    const bool vrow = R + i < m;
-    for (int jc = 0; jc < NT; jc += 4) {
-        V4<S> x[4];
+    V4<S> x[NT];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) load_tile<S, S>(x[t], P, lda, R, 16 * (jc + t), m, NB, false, false);
-        for (int p = 0; p < jc; ++p) {
-            S xp[4];
+    for (int t = 0; t < NT; ++t) load_tile<S, S>(x[t], P, lda, R, 16 * t, m, NB, false, false);
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks)
-                xp[ks] = vrow ? P[idx(R + i, 16 * p + tcol<S>(g, ks), lda)] : (S)0;
+    for (int t = 0; t < NT; ++t) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
+        for (int p = 0; p < t; ++p) {
+            const S* Z = Lt[t * (t + 1) / 2 + p] + i * 17;
 #pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
-                    const S z = Lkk[idx(16 * (jc + t) + i, 16 * p + tcol<S>(g, ks), lda)];
-                    x[t] = mma_xzt(x[t], xp[ks], -z);
-                }
-            }
+            for (int ks = 0; ks < 4; ++ks) x[t] = mma_xzt(x[t], x[p][ks], -Z[tcol<S>(g, ks)]);
         }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-#pragma unroll
-            for (int p = 0; p < t; ++p) {
-#pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
-                    const S z = Lkk[idx(16 * (jc + t) + i, 16 * (jc + p) + tcol<S>(g, ks), lda)];
-                    x[t] = mma_xzt(x[t], x[p][ks], -z);
-                }
-            }
-            solve16s<S, 17>(x[t], Ld[jc + t], Pv[jc + t]);
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) store_tile<S, S>(x[t], P, lda, R, 16 * (jc + t), m, NB, false);
+        solve16s<S, 17>(x[t], Lt[t * (t + 1) / 2 + t], Pv[t]);
     }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) store_tile<S, S>(x[t], P, lda, R, 16 * t, m, NB, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -435,7 +458,6 @@ static mg_status launch_trsm(hipStream_t st, int64_t nb, S* P, const S* Lkk, int
     switch (nb) {
         case 64: hipLaunchKernelGGL((k_trsm_panel<S, 64>), grid, block, 0, st, P, Lkk, lda, m, info); break;
         case 128: hipLaunchKernelGGL((k_trsm_panel<S, 128>), grid, block, 0, st, P, Lkk, lda, m, info); break;
-        case 256: hipLaunchKernelGGL((k_trsm_panel<S, 256>), grid, block, 0, st, P, Lkk, lda, m, info); break;
         default: return MG_ERR_UNSUPPORTED;
     }
     MG_LAUNCH_CHECK();
@@ -472,7 +494,8 @@ static mg_status panel_step(mg_handle_t h, hipStream_t st, T* A, int64_t lda, in
     T* Akk = A + idx(k0, k0, lda);
     mg_status rc;
     if ((rc = prof_begin(h, MG_PROF_DIAG, st))) return rc;
-    hipLaunchKernelGGL((k_factor_block<T, 8, FB_MAX>), dim3(1), dim3(512), 0, st, Akk, lda, (int)kb, k0, info);
+    hipLaunchKernelGGL((k_factor_block<T, FB_MAX / 32, FB_MAX>), dim3(1), dim3(2 * FB_MAX), 0, st, Akk, lda, (int)kb, k0,
+                       info);
     MG_LAUNCH_CHECK();
     const double b = (double)kb;
     if ((rc = prof_end(h, MG_PROF_DIAG, b * b * b / 3 + b * b / 2 + b / 6, b * (b + 1) * sizeof(T), st))) return rc;
@@ -527,9 +550,12 @@ static mg_status trailing(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int6
     return prof_end(h, MG_PROF_TRAILING, 2.0 * b * elems, (2.0 * elems + (md - c0) * b) * sizeof(T), st);
 }
 
+// The two streams of the look-ahead schedule (created on first use).
 static mg_status ensure_side(mg_handle_t h) {
     if (h->side) return MG_OK;
     MG_HIP(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    MG_HIP(hipStreamCreateWithFlags(&h->chain, hipStreamNonBlocking));
+    MG_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
     MG_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
     MG_HIP(hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming));
     MG_HIP(hipEventCreateWithFlags(&h->ev_rest, hipEventDisableTiming));
@@ -551,28 +577,34 @@ mg_status potrf_impl(mg_handle_t h, int64_t n, T* A, int64_t lda, int32_t* info)
         }
         return MG_OK;
     }
-    // Look-ahead: this stream updates the next block column with panel k,
+    // Look-ahead: a chain stream updates the next block column with panel k,
     // then factors it and solves its panel while the second stream applies
     // panel k to everything to the right of that column:
-    //   stream : wait(ev_rest) -> next(k) -> [ev_next] -> panel(k+1)
-    //   side   : wait(ev_next) -> rest(k) -> [ev_rest]
+    //   chain : wait(ev_rest) -> next(k) -> [ev_panel] -> panel(k+1)
+    //   side  : wait(ev_panel) -> rest(k) -> [ev_rest]
     // The remainder is released only once next(k) is done, so the one-
     // workgroup diagonal factor of block k+1 becomes runnable together with
     // it and is dispatched before the remainder's workgroups fill the chip.
+    // Both streams are the handle's own, non-blocking, and fork from / join
+    // into the caller's stream by events.
     if ((rc = ensure_side(h))) return rc;
+    hipStream_t ch = h->chain;
     MG_HIP(hipEventRecord(h->ev_fork, st));
+    MG_HIP(hipStreamWaitEvent(ch, h->ev_fork, 0));
     MG_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-    if ((rc = panel_block<T>(h, st, A, lda, n, 0, nb, info))) return rc;
+    if ((rc = panel_block<T>(h, ch, A, lda, n, 0, nb, info))) return rc;
     for (int64_t k = 0; k + 1 < nsteps; ++k) {
         const int64_t k0 = k * nb;
-        if ((rc = trailing<T>(h, st, A, lda, n, k0, nb, info, 0, wnext))) return rc;
-        MG_HIP(hipEventRecord(h->ev_panel, st));             // panel k applied to block column k+1
+        if ((rc = trailing<T>(h, ch, A, lda, n, k0, nb, info, 0, wnext))) return rc;
+        MG_HIP(hipEventRecord(h->ev_panel, ch));             // panel k applied to block column k+1
         MG_HIP(hipStreamWaitEvent(h->side, h->ev_panel, 0));
         if ((rc = trailing<T>(h, h->side, A, lda, n, k0, nb, info, wnext, -1))) return rc;
-        if ((rc = panel_block<T>(h, st, A, lda, n, k0 + nb, nb, info))) return rc;
+        if ((rc = panel_block<T>(h, ch, A, lda, n, k0 + nb, nb, info))) return rc;
         MG_HIP(hipEventRecord(h->ev_rest, h->side));         // rest(k) done
-        MG_HIP(hipStreamWaitEvent(st, h->ev_rest, 0));
+        MG_HIP(hipStreamWaitEvent(ch, h->ev_rest, 0));
     }
+    MG_HIP(hipEventRecord(h->ev_join, ch));
+    MG_HIP(hipStreamWaitEvent(st, h->ev_join, 0));
     return MG_OK;
 }
 
