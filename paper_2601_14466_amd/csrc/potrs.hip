@@ -4,27 +4,29 @@
 // Each triangular sweep is ONE launch of a persistent kernel over blocks of
 // JB = 64 rows.  A workgroup takes the next block from an atomic ticket (the
 // forward sweep hands out blocks top-down, the backward sweep bottom-up), so a
-// block only ever waits for blocks whose workgroups are already running, and
-// blocks complete strictly in ticket order: block t can finish only after
-// block t - 1.  One counter per sweep therefore says how many blocks are
-// final; a workgroup polls it with acquire loads and publishes its own block
-// with a release store.  Inside a workgroup:
-//   * the four waves split the finished blocks j (j = w, w + 4, ...), each
-//     streaming its rows of L straight from memory (one lane per row of the
-//     block: L(i, j) for the forward sweep, read down a column of L for the
-//     backward sweep, where L(j, i) is the transposed block) and applying
-//     acc -= L_ij X_j with the block's solution broadcast by the scalar unit;
-//   * the four partial sums are added in a fixed order through LDS;
-//   * wave 0 solves the diagonal block by substitution in registers (a lane per
-//     row, each step's pivot row broadcast by readlane), with L_ii staged in
-//     LDS pre-scaled by its pivots (column c divided by L_cc for the forward
+// block only ever waits for blocks whose workgroups are already running.
+// Before a sweep its output array is filled with a signalling-NaN sentinel;
+// a finished block simply stores its values (device-coherent stores), and a
+// dependent block loads the values it needs (device-coherent loads) until
+// none of them is the sentinel.  Arithmetic never produces a signalling NaN
+// (IEEE operations quiet them), so a sentinel can only mean "not yet written",
+// and the hand-over costs one store and one load, with no flag or fence.
+// Inside a workgroup:
+//   * each dependency block j is loaded into LDS once, then the four waves
+//     (16 rows of the block each) apply acc += L_ij X_j with MFMAs (forward;
+//     the backward sweep reads L down its columns for L_ji^T), L streamed
+//     from memory;
+//   * the products go through LDS to a row-per-lane layout and wave w solves
+//     the right-hand sides w, w + 4, ... by substitution in registers (each
+//     step's pivot row broadcast by readlane), with L_ii staged in LDS
+//     pre-scaled by its pivots (column c divided by L_cc for the forward
 //     sweep, row c for the backward one, diagonal 0) so a step is one FMA per
 //     value and the division by the pivot happens once at the end (integer
 //     data with power-of-two pivots stays exact).
-// Every wait is bounded: a counter that does not advance within the spin
-// limit sets an error word in the workspace and the kernel drains.  Each sweep
-// reads the lower triangle once (HBM-bound, nrhs/4 flop per byte in FP64); the
-// chain of block solves is the latency floor.
+// Every wait is bounded: a block that stays unwritten past the spin limit
+// sets an error word in the workspace and the kernel drains.  Each sweep
+// reads the lower triangle once (HBM-bound, nrhs/4 flop per byte in FP64);
+// the chain of block solves is the latency floor.
 #include <algorithm>
 
 #include "mg_internal.h"
@@ -36,12 +38,11 @@ constexpr int JB = 64;       // rows per block
 constexpr int LDP = JB + 1;  // LDS leading dimension (bank spread)
 constexpr int SWEEP_SPIN_LIMIT = 1 << 22;
 
-// Per-sweep synchronisation words, kept in the workspace after Y.
+// Per-sweep words, kept in the workspace after Y.
 struct SweepSync {
-    int done;    // blocks final so far (in ticket order)
     int ticket;  // next block to hand out
     int err;     // set when a bounded wait gives up
-    int pad;
+    int pad[2];
 };
 
 static size_t y_bytes(int64_t n, int64_t nrhs, int es) { return align_up((size_t)n * (size_t)nrhs * es, 256); }
@@ -50,8 +51,26 @@ size_t potrs_work_bytes(int64_t n, int64_t nrhs, int es) {
     return (n == 0 || nrhs == 0) ? 0 : y_bytes(n, nrhs, es) + 256;
 }
 
-__global__ void k_sweep_init(SweepSync* s) {
-    if (threadIdx.x < 2) s[threadIdx.x] = SweepSync{0, 0, 0, 0};
+// Signalling NaNs (quiet bit clear, non-zero payload): never produced by
+// arithmetic, so they mark entries that have not been written yet.
+__device__ __forceinline__ double sentinel(double*) { return __builtin_bit_cast(double, 0x7ff4d1e5a1f00d01ull); }
+__device__ __forceinline__ float sentinel(float*) { return __builtin_bit_cast(float, 0x7fa1d1e5u); }
+__device__ __forceinline__ bool is_sentinel(double v) {
+    return __builtin_bit_cast(unsigned long long, v) == 0x7ff4d1e5a1f00d01ull;
+}
+__device__ __forceinline__ bool is_sentinel(float v) { return __builtin_bit_cast(unsigned, v) == 0x7fa1d1e5u; }
+
+// Fill the sweep's output (n x nrhs, leading dimension ld) with the sentinel
+// and reset its words.  Skipped when a preceding factorisation failed, so B
+// is left as it was.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sweep_init(T* Out, int64_t ld, int64_t n, int64_t nrhs, SweepSync* sy,
+                                                    const int32_t* info) {
+    if (info && *info != 0) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *sy = SweepSync{0, 0, {0, 0}};
+    const int64_t tot = n * nrhs;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256)
+        Out[idx(e % n, e / n, ld)] = sentinel((T*)nullptr);
 }
 
 // L_jj (jb x jb lower, identity-padded to 64 x 64) into Ls[r*LDP + c] scaled
@@ -78,12 +97,10 @@ __device__ __forceinline__ void stage_diag(T* Ls, T* piv, const T* L, int64_t ld
     }
 }
 
-// Cross-workgroup traffic of the sweeps (the counter and the solution blocks)
-// uses device-coherent loads and stores, which bypass the per-XCD caches, so
-// no cache invalidation or write-back fence is needed: a block's values are
-// stored coherently, the storing wave waits for those stores to complete,
-// and only then is the counter advanced.  A reader issues its loads of a
-// block only after it has seen the counter pass that block.
+// Cross-workgroup traffic of the sweeps (the solution blocks and the error
+// word) uses device-coherent loads and stores, which bypass the per-XCD
+// caches, so a value stored by one workgroup is seen by the others without
+// cache invalidation or write-back fences.
 __device__ __forceinline__ int load_coherent(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -121,47 +138,82 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t 
     stage_diag<T, !FWD>(Ls, piv, L, lda, r0, jb);
     // MFMA phase: wave w owns rows 16 w .. 16 w + 15 of the block
     const int64_t rwc = (16 * w + i < jb) ? r0 + 16 * w + i : r0;  // clamped for loads
-    // blocks this one depends on: j < bi (forward) or j > bi (backward); the
-    // d-th of them in completion order is final once done > d
+    // blocks this one depends on: j = 0 .. bi - 1 (forward) or j = nblk - 1
+    // down to bi + 1 (backward), visited in the order they are handed out
     const int ndep = FWD ? bi : nblk - 1 - bi;
-    int ready = 0;
     bool abort = false;
+    constexpr int XPT = JB * NR / 256;  // solution values each thread moves per block
     for (int64_t rc0 = 0; rc0 < nrhs; rc0 += NR) {
         V4<T> acc[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) acc[rt] = V4<T>{0, 0, 0, 0};
-        for (int d = 0; d < ndep; ++d) {
-            if (ready <= d && !abort) {
-                int spins = 0;
-                while ((ready = load_coherent(&sy->done)) <= d) {
-                    if (++spins > SWEEP_SPIN_LIMIT || load_coherent(&sy->err)) {
-                        abort = true;
-                        if (lane == 0) atomicExch(&sy->err, 1);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            }
+        // Software pipeline over the dependency blocks: the L values (per
+        // lane, one per k-step) and the solution values of block d + 1 are
+        // requested before block d is multiplied, so memory latency is paid
+        // once per sweep step, not once per block.
+        T lc[JB / 4], ln[JB / 4], xc[XPT], xn[XPT];
+        auto load_l = [&](T* dst, int d) {
             const int j = FWD ? d : nblk - 1 - d;
             const int64_t c0 = (int64_t)j * JB;
             const int jbj = (int)(n - c0 < JB ? n - c0 : JB);
-            // the finished block X_j (jbj x NR) into LDS; consecutive threads
-            // walk its rows, the contiguous direction
-            T* xs = Xs[d & 1];
-            for (int e = tid; e < JB * NR; e += 256) {
-                const int c = e & (JB - 1), q = e >> 6;
-                xs[c * XP + q] = (c < jbj && rc0 + q < nrhs) ? load_coherent(&Out[idx(c0 + c, rc0 + q, ldo)]) : (T)0;
-            }
-            __syncthreads();
-            // acc += L_ij X_j (forward) or L_ji^T X_j (backward), 16 k-steps
-#pragma unroll 4
+#pragma unroll
             for (int ks = 0; ks < JB / 4; ++ks) {
                 const int c = 4 * ks + g;
-                const T x = (c < jbj) ? (FWD ? L[idx(rwc, c0 + c, lda)] : L[idx(c0 + c, rwc, lda)]) : (T)0;
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt) acc[rt] = mma_xzt(acc[rt], x, xs[c * XP + 16 * rt + i]);
+                dst[ks] = (c < jbj) ? (FWD ? L[idx(rwc, c0 + c, lda)] : L[idx(c0 + c, rwc, lda)]) : (T)0;
             }
+        };
+        auto load_x = [&](T* dst, int d) {
+            const int j = FWD ? d : nblk - 1 - d;
+            const int64_t c0 = (int64_t)j * JB;
+            const int jbj = (int)(n - c0 < JB ? n - c0 : JB);
+#pragma unroll
+            for (int k = 0; k < XPT; ++k) {
+                const int e = tid + 256 * k, c = e & (JB - 1), q = e >> 6;
+                dst[k] = (c < jbj && rc0 + q < nrhs) ? load_coherent(&Out[idx(c0 + c, rc0 + q, ldo)]) : (T)0;
+            }
+        };
+        if (ndep > 0) {
+            load_l(lc, 0);
+            load_x(xc, 0);
+        }
+        for (int d = 0; d < ndep; ++d) {
+            if (d + 1 < ndep) {
+                load_l(ln, d + 1);
+                load_x(xn, d + 1);
+            }
+            // block d's solution into LDS, reloaded until every value is
+            // written (the barrier that checks this also publishes the LDS)
+            T* xs = Xs[d & 1];
+            for (int spins = 0;; ++spins) {
+                bool ok = true;
+#pragma unroll
+                for (int k = 0; k < XPT; ++k) {
+                    const int e = tid + 256 * k, c = e & (JB - 1), q = e >> 6;
+                    xs[c * XP + q] = xc[k];
+                    ok = ok && !is_sentinel(xc[k]);
+                }
+                if (__syncthreads_and(ok) || abort) break;
+                // give up (uniformly across the workgroup) past the spin limit
+                // or once another workgroup has given up
+                if (__syncthreads_or(spins > SWEEP_SPIN_LIMIT || load_coherent(&sy->err) != 0)) {
+                    abort = true;
+                    if (tid == 0) atomicExch(&sy->err, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                load_x(xc, d);
+            }
+            // acc += L_ij X_j (forward) or L_ji^T X_j (backward), 16 k-steps
+#pragma unroll
+            for (int ks = 0; ks < JB / 4; ++ks) {
+                const int c = 4 * ks + g;
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) acc[rt] = mma_xzt(acc[rt], lc[ks], xs[c * XP + 16 * rt + i]);
+            }
+#pragma unroll
+            for (int ks = 0; ks < JB / 4; ++ks) lc[ks] = ln[ks];
+#pragma unroll
+            for (int k = 0; k < XPT; ++k) xc[k] = xn[k];
         }
         // partial products to LDS, one row per entry: lane (i, g) holds rows
         // 16 w + i, right-hand sides 16 rt + tcol(g, r)
@@ -203,21 +255,20 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t 
         }
         __syncthreads();  // part is reused by the next pass
     }
-    // every wave's coherent stores complete before the block is published
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (tid == 0) store_coherent(&sy->done, t + 1);
 }
 
 template <typename T, int RT>
 static mg_status sweep(hipStream_t st, int64_t n, int64_t nrhs, const T* L, int64_t lda, T* B, int64_t ldb, T* Y,
                        SweepSync* sy, const int32_t* info) {
     const unsigned nblk = (unsigned)cdiv(n, JB);
-    hipLaunchKernelGGL(k_sweep_init, dim3(1), dim3(64), 0, st, sy);
+    const unsigned gfill = (unsigned)std::min<int64_t>(std::max<int64_t>(1, cdiv(n * nrhs, 256)), 2048);
+    hipLaunchKernelGGL((k_sweep_init<T>), dim3(gfill), dim3(256), 0, st, Y, n, n, nrhs, sy, info);
     MG_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_sweep<T, RT, true>), dim3(nblk), dim3(256), 0, st, L, lda, n, nrhs, (const T*)B, ldb, Y,
                        n, sy, info);
+    MG_LAUNCH_CHECK();
+    // B has been read; it now receives X
+    hipLaunchKernelGGL((k_sweep_init<T>), dim3(gfill), dim3(256), 0, st, B, ldb, n, nrhs, sy + 1, info);
     MG_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_sweep<T, RT, false>), dim3(nblk), dim3(256), 0, st, L, lda, n, nrhs, (const T*)Y, n, B,
                        ldb, sy + 1, info);
