@@ -33,6 +33,25 @@ METRIC = "potrf+potrs TFLOP/s: FP64 vs mixed-precision+IR at 1e-12 backward erro
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 matrix peak (public specification)
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the rank-512 trailing-update kernel, k_syrk_lower<double, true>,
+# from two rocprofv3 --pmc runs of this benchmark (profiles/k_syrk_lower_n32768_hbm_traffic.md):
+# average FETCH_SIZE and WRITE_SIZE per dispatch in KiB, each scaled by what the
+# same counter reads for an 8 GiB device-to-device copy (FETCH_SIZE reads half
+# the bytes moved, WRITE_SIZE all of them).  Valid only for the kernel source
+# it was measured on: reported as null once that source changes.
+SYRK_TRAFFIC = dict(fetch_kib=1863985.3, write_kib=699267.1, fetch_scale=2.0, write_scale=1.0,
+                    kernel_sha1="e650867552d16b4750d6b3d596a1068c20ba44bd")
+
+
+def syrk_traffic_bytes():
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2601_14466_amd", "csrc", "potrf.hip")).read()
+    a, b = src.find("template <typename S, bool FOLD>"), src.find("// Host driver.")
+    if a < 0 or b < 0 or hashlib.sha1(src[a:b].encode()).hexdigest() != SYRK_TRAFFIC["kernel_sha1"]:
+        return None
+    t = SYRK_TRAFFIC
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
+
 
 def nominal_flops(n: int, nrhs: int) -> float:
     return n ** 3 / 3 + n ** 2 / 2 + n / 6 + 2.0 * n * n * nrhs
@@ -81,7 +100,7 @@ def bench_fp64(torch, mg, synth, n: int, nrhs: int, steps: int, warmup: int, nb:
         Bs[j].copy_(B0c)
     torch.cuda.synchronize()
     h.set_profiling(True)
-    for kind in range(4):
+    for kind in range(_lib.MG_PROF_TRAILING_NARROW + 1):
         h.profile(kind, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -94,8 +113,8 @@ def bench_fp64(torch, mg, synth, n: int, nrhs: int, steps: int, warmup: int, nb:
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     prof = {k: h.profile(v, reset=True) for k, v in
-            (("trailing", _lib.MG_PROF_TRAILING), ("diag", _lib.MG_PROF_DIAG),
-             ("trsm", _lib.MG_PROF_TRSM), ("solve", _lib.MG_PROF_SOLVE))}
+            (("trailing", _lib.MG_PROF_TRAILING), ("trailing_narrow", _lib.MG_PROF_TRAILING_NARROW),
+             ("diag", _lib.MG_PROF_DIAG), ("trsm", _lib.MG_PROF_TRSM), ("solve", _lib.MG_PROF_SOLVE))}
     h.set_profiling(False)
     info_max = int(infos.max())
     # sanity residual of the last step's solution, FP64 on the device (harness, not the method)
@@ -357,10 +376,13 @@ def main():
     tr = r["prof"]["trailing"]
     roof = None
     if r["trailing_tflops"] is not None:
+        traffic = syrk_traffic_bytes() if (args.n == 32768 and r["nb"] == 512) else None
         roof = dict(bound="mfma", achieved=round(r["trailing_tflops"], 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(r["trailing_tflops"] / FP64_PEAK_TFLOPS, 4), traffic=None,
-                    kernel="k_syrk_lower<double>", launches=tr["launches"],
-                    flops_per_launch=tr["flops"] / tr["launches"], avg_launch_ms=tr["ms"] / tr["launches"])
+                    frac=round(r["trailing_tflops"] / FP64_PEAK_TFLOPS, 4), traffic=traffic,
+                    kernel="k_syrk_lower<double, true>", launches=tr["launches"],
+                    flops_per_launch=tr["flops"] / tr["launches"],
+                    algorithmic_bytes_per_launch=tr["bytes"] / tr["launches"],
+                    avg_launch_ms=tr["ms"] / tr["launches"])
     line = {
         "metric": METRIC,
         "value": round(r["tflops"], 3),

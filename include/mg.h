@@ -268,13 +268,18 @@ mg_status mg_logdet(mg_handle_t handle, mg_dtype dtype, int64_t n, const void *L
  * Profiling.  When enabled, every launch of the kernel kinds below is
  * bracketed by a pair of HIP events on the handle's stream, and the
  * algorithmic work of each launch is accumulated.
- *   MG_PROF_TRAILING  -- trailing update lower(C) -= P P^T; flops = k m (m+1)
+ *   MG_PROF_TRAILING  -- trailing update lower(C) -= P P^T of rank k = 256 or
+ *                        512 (the kernel variant that folds C into the
+ *                        k-loop); flops = 2 k x (lower entries updated)
  *   MG_PROF_DIAG      -- diagonal-block factor; flops = b^3/3 + b^2/2 + b/6
  *   MG_PROF_TRSM      -- panel triangular solve; flops = m b^2
  *   MG_PROF_SOLVE     -- potrs steps; flops = 2 n^2 nrhs in total
  *   MG_PROF_ADJOINT   -- gradient product of mg_posv_backward; flops = 4 n^2 nrhs
  *   MG_PROF_BATCHED   -- one batched replay; flops = nominal posv flops summed
  *                        over the systems
+ *   MG_PROF_TRAILING_NARROW -- trailing updates of rank 64 or 128 (inside a
+ *                        two-level block column, and the rank-64/128 block
+ *                        sizes); flops as MG_PROF_TRAILING
  * mg_profile_query synchronises on the last recorded event, returns the
  * summed event time (ms), the number of launches and the summed flops and
  * algorithmic bytes, and resets the counter when reset != 0.
@@ -285,7 +290,8 @@ mg_status mg_logdet(mg_handle_t handle, mg_dtype dtype, int64_t n, const void *L
 #define MG_PROF_SOLVE 3
 #define MG_PROF_ADJOINT 4
 #define MG_PROF_BATCHED 5
-#define MG_PROF_KINDS 6
+#define MG_PROF_TRAILING_NARROW 6
+#define MG_PROF_KINDS 7
 /* Errors: -1 NULL handle. */
 mg_status mg_set_profiling(mg_handle_t handle, int32_t enable);
 /* Errors: -1 NULL handle, -2 bad kind, -3..-6 NULL outputs. */

@@ -26,6 +26,7 @@ MG_PROF_TRSM = 2
 MG_PROF_SOLVE = 3
 MG_PROF_ADJOINT = 4
 MG_PROF_BATCHED = 5
+MG_PROF_TRAILING_NARROW = 6
 MG_GRAD_SYM = 0
 MG_GRAD_LOWER = 1
 

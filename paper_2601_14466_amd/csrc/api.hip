@@ -106,7 +106,8 @@ mg_status mg_set_block_size(mg_handle_t h, int64_t nb) {
 
 mg_status mg_set_lookahead(mg_handle_t h, int32_t enable) {
     if (!h) return -1;
-    h->lookahead = enable ? 1 : 0;
+    if (enable < 0 || enable > 2) return -2;
+    h->lookahead = enable;
     return MG_OK;
 }
 

@@ -20,7 +20,8 @@ struct mg_handle_s {
     int device = 0;
     int cu_count = 256;
     int64_t nb = 0;          // potrf block size (the paper's tile size T_A); 0 = default
-    int lookahead = 1;       // overlap the next panel with the trailing update
+    int lookahead = 1;       // 0 serial; 1 look-ahead; 2 look-ahead with one CU per XCD kept for the panel
+    int side_mode = 0;       // look-ahead mode the bulk stream was created for
     int trail_lo = 1;        // FP32 trailing update: 1 plain, 2 operands rounded to bfloat16
     int profiling = 0;
     mg_prof_counter prof[MG_PROF_KINDS];

@@ -446,6 +446,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_lower(S* __restrict__ Cm, const
 int64_t potrf_block_size(mg_handle_t h, int64_t n, int es) {
     (void)es;
     if (h && h->nb > 0) return h->nb;
+    if (n >= 24576) return 512;
     if (n >= 8192) return 256;
     if (n >= 2048) return 128;
     return 64;
@@ -539,7 +540,9 @@ static mg_status trailing(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int6
     if (wj < 0) wj = T_ - j0;
     if (m <= 0 || j0 >= T_ || wj <= 0) return MG_OK;
     mg_status rc;
-    if ((rc = prof_begin(h, MG_PROF_TRAILING, st))) return rc;
+    // rank-256/512 updates run the C-folding kernel variant, narrower ones the other
+    const int kind = (kb % 256 == 0) ? MG_PROF_TRAILING : MG_PROF_TRAILING_NARROW;
+    if ((rc = prof_begin(h, kind, st))) return rc;
     if ((rc = syrk_lower_launch<T>(st, A + idx(e, e, lda), A + idx(e, k0, lda), lda, m, kb, info, j0, wj,
                                    h->trail_lo == 2 ? 1 : 0)))
         return rc;
@@ -547,13 +550,40 @@ static mg_status trailing(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int6
     const double c0 = (double)std::min(m, j0 * SY_BM), c1 = (double)std::min(m, (j0 + wj) * SY_BM);
     const double md = (double)m, b = (double)kb;
     const double elems = (c1 - c0) * md - (c1 * (c1 - 1) - c0 * (c0 - 1)) / 2;  // lower entries in the slab
-    return prof_end(h, MG_PROF_TRAILING, 2.0 * b * elems, (2.0 * elems + (md - c0) * b) * sizeof(T), st);
+    return prof_end(h, kind, 2.0 * b * elems, (2.0 * elems + (md - c0) * b) * sizeof(T), st);
 }
 
-// The two streams of the look-ahead schedule (created on first use).
+// The two streams of the look-ahead schedule (created on first use).  In
+// mode 2 the bulk stream is created with a CU mask that leaves one CU per XCD
+// out (mask bits 33 x for x = 0..7: one per group of 32 consecutive bits and
+// one per residue mod 8, so one per XCD whichever way the bits map to XCDs),
+// so that the one-workgroup diagonal factor on the chain stream finds a CU
+// the bulk update does not occupy.  A CU-masked stream synchronises with the
+// legacy default stream, which the schedule never uses.
 static mg_status ensure_side(mg_handle_t h) {
-    if (h->side) return MG_OK;
-    MG_HIP(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    if (h->side && h->side_mode == h->lookahead) return MG_OK;
+    if (h->side) {
+        MG_HIP(hipStreamSynchronize(h->side));
+        MG_HIP(hipStreamDestroy(h->side));
+        h->side = nullptr;
+    }
+    if (h->lookahead == 2 && h->cu_count >= 64) {
+        const int words = std::min(64, (h->cu_count + 31) / 32);
+        uint32_t mask[64];
+        for (int k = 0; k < words; ++k) {
+            const int nbits = std::min(32, h->cu_count - 32 * k);
+            mask[k] = nbits >= 32 ? 0xffffffffu : ((1u << nbits) - 1u);
+        }
+        for (int x = 0; x < 8; ++x) {
+            const int bit = 33 * x;
+            if (bit < h->cu_count) mask[bit >> 5] &= ~(1u << (bit & 31));
+        }
+        MG_HIP(hipExtStreamCreateWithCUMask(&h->side, (uint32_t)words, mask));
+    } else {
+        MG_HIP(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    }
+    h->side_mode = h->lookahead;
+    if (h->chain) return MG_OK;
     MG_HIP(hipStreamCreateWithFlags(&h->chain, hipStreamNonBlocking));
     MG_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
     MG_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
