@@ -49,51 +49,42 @@ struct BatchArgs {
 // Factor + solve one system: A (n x n, lda) in place, B (n x nrhs, ldb) overwritten
 // by X.  Returns 0 or the failing column (1-based), uniform across the workgroup.
 template <typename T>
-__device__ int solve_one(T* __restrict__ A, int64_t lda, int n, T* __restrict__ B, int64_t ldb, int nrhs,
+__device__ __forceinline__ int solve_one(T* __restrict__ A, int64_t lda, int n, T* __restrict__ B, int64_t ldb, int nrhs,
                          T (*Zs)[BMAX + 1], T* Ls, T* Lsc, T* piv, T* bv, T (*xacc)[16], int* s_fail) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, g = l >> 4;
     const int nt = (n + 15) >> 4;
     for (int j = 0; j < nt; ++j) {
-        // ---- stage row block j of L (columns 0..16j-1) for the z operand
+        // ---- stage row block j of L (columns 0..16j-1): the z operand of
+        // every tile of block column j, and both operands of its diagonal tile
         for (int e = threadIdx.x; e < 16 * 16 * j; e += 256) {
             const int rr = e & 15, c = e >> 4;
             Zs[rr][c] = (16 * j + rr < n) ? A[idx(16 * j + rr, c, lda)] : (T)0;
         }
         __syncthreads();
-        // ---- left-looking update of the tiles of block column j
-        V4<T> acc[BTPW];
+        // ---- diagonal tile (wave 0): A_jj - sum_p L_jp L_jp^T from LDS, factor,
+        // publish, forward substitution of block j
+        if (w == 0) {
+            V4<T> d;
+            load_tile<T, T>(d, A, lda, 16 * j, 16 * j, n, n, true, true);
+            for (int p = 0; p < j; ++p) {
 #pragma unroll
-        for (int t = 0; t < BTPW; ++t) {
-            const int I = j + w + 4 * t;
-            if (I < nt) {
-                load_tile<T, T>(acc[t], A, lda, 16 * I, 16 * j, n, n, I == j, I == j);
-                const int64_t ri = 16 * I + i;
-                const T* xr = A + (ri < n ? ri : 0);
-                for (int p = 0; p < j; ++p) {
-#pragma unroll
-                    for (int ks = 0; ks < 4; ++ks) {
-                        const int kk = 16 * p + 4 * ks + g;
-                        const T x = (ri < n) ? xr[(int64_t)kk * lda] : (T)0;
-                        acc[t] = mma_xzt(acc[t], x, -Zs[i][kk]);
-                    }
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int kk = 16 * p + 4 * ks + g;
+                    d = mma_xzt(d, Zs[i][kk], -Zs[i][kk]);
                 }
             }
-        }
-        // ---- the diagonal tile (wave 0, t = 0)
-        if (w == 0) {
-            const int f = factor16<T>(acc[0]);
+            const int f = factor16<T>(d);
             if (f) {
                 if (l == 0) *s_fail = 16 * j + f;
             } else {
-                tile_to_lds_lower<T, 17>(acc[0], Ls);
-                store_tile<T, T>(acc[0], A, lda, 16 * j, 16 * j, n, n, true);
+                tile_to_lds_lower<T, 17>(d, Ls);
+                store_tile<T, T>(d, A, lda, 16 * j, 16 * j, n, n, true);
             }
         }
         __syncthreads();
         if (*s_fail) return *s_fail;
         scale_lower16<T, 17>(Ls, Lsc, piv, threadIdx.x);
         __syncthreads();
-        // ---- forward substitution for block j: y_j = L_jj^{-1} b_j (wave 0, lanes = rows)
         if (w == 0 && l < 16) {
             for (int r = 0; r < nrhs; ++r) {
                 T v = bv[r * BMAX + 16 * j + l];
@@ -104,28 +95,58 @@ __device__ int solve_one(T* __restrict__ A, int64_t lda, int n, T* __restrict__ 
                 bv[r * BMAX + 16 * j + l] = v / piv[l];
             }
         }
-        // ---- solve the tiles below the diagonal and store them
+        __syncthreads();  // y_j in LDS
+        // ---- tiles below the diagonal, two per wave at a time: left-looking
+        // update (x operand streamed from memory one finished column ahead of
+        // the MFMAs), solve against L_jj, store, and b_I -= L_Ij y_j
+        for (int I0 = j + 1 + w; I0 < nt; I0 += 8) {
+            V4<T> acc[2];
+            int64_t rr_[2];
 #pragma unroll
-        for (int t = 0; t < BTPW; ++t) {
-            const int I = j + w + 4 * t;
-            if (I < nt && I != j) {
-                solve16s<T, 17>(acc[t], Lsc, piv);
-                store_tile<T, T>(acc[t], A, lda, 16 * I, 16 * j, n, n, false);
+            for (int u = 0; u < 2; ++u) {
+                const int I = I0 + 4 * u;
+                const int64_t ri = 16 * I + i;
+                rr_[u] = (I < nt && ri < n) ? ri : -1;
+                if (I < nt) load_tile<T, T>(acc[u], A, lda, 16 * I, 16 * j, n, n, false, false);
+                else acc[u] = V4<T>{0, 0, 0, 0};
             }
-        }
-        __syncthreads();
-        // ---- b_I -= L_Ij y_j for the tiles below (each lane: its row, its 4 columns)
+            T xa[2][4], xb[2][4];
+#define MG_LDX(x, pp)                                                                            \
+    _Pragma("unroll") for (int u = 0; u < 2; ++u)                                                \
+        _Pragma("unroll") for (int ks = 0; ks < 4; ++ks)                                         \
+            x[u][ks] = (rr_[u] >= 0) ? A[rr_[u] + (int64_t)(16 * (pp) + 4 * ks + g) * lda] : (T)0
+#define MG_MMA(x, pp)                                                                            \
+    do {                                                                                         \
+        _Pragma("unroll") for (int ks = 0; ks < 4; ++ks) {                                       \
+            const T z_ = -Zs[i][16 * (pp) + 4 * ks + g];                                         \
+            _Pragma("unroll") for (int u = 0; u < 2; ++u) acc[u] = mma_xzt(acc[u], x[u][ks], z_); \
+        }                                                                                        \
+    } while (0)
+            if (j > 0) { MG_LDX(xa, 0); }
+            for (int p = 0; p < j; p += 2) {
+                if (p + 1 < j) { MG_LDX(xb, p + 1); }
+                MG_MMA(xa, p);
+                if (p + 1 < j) {
+                    if (p + 2 < j) { MG_LDX(xa, p + 2); }
+                    MG_MMA(xb, p + 1);
+                }
+            }
+#undef MG_LDX
+#undef MG_MMA
 #pragma unroll
-        for (int t = 0; t < BTPW; ++t) {
-            const int I = j + w + 4 * t;
-            if (I < nt && I != j) {
+            for (int u = 0; u < 2; ++u) {
+                const int I = I0 + 4 * u;
+                if (I >= nt) continue;
+                solve16s<T, 17>(acc[u], Lsc, piv);
+                store_tile<T, T>(acc[u], A, lda, 16 * I, 16 * j, n, n, false);
+                // b_I -= L_Ij y_j (each lane: its row, its 4 columns; reduce over groups)
                 for (int r = 0; r < nrhs; ++r) {
-                    T s = 0;
+                    T sm = 0;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) s = s + acc[t][q] * bv[r * BMAX + 16 * j + tcol<T>(g, q)];
-                    s = s + shfl(s, l ^ 16);
-                    s = s + shfl(s, l ^ 32);
-                    if (g == 0 && 16 * I + i < n) bv[r * BMAX + 16 * I + i] -= s;
+                    for (int q = 0; q < 4; ++q) sm = sm + acc[u][q] * bv[r * BMAX + 16 * j + tcol<T>(g, q)];
+                    sm = sm + shfl(sm, l ^ 16);
+                    sm = sm + shfl(sm, l ^ 32);
+                    if (g == 0 && 16 * I + i < n) bv[r * BMAX + 16 * I + i] -= sm;
                 }
             }
         }
@@ -154,18 +175,24 @@ __device__ int solve_one(T* __restrict__ A, int64_t lda, int n, T* __restrict__ 
             }
             __syncthreads();
             if (w == 0 && l < 16) {
-                // diagonal block: L_jj^T x_j = y_j - sum, row-scaled back substitution
+                // diagonal block: L_jj^T x_j = y_j - sum by substitution from
+                // the last row up; row c of L_jj^T is scaled by 1/L_cc (one
+                // reciprocal per lane, broadcast by readlane)
                 const T sum = ((xacc[0][l] + xacc[1][l]) + xacc[2][l]) + xacc[3][l];
                 T v = bv[r * BMAX + 16 * j + l] - sum;
                 const bool vl = 16 * j + l < n;
                 const T lj = vl ? A[idx(16 * j + l, 16 * j + l, lda)] : (T)1;
+                const T rl = (T)1 / lj;
+                T lcl[16];
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+                    lcl[c] = (l < c && 16 * j + c < n) ? A[idx(16 * j + c, 16 * j + l, lda)] : (T)0;
+#pragma unroll
                 for (int c = 15; c >= 0; --c) {
                     const T vc = readlane(v, c);
-                    const T lcc = readlane(lj, c);
-                    const T lcl = (l < c && 16 * j + c < n) ? A[idx(16 * j + c, 16 * j + l, lda)] : (T)0;
-                    v = v - (lcl / lcc) * vc;
+                    v = v - lcl[c] * (readlane(rl, c) * vc);
                 }
-                if (vl) bv[r * BMAX + 16 * j + l] = v / lj;
+                if (vl) bv[r * BMAX + 16 * j + l] = v * rl;
             }
             __syncthreads();
         }
