@@ -186,7 +186,7 @@ mg_status mg_posv_mixed_buffer_size(mg_handle_t h, mg_prec lo, int64_t n, int64_
     if (n < 0) return -3;
     if (nrhs < 0) return -4;
     if (!bytes) return -5;
-    *bytes = mixed_work_bytes(n, nrhs, fallback ? 1 : 0);
+    *bytes = mixed_work_bytes(n, nrhs, fallback ? 1 : 0, lo);
     return MG_OK;
 }
 
@@ -209,7 +209,7 @@ mg_status mg_posv_mixed(mg_handle_t h, mg_prec lo, int64_t n, int64_t nrhs, cons
         if (!(opts->tol >= 0.0) || opts->max_iter < 0) return -11;
         o = *opts;
     }
-    const size_t need = mixed_work_bytes(n, nrhs, o.fallback ? 1 : 0);
+    const size_t need = mixed_work_bytes(n, nrhs, o.fallback ? 1 : 0, lo);
     if (!work && any) return -12;
     if (any && work_bytes < need) return -13;
     if (!result) return -14;

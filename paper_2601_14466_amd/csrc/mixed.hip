@@ -82,85 +82,119 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t cnt, unsigned long lon
 // R = B - A X (A symmetric, lower triangle stored), FP64, and the per-column
 // maxima |r|, |x|, |b| (as ordered bit patterns: non-negative doubles order
 // like unsigned integers, so atomicMax is exact and order-independent).
-// With absmode != 0 the kernel instead accumulates the row sums of |A| into
-// colmax[0] as max over rows (|A|_inf of the symmetric matrix) and ignores
-// B, X, R.
-// One workgroup per 64-row strip; it walks the 64 x 64 tiles (I, J) of the
-// whole row, reading the stored tile A(I, J) for J <= I and the transpose of
-// the stored tile A(J, I) for J > I, each staged through LDS with coalesced
-// column reads.
-constexpr int RS = 64;        // strip height / tile width
-constexpr int RQ = 4;         // threads per row (right-hand-side groups)
+// With absmode != 0 the kernels instead produce the row sums of |A| and their
+// maximum (|A|_inf of the symmetric matrix) in colmax[0].
+//
+// Pass 1 (k_sym_rowprod): the grid is (64-row strips) x RSPLIT column ranges.
+// Each workgroup's four waves take the 64 x 64 tiles of its range in turn;
+// a lane owns one row of the strip and streams that row of the tile from
+// memory: stored tiles (J <= I) down their columns (coalesced across lanes),
+// tiles above the diagonal (J > I) as the transposed stored tile, each lane
+// walking its own column.  The x values of the tile arrive one per lane and
+// are broadcast by readlane.  No LDS staging and no barrier inside the loop;
+// the loads of the next 16 columns are issued before the current 16 are
+// used.  The four waves' sums are added in a fixed order and written as one
+// partial per (strip, range).
+// Pass 2 (k_sym_finish): R = B - sum of the partials over the ranges (fixed
+// order), and the column maxima.  The result does not depend on the launch.
+constexpr int RS = 64;      // strip height / tile width
+constexpr int RSPLIT = 8;   // column ranges per strip
+constexpr int RRPT = 8;     // right-hand sides per pass
+
+// partial sums: RSPLIT ranges x n rows x (up to) RRPT right-hand sides
+size_t residual_part_bytes(int64_t n, int64_t nrhs) {
+    (void)nrhs;
+    return (size_t)RSPLIT * (size_t)n * RRPT * 8;
+}
 
 template <int RPT>
-__global__ __launch_bounds__(256) void k_sym_residual(const double* __restrict__ A, int64_t lda, int64_t n,
-                                                      int64_t nrhs, const double* __restrict__ X, int64_t ldx,
-                                                      const double* __restrict__ B, int64_t ldb,
-                                                      double* __restrict__ R, int64_t ldr,
-                                                      unsigned long long* __restrict__ colmax, int absmode) {
-    __shared__ double Ts[RS][RS + 1];          // tile, Ts[row][col] in strip-local orientation
-    __shared__ double Xs[RS][RQ * RPT];        // x rows of tile J
-    const int tid = threadIdx.x, row = tid & (RS - 1), q = tid >> 6;
-    const int64_t I0 = (int64_t)blockIdx.x * RS;
+__global__ __launch_bounds__(256) void k_sym_rowprod(const double* __restrict__ A, int64_t lda, int64_t n,
+                                                     int64_t nrhs, int64_t rc0, const double* __restrict__ X,
+                                                     int64_t ldx, double* __restrict__ Pp, int absmode) {
+    __shared__ double red[4][RPT][RS];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int64_t strip = blockIdx.x, I0 = strip * RS;
     const int64_t nt = (n + RS - 1) / RS;
+    const int64_t per = (nt + RSPLIT - 1) / RSPLIT;
+    const int64_t jb = blockIdx.y * per, je = jb + per < nt ? jb + per : nt;
+    const int64_t gi = I0 + lane;
+    const bool rin = gi < n;
+    const int64_t gic = rin ? gi : I0;  // clamped row for loads
     double acc[RPT];
-    double asum = 0.0;
-    for (int64_t rc0 = 0; rc0 < (absmode ? 1 : nrhs); rc0 += RQ * RPT) {
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) acc[r] = 0.0;
-        for (int64_t Jt = 0; Jt < nt; ++Jt) {
-            const int64_t J0 = Jt * RS;
-            __syncthreads();
-            // stage the tile: for J <= I the block A(I0.., J0..); else A(J0.., I0..)^T
-            for (int e = tid; e < RS * RS; e += 256) {
-                const int a = e & (RS - 1), b = e >> 6;  // a walks the contiguous (row) direction
-                double v = 0.0;
-                if (Jt <= (int64_t)blockIdx.x) {
-                    const int64_t gi = I0 + a, gj = J0 + b;      // Ts[a][b] = A(gi, gj)
-                    if (gi < n && gj < n) v = (gi >= gj) ? A[idx(gi, gj, lda)] : A[idx(gj, gi, lda)];
-                    Ts[a][b] = v;
+    for (int r = 0; r < RPT; ++r) acc[r] = 0.0;
+    for (int64_t Jt = jb + w; Jt < je; Jt += 4) {
+        const int64_t J0 = Jt * RS;
+        const int jw = (int)(n - J0 < RS ? n - J0 : RS);
+        double xv[RPT];
+        if (!absmode) {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r)
+                xv[r] = (lane < jw && rc0 + r < nrhs) ? X[idx(J0 + lane, rc0 + r, ldx)] : 0.0;
+        }
+        // element (gi, J0 + c) of the symmetric matrix: below the diagonal of
+        // the stored triangle it is A[gi + (J0 + c) lda], above it A[(J0 + c) + gi lda]
+        const bool below = Jt < strip, above = Jt > strip;
+#pragma unroll
+        for (int c0 = 0; c0 < RS; c0 += 16) {
+            double av[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int cc = c0 + c;
+                const int64_t gj = J0 + (cc < jw ? cc : 0);
+                double v;
+                if (below) v = A[idx(gic, gj, lda)];
+                else if (above) v = A[idx(gj, gic, lda)];
+                else v = (gic >= gj) ? A[idx(gic, gj, lda)] : A[idx(gj, gic, lda)];
+                av[c] = (cc < jw && rin) ? v : 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                if (absmode) {
+                    acc[0] += fabs(av[c]);
                 } else {
-                    const int64_t gi = J0 + a, gj = I0 + b;      // Ts[b][a] = A(gi, gj) = A_sym(I0+b, J0+a)
-                    if (gi < n && gj < n) v = A[idx(gi, gj, lda)];
-                    Ts[b][a] = v;
-                }
-            }
-            if (!absmode) {
-                for (int e = tid; e < RS * RQ * RPT; e += 256) {
-                    const int c = e % RS, r = e / RS;
-                    const int64_t gc = J0 + c, gr = rc0 + r;
-                    Xs[c][r] = (gc < n && gr < nrhs) ? X[idx(gc, gr, ldx)] : 0.0;
-                }
-            }
-            __syncthreads();
-            if (absmode) {
-                if (q == 0)
-                    for (int c = 0; c < RS; ++c) asum += fabs(Ts[row][c]);
-            } else {
-                for (int c = 0; c < RS; ++c) {
-                    const double a = Ts[row][c];
 #pragma unroll
-                    for (int r = 0; r < RPT; ++r) acc[r] = fma(a, Xs[c][q * RPT + r], acc[r]);
+                    for (int r = 0; r < RPT; ++r) acc[r] = fma(av[c], readlane(xv[r], c0 + c), acc[r]);
                 }
             }
         }
-        const int64_t gi = I0 + row;
-        if (absmode) {
-            if (q == 0 && gi < n) atomicMax(&colmax[0], (unsigned long long)__double_as_longlong(asum));
-        } else if (gi < n) {
+    }
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                const int64_t gr = rc0 + q * RPT + r;
-                if (gr < nrhs) {
-                    const double b = B[idx(gi, gr, ldb)];
-                    const double x = X[idx(gi, gr, ldx)];
-                    const double res = b - acc[r];
-                    R[idx(gi, gr, ldr)] = res;
-                    atomicMax(&colmax[3 * gr + 0], (unsigned long long)__double_as_longlong(fabs(res)));
-                    atomicMax(&colmax[3 * gr + 1], (unsigned long long)__double_as_longlong(fabs(x)));
-                    atomicMax(&colmax[3 * gr + 2], (unsigned long long)__double_as_longlong(fabs(b)));
-                }
-            }
+    for (int r = 0; r < RPT; ++r) red[w][r][lane] = acc[r];
+    __syncthreads();
+    if (w == 0 && rin) {
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+            Pp[((size_t)blockIdx.y * n + gi) * RPT + r] = ((red[0][r][lane] + red[1][r][lane]) + red[2][r][lane]) +
+                                                          red[3][r][lane];
+    }
+}
+
+template <int RPT>
+__global__ __launch_bounds__(256) void k_sym_finish(int64_t n, int64_t nrhs, int64_t rc0, const double* __restrict__ X,
+                                                    int64_t ldx, const double* __restrict__ B, int64_t ldb,
+                                                    double* __restrict__ R, int64_t ldr, const double* __restrict__ Pp,
+                                                    unsigned long long* __restrict__ colmax, int absmode) {
+    for (int64_t gi = (int64_t)blockIdx.x * 256 + threadIdx.x; gi < n; gi += (int64_t)gridDim.x * 256) {
+        if (absmode) {
+            double sm = 0.0;
+            for (int sp = 0; sp < RSPLIT; ++sp) sm += Pp[((size_t)sp * n + gi) * RPT];
+            atomicMax(&colmax[0], (unsigned long long)__double_as_longlong(sm));
+            continue;
+        }
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int64_t gr = rc0 + r;
+            if (gr >= nrhs) break;
+            double sm = 0.0;
+            for (int sp = 0; sp < RSPLIT; ++sp) sm += Pp[((size_t)sp * n + gi) * RPT + r];
+            const double b = B[idx(gi, gr, ldb)];
+            const double x = X[idx(gi, gr, ldx)];
+            const double res = b - sm;
+            R[idx(gi, gr, ldr)] = res;
+            atomicMax(&colmax[3 * gr + 0], (unsigned long long)__double_as_longlong(fabs(res)));
+            atomicMax(&colmax[3 * gr + 1], (unsigned long long)__double_as_longlong(fabs(x)));
+            atomicMax(&colmax[3 * gr + 2], (unsigned long long)__double_as_longlong(fabs(b)));
         }
     }
 }
@@ -181,10 +215,10 @@ __global__ void k_eta(const unsigned long long* __restrict__ colmax, const unsig
 // ------------------------------------------------------------ workspace
 struct MixedWork {
     size_t bytes = 0;
-    size_t o_aw = 0, o_r = 0, o_d = 0, o_y = 0, o_cm = 0, o_an = 0, o_eta = 0, o_info = 0;
+    size_t o_aw = 0, o_r = 0, o_d = 0, o_y = 0, o_cm = 0, o_an = 0, o_eta = 0, o_info = 0, o_p16 = 0, o_rp = 0;
 };
 
-static MixedWork mixed_layout(int64_t n, int64_t nrhs, int fallback) {
+static MixedWork mixed_layout(int64_t n, int64_t nrhs, int fallback, int lo) {
     MixedWork w;
     size_t o = 0;
     auto take = [&](size_t b) {
@@ -201,28 +235,50 @@ static MixedWork mixed_layout(int64_t n, int64_t nrhs, int fallback) {
     w.o_an = take(8);
     w.o_eta = take((size_t)std::max<int64_t>(nrhs, 1) * 8);
     w.o_info = take(8);
+    w.o_rp = take(residual_part_bytes(n, nrhs));  // residual partial sums
+    // bfloat16 mode: two row-major bfloat16 copies of a block column panel
+    // (n x 512 each), alternating between consecutive block columns
+    if (lo == MG_PREC_BF16) w.o_p16 = take(bf16_panel_bytes(n));
     w.bytes = o;
     return w;
 }
 
-size_t mixed_work_bytes(int64_t n, int64_t nrhs, int fallback) { return mixed_layout(n, nrhs, fallback).bytes; }
+size_t mixed_work_bytes(int64_t n, int64_t nrhs, int fallback, int lo) {
+    return mixed_layout(n, nrhs, fallback, lo).bytes;
+}
 
 static inline unsigned grid1(int64_t tot) { return (unsigned)std::min<int64_t>(std::max<int64_t>(1, cdiv(tot, 256)), 65535); }
 
 static mg_status sym_residual(hipStream_t st, const double* A, int64_t lda, int64_t n, int64_t nrhs, const double* X,
                               int64_t ldx, const double* B, int64_t ldb, double* R, unsigned long long* colmax,
-                              int absmode) {
-    const dim3 grid((unsigned)cdiv(n, RS)), block(256);
-    const int64_t per = absmode ? 1 : std::min<int64_t>(nrhs, RQ * 16);
-    if (per <= RQ * 1)
-        hipLaunchKernelGGL((k_sym_residual<1>), grid, block, 0, st, A, lda, n, nrhs, X, ldx, B, ldb, R, n, colmax, absmode);
-    else if (per <= RQ * 2)
-        hipLaunchKernelGGL((k_sym_residual<2>), grid, block, 0, st, A, lda, n, nrhs, X, ldx, B, ldb, R, n, colmax, absmode);
-    else if (per <= RQ * 4)
-        hipLaunchKernelGGL((k_sym_residual<4>), grid, block, 0, st, A, lda, n, nrhs, X, ldx, B, ldb, R, n, colmax, absmode);
-    else
-        hipLaunchKernelGGL((k_sym_residual<8>), grid, block, 0, st, A, lda, n, nrhs, X, ldx, B, ldb, R, n, colmax, absmode);
-    MG_LAUNCH_CHECK();
+                              int absmode, double* Pp) {
+    const dim3 grid((unsigned)cdiv(n, RS), RSPLIT), block(256);
+    const unsigned gf = (unsigned)std::min<int64_t>(std::max<int64_t>(1, cdiv(n, 256)), 4096);
+    for (int64_t rc0 = 0; rc0 < (absmode ? 1 : nrhs); rc0 += RRPT) {
+        const int64_t cnt = absmode ? 1 : std::min<int64_t>(RRPT, nrhs - rc0);
+        if (cnt <= 1) {
+            hipLaunchKernelGGL((k_sym_rowprod<1>), grid, block, 0, st, A, lda, n, nrhs, rc0, X, ldx, Pp, absmode);
+            MG_LAUNCH_CHECK();
+            hipLaunchKernelGGL((k_sym_finish<1>), dim3(gf), block, 0, st, n, nrhs, rc0, X, ldx, B, ldb, R, n, Pp,
+                               colmax, absmode);
+        } else if (cnt <= 2) {
+            hipLaunchKernelGGL((k_sym_rowprod<2>), grid, block, 0, st, A, lda, n, nrhs, rc0, X, ldx, Pp, absmode);
+            MG_LAUNCH_CHECK();
+            hipLaunchKernelGGL((k_sym_finish<2>), dim3(gf), block, 0, st, n, nrhs, rc0, X, ldx, B, ldb, R, n, Pp,
+                               colmax, absmode);
+        } else if (cnt <= 4) {
+            hipLaunchKernelGGL((k_sym_rowprod<4>), grid, block, 0, st, A, lda, n, nrhs, rc0, X, ldx, Pp, absmode);
+            MG_LAUNCH_CHECK();
+            hipLaunchKernelGGL((k_sym_finish<4>), dim3(gf), block, 0, st, n, nrhs, rc0, X, ldx, B, ldb, R, n, Pp,
+                               colmax, absmode);
+        } else {
+            hipLaunchKernelGGL((k_sym_rowprod<8>), grid, block, 0, st, A, lda, n, nrhs, rc0, X, ldx, Pp, absmode);
+            MG_LAUNCH_CHECK();
+            hipLaunchKernelGGL((k_sym_finish<8>), dim3(gf), block, 0, st, n, nrhs, rc0, X, ldx, B, ldb, R, n, Pp,
+                               colmax, absmode);
+        }
+        MG_LAUNCH_CHECK();
+    }
     return MG_OK;
 }
 
@@ -237,7 +293,7 @@ mg_status posv_mixed_impl(mg_handle_t h, int lo, int64_t n, int64_t nrhs, const 
         MG_HIP(hipStreamSynchronize(st));
         return MG_OK;
     }
-    const MixedWork L = mixed_layout(n, nrhs, o->fallback);
+    const MixedWork L = mixed_layout(n, nrhs, o->fallback, lo);
     char* base = (char*)work;
     float* Aw = (float*)(base + L.o_aw);
     double* R = (double*)(base + L.o_r);
@@ -247,14 +303,17 @@ mg_status posv_mixed_impl(mg_handle_t h, int lo, int64_t n, int64_t nrhs, const 
     unsigned long long* an = (unsigned long long*)(base + L.o_an);
     double* eta_d = (double*)(base + L.o_eta);
     int32_t* info_lo = (int32_t*)(base + L.o_info);
+    double* Pp = (double*)(base + L.o_rp);
 
     const int saved_trail = h->trail_lo;
     h->trail_lo = (lo == MG_PREC_BF16) ? 2 : 1;
+    h->bf16_panel = (lo == MG_PREC_BF16) ? (void*)(base + L.o_p16) : nullptr;
     // 1. working copy and low-precision factor
     hipLaunchKernelGGL(k_cast_lower_f64_f32, dim3(grid1(n), (unsigned)n), dim3(256), 0, st, A, lda, Aw, n, n);
     MG_LAUNCH_CHECK();
     rc = potrf_impl<float>(h, n, Aw, n, info_lo);
     h->trail_lo = saved_trail;
+    h->bf16_panel = nullptr;
     if (rc) return rc;
     int32_t hinfo = 0;
     MG_HIP(hipMemcpyAsync(&hinfo, info_lo, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -272,14 +331,14 @@ mg_status posv_mixed_impl(mg_handle_t h, int lo, int64_t n, int64_t nrhs, const 
         // |A|_inf once
         hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, an, (int64_t)1, 0ull);
         MG_LAUNCH_CHECK();
-        if ((rc = sym_residual(st, A, lda, n, nrhs, X, ldx, B, ldb, R, an, 1))) return rc;
+        if ((rc = sym_residual(st, A, lda, n, nrhs, X, ldx, B, ldb, R, an, 1, Pp))) return rc;
         double prev = INFINITY;
         int slow = 0;
         for (int it = 0;; ++it) {
             // 3. FP64 residual and per-column backward error
             hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, st, cm, 3 * nrhs, 0ull);
             MG_LAUNCH_CHECK();
-            if ((rc = sym_residual(st, A, lda, n, nrhs, X, ldx, B, ldb, R, cm, 0))) return rc;
+            if ((rc = sym_residual(st, A, lda, n, nrhs, X, ldx, B, ldb, R, cm, 0, Pp))) return rc;
             hipLaunchKernelGGL(k_eta, dim3(1), dim3(256), 0, st, cm, an, nrhs, eta_d);
             MG_LAUNCH_CHECK();
             MG_HIP(hipMemcpyAsync(eta.data(), eta_d, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
@@ -325,10 +384,10 @@ mg_status posv_mixed_impl(mg_handle_t h, int lo, int64_t n, int64_t nrhs, const 
         if ((rc = potrs_impl<double>(h, n, nrhs, Ad, n, X, ldx, (double*)Yw, info))) return rc;
         hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, st, cm, 3 * nrhs, 0ull);
         MG_LAUNCH_CHECK();
-        if ((rc = sym_residual(st, A, lda, n, nrhs, X, ldx, B, ldb, R, cm, 0))) return rc;
+        if ((rc = sym_residual(st, A, lda, n, nrhs, X, ldx, B, ldb, R, cm, 0, Pp))) return rc;
         hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, an, (int64_t)1, 0ull);
         MG_LAUNCH_CHECK();
-        if ((rc = sym_residual(st, A, lda, n, nrhs, X, ldx, B, ldb, R, an, 1))) return rc;
+        if ((rc = sym_residual(st, A, lda, n, nrhs, X, ldx, B, ldb, R, an, 1, Pp))) return rc;
         hipLaunchKernelGGL(k_eta, dim3(1), dim3(256), 0, st, cm, an, nrhs, eta_d);
         MG_LAUNCH_CHECK();
         MG_HIP(hipMemcpyAsync(eta.data(), eta_d, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));

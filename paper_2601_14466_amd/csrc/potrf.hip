@@ -441,6 +441,122 @@ __global__ __launch_bounds__(256, 2) void k_syrk_lower(S* __restrict__ Cm, const
 }
 
 // ---------------------------------------------------------------------------
+// bfloat16 trailing update (mixed precision, bfloat16 mode): lower(C) -= P P^T
+// with C in binary32 and P given as a row-major bfloat16 copy Pt (m x kdim,
+// leading dimension kdim, kdim % 128 == 0), products of bfloat16 inputs
+// accumulated in FP32 on the 16x16x32 bfloat16 matrix instruction.  Same
+// tiling, tile order, buffer-resource addressing and four-slot operand ring
+// as k_syrk_lower; each lane loads 8 consecutive k of one row (16 bytes) per
+// operand and k-step.  The C tile is loaded up front (short k-loop).
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mma_xzt_bf16(f32x4 acc, bf16x8 x, bf16x8 z) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(z, x, acc, 0, 0, 0);
+}
+
+// Row-major bfloat16 copy of the m x kb panel P (column-major, lda): thread
+// per (row, 8 columns), reading down columns (coalesced) and writing 16
+// contiguous bytes; rounding to nearest even as round_bf16.
+__global__ __launch_bounds__(256) void k_pack_bf16(const float* __restrict__ P, int64_t lda, int64_t m, int kb,
+                                                   __bf16* __restrict__ Pt, const int32_t* info) {
+    if (*info != 0) return;
+    const int64_t groups = kb / 8, tot = m * groups;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+        const int64_t row = e % m, gq = e / m;
+        bf16x8 v;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float r = round_bf16(P[idx(row, gq * 8 + c, lda)]);
+            v[c] = __builtin_bit_cast(__bf16, (unsigned short)(__builtin_bit_cast(unsigned, r) >> 16));
+        }
+        *(bf16x8*)(Pt + row * kb + gq * 8) = v;
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void k_syrk_lower_bf16(float* __restrict__ Cm, const __bf16* __restrict__ Pt,
+                                                            int64_t lda, int64_t m, int kdim, int64_t j0, int64_t wj,
+                                                            const int32_t* info) {
+    if (*info != 0) return;
+    const int64_t T = (m + SY_BM - 1) / SY_BM;
+    const int64_t ntiles = slab_tiles(T, j0, wj);
+    const int64_t per = gridDim.x / 8;
+    const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (t >= ntiles) return;
+    int64_t I, J;
+    slab_tile_coords(t, j0, wj, I, J);
+    constexpr int ES = 4;
+    const int tid = threadIdx.x, l = tid & 63, i = l & 15, g = l >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = w >> 1, wc = w & 1;
+    const int64_t sr0 = I * SY_BM + 64 * wr, sc0 = J * SY_BM + 64 * wc;
+    if (sr0 + 63 < sc0 || sr0 >= m || sc0 >= m) return;
+    const int ld = (int)lda;
+    const int rmax = (int)(m - 1 - sr0 < 63 ? m - 1 - sr0 : 63);
+    const int cmax = (int)(m - 1 - sc0 < 63 ? m - 1 - sc0 : 63);
+    const int dd = (int)(sr0 - sc0 < 64 ? sr0 - sc0 : 64);
+    const __amdgpu_buffer_rsrc_t crs = buf_rsrc(Cm + idx(sr0, sc0, lda), 0x7fffffff);
+    auto c_in = [&](int bi, int bj, int r) {
+        const int rr = 16 * bi + i, cc = 16 * bj + tcol<float>(g, r);
+        return rr <= rmax && cc <= cmax && rr + dd >= cc;
+    };
+    auto c_off = [&](int bi, int bj, int r) {
+        const int rr = min(16 * bi + i, rmax), cc = min(16 * bj + tcol<float>(g, r), cmax);
+        return (rr + cc * ld) * ES;
+    };
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float v = buf_ld((float*)nullptr, crs, c_off(bi, bj, r), 0);
+                acc[bi][bj][r] = c_in(bi, bj, r) ? -v : 0.0f;
+            }
+    // operand rows (clamped into the block) of the row-major panel; k-step
+    // kn covers k = 32 kn .. 32 kn + 31, lane group g its 8 entries 8 g ..
+    const __amdgpu_buffer_rsrc_t prs = buf_rsrc(Pt, 0x7fffffff);
+    int xo[4], zo[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        xo[b] = (((int)sr0 + min(16 * b + i, rmax)) * kdim + 8 * g) * 2;
+        zo[b] = (((int)sc0 + min(16 * b + i, cmax)) * kdim + 8 * g) * 2;
+    }
+    const int nks = kdim / 32;
+    bf16x8 xq[4][4], zq[4][4];
+    auto fetch = [&](int slot, int kn) {
+        const int soff = (kn < nks ? kn : nks - 1) * 64;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            xq[slot][b] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(prs, xo[b], soff, 0));
+            zq[slot][b] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(prs, zo[b], soff, 0));
+        }
+    };
+    fetch(0, 0);
+    fetch(1, 1);
+    fetch(2, 2);
+    for (int ks = 0; ks < nks; ks += 4) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            fetch((s + 3) & 3, ks + s + 3);
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mma_xzt_bf16(acc[bi][bj], xq[s][bi], zq[s][bj]);
+        }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (c_in(bi, bj, r)) buf_st(-acc[bi][bj][r], crs, c_off(bi, bj, r), 0);
+}
+
+// ---------------------------------------------------------------------------
 // Host driver.
 // ---------------------------------------------------------------------------
 int64_t potrf_block_size(mg_handle_t h, int64_t n, int es) {
@@ -511,6 +627,20 @@ template <typename T>
 static mg_status trailing(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int64_t n, int64_t k0, int64_t nb,
                          const int32_t* info, int64_t j0, int64_t wj);
 
+// bfloat16 mode: the row-major bfloat16 copy of block column k0's panel
+// (block columns of 256 or 512 only; two buffers alternate between
+// consecutive block columns, so packing column k + 1 never overwrites the
+// copy that the update of column k is still reading), or null.
+template <typename T>
+static const __bf16* bf16_panel_of(mg_handle_t h, int64_t n, int64_t k0, int64_t nb, int64_t kb) {
+    if constexpr (sizeof(T) != 4) {
+        return nullptr;
+    } else {
+        if (h->trail_lo != 2 || !h->bf16_panel || kb != nb || nb % 256 != 0) return nullptr;
+        return (const __bf16*)h->bf16_panel + (size_t)((k0 / nb) & 1) * (size_t)n * 512;
+    }
+}
+
 // Block column [k0, k0 + nb) factored completely (diagonal block and the
 // panel below it).  For nb <= 256 this is one panel_step; for nb = 512 the
 // column is itself factored right-looking in two halves of 256: the second
@@ -528,6 +658,14 @@ static mg_status panel_block(mg_handle_t h, hipStream_t st, T* A, int64_t lda, i
         const int64_t rest = end - (k1 + nbi);
         if (rest > 0 && (rc = trailing<T>(h, st, A, lda, n, k1, nbi, info, 0, cdiv(rest, SY_BM)))) return rc;
     }
+    const __bf16* Pt = bf16_panel_of<T>(h, n, k0, nb, end - k0);
+    const int64_t m = n - end;
+    if (Pt && m > 0) {
+        const unsigned grid = (unsigned)std::min<int64_t>(cdiv(m * (nb / 8), 256), 8192);
+        hipLaunchKernelGGL(k_pack_bf16, dim3(grid), dim3(256), 0, st, (const float*)(A + idx(end, k0, lda)), lda, m,
+                           (int)nb, (__bf16*)Pt, info);
+        MG_LAUNCH_CHECK();
+    }
     return MG_OK;
 }
 
@@ -543,9 +681,18 @@ static mg_status trailing(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int6
     // rank-256/512 updates run the C-folding kernel variant, narrower ones the other
     const int kind = (kb % 256 == 0) ? MG_PROF_TRAILING : MG_PROF_TRAILING_NARROW;
     if ((rc = prof_begin(h, kind, st))) return rc;
-    if ((rc = syrk_lower_launch<T>(st, A + idx(e, e, lda), A + idx(e, k0, lda), lda, m, kb, info, j0, wj,
-                                   h->trail_lo == 2 ? 1 : 0)))
+    const __bf16* Pt = bf16_panel_of<T>(h, n, k0, nb, kb);
+    if (Pt) {
+        // bfloat16 mode, full block column: the panel was packed by panel_block
+        const int64_t ntiles = slab_tiles(T_, j0, wj);
+        if ((m + (int64_t)(kb + 64) * lda) * 4 >= ((int64_t)1 << 31) - 65536) return MG_ERR_UNSUPPORTED;
+        hipLaunchKernelGGL(k_syrk_lower_bf16, dim3((unsigned)(8 * cdiv(ntiles, 8))), dim3(256), 0, st,
+                           (float*)(A + idx(e, e, lda)), Pt, lda, m, (int)kb, j0, wj, info);
+        MG_LAUNCH_CHECK();
+    } else if ((rc = syrk_lower_launch<T>(st, A + idx(e, e, lda), A + idx(e, k0, lda), lda, m, kb, info, j0, wj,
+                                          h->trail_lo == 2 ? 1 : 0))) {
         return rc;
+    }
     // algorithmic work of this slab: columns c0..c1 of the lower triangle
     const double c0 = (double)std::min(m, j0 * SY_BM), c1 = (double)std::min(m, (j0 + wj) * SY_BM);
     const double md = (double)m, b = (double)kb;
