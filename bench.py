@@ -40,14 +40,15 @@ HBM_PEAK_GBS = 8000.0
 # the bytes moved, WRITE_SIZE all of them).  Valid only for the kernel source
 # it was measured on: reported as null once that source changes.
 SYRK_TRAFFIC = dict(fetch_kib=1863985.3, write_kib=699267.1, fetch_scale=2.0, write_scale=1.0,
-                    kernel_sha1="e650867552d16b4750d6b3d596a1068c20ba44bd")
+                    kernel_sha1="27a48ab921ed0e0a005f0108ed491441cba0650e")
 
 
 def syrk_traffic_bytes():
     import hashlib
     src = open(os.path.join(ROOT, "paper_2601_14466_amd", "csrc", "potrf.hip")).read()
-    a, b = src.find("template <typename S, bool FOLD>"), src.find("// Host driver.")
-    if a < 0 or b < 0 or hashlib.sha1(src[a:b].encode()).hexdigest() != SYRK_TRAFFIC["kernel_sha1"]:
+    a = src.find("template <typename S, bool FOLD>")
+    b = src.find("\n}\n", a) + 3 if a >= 0 else -1  # the kernel's text, through its closing brace
+    if a < 0 or b < 3 or hashlib.sha1(src[a:b].encode()).hexdigest() != SYRK_TRAFFIC["kernel_sha1"]:
         return None
     t = SYRK_TRAFFIC
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0

@@ -57,6 +57,27 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ double shfl(double v, int src) { return __shfl(v, src, 64); }
 __device__ __forceinline__ float shfl(float v, int src) { return __shfl(v, src, 64); }
 
+// Row broadcast: every lane (i, g) receives the value of lane (i, G), G a
+// wave-uniform lane group (rows of 16 lanes; a constant in the unrolled
+// loops that call it, so the selects fold away).  Two gfx950 lane swaps instead
+// of an LDS permute: permlane16_swap pairs rows 0/1 and 2/3, giving either
+// (R0 R0 R2 R2) or (R1 R1 R3 R3); permlane32_swap of that pairs the halves,
+// giving one row in all four.
+__device__ __forceinline__ unsigned rowbcast_u32(unsigned v, int G) {
+    const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    const unsigned x = (G & 1) ? a[1] : a[0];
+    const auto b = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return (G & 2) ? b[1] : b[0];
+}
+__device__ __forceinline__ float rowbcast(float v, int G) {
+    return __builtin_bit_cast(float, rowbcast_u32(__builtin_bit_cast(unsigned, v), G));
+}
+__device__ __forceinline__ double rowbcast(double v, int G) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = rowbcast_u32((unsigned)b, G), hi = rowbcast_u32((unsigned)(b >> 32), G);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Broadcast lane `src` (wave-uniform) through the scalar unit.
 __device__ __forceinline__ float readlane(float v, int src) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
@@ -125,7 +146,7 @@ __device__ __forceinline__ int factor16(V4<C>& y) {
         const C p = readlane(y[rc], gc * 16 + c);
         if (!(p > (C)0)) return c + 1;
         const C s = sqrt(p);
-        const C v = shfl(y[rc], gc * 16 + i);   // Y[i][c]
+        const C v = rowbcast(y[rc], gc);   // Y[i][c]
         const C lic = (i > c) ? v / s : (i == c ? s : (C)0);
         if (g == gc) y[rc] = lic;
 #pragma unroll
@@ -150,7 +171,7 @@ __device__ __forceinline__ void solve16s(V4<C>& y, const C* Lsc, const C* piv) {
 #pragma unroll
     for (int c = 0; c < 15; ++c) {
         const int gc = tgrp<C>(c), rc = treg<C>(c);
-        const C yc = shfl(y[rc], gc * 16 + i);  // (updated) Y[i][c]
+        const C yc = rowbcast(y[rc], gc);  // (updated) Y[i][c]
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int j = tcol<C>(g, r);
