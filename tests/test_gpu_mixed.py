@@ -107,16 +107,19 @@ def test_rhs_one_and_many(mg, orc):
         assert np.all(orc.backward_error(A, X, B) <= 1e-12), (nrhs, st)
 
 
-@pytest.mark.parametrize("n", [16384])
-def test_full_size_config2(mg, orc, n):
-    """A = Q diag(lambda) Q^T with Haar Q and cond 1e4, nrhs = 8 (the mixed
-    configuration), checked by the oracle's extended-precision residual."""
-    A = synth.torch_haar_spd(n, 1e4, 700 + n)
+@pytest.mark.parametrize("n,precision,cond", [(16384, "fp32", 1e4), (32768, "fp32", 1e4), (32768, "bf16", 1e2)])
+def test_full_size_config2(mg, orc, n, precision, cond):
+    """A = Q diag(lambda) Q^T with Haar Q, nrhs = 8 (the mixed configuration;
+    n = 32768 is the size the benchmark times, with the library's default
+    block size), checked by the oracle's extended-precision residual on every
+    column."""
+    A = synth.torch_haar_spd(n, cond, 700 + n)
     Xt = synth.torch_normal((n, 8), 701 + n)
     B = A @ Xt
-    X, st = mg.posv_mixed(A, B, precision="fp32")
+    X, st = mg.posv_mixed(A, B, precision=precision)
     torch.cuda.synchronize()
-    assert not st["fell_back"], st
+    assert not st["fell_back"] and st["info"] == 0 and st["lo_info"] == 0, st
+    assert st["iters"] <= (2 if precision == "fp32" else 8), st
     Ah = A.cpu().numpy()
     eta = orc.backward_error(Ah.T, X.cpu().numpy(), B.cpu().numpy())
     assert np.all(eta <= 1e-12), eta.max()
