@@ -60,9 +60,11 @@ mg_status mg_destroy(mg_handle_t handle);
 mg_status mg_set_stream(mg_handle_t handle, void *stream);
 
 /* potrf block size nb (the paper's tile size T_A).  0 selects the built-in
- * default for the problem size; otherwise nb must be one of 64, 128, 256,
- * 512.  With 512 each block column is factored as two halves of 256 and the
- * trailing matrix receives one rank-512 update per block column.
+ * default for the problem size; otherwise nb must be 64, 128, or a multiple
+ * of 256 up to 1024.  Blocks wider than 128 are factored in 128-wide steps
+ * (diagonal factor, panel solve, rank-128 update of the rest of the block
+ * column), and the trailing matrix receives one rank-nb update per block
+ * column.
  * Errors: -1 NULL handle, -2 unsupported nb. */
 mg_status mg_set_block_size(mg_handle_t handle, int64_t nb);
 /* Look-ahead schedule for potrf (default on): the trailing update of step k

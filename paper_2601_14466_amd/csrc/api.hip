@@ -99,7 +99,7 @@ mg_status mg_set_stream(mg_handle_t h, void* stream) {
 
 mg_status mg_set_block_size(mg_handle_t h, int64_t nb) {
     if (!h) return -1;
-    if (!(nb == 0 || nb == 64 || nb == 128 || nb == 256 || nb == 512)) return -2;
+    if (!(nb == 0 || nb == 64 || nb == 128 || (nb % 256 == 0 && nb >= 256 && nb <= 1024))) return -2;
     h->nb = nb;
     return MG_OK;
 }

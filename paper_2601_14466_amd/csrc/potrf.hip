@@ -636,7 +636,7 @@ static const __bf16* bf16_panel_of(mg_handle_t h, int64_t n, int64_t k0, int64_t
     if constexpr (sizeof(T) != 4) {
         return nullptr;
     } else {
-        if (h->trail_lo != 2 || !h->bf16_panel || kb != nb || nb % 256 != 0) return nullptr;
+        if (h->trail_lo != 2 || !h->bf16_panel || kb != nb || nb % 256 != 0 || nb > 512) return nullptr;
         return (const __bf16*)h->bf16_panel + (size_t)((k0 / nb) & 1) * (size_t)n * 512;
     }
 }

@@ -218,6 +218,24 @@ def test_fp32_posv(mg, orc, n):
     assert np.all(eta <= n * 2.0 ** -24), eta.max()
 
 
+# ------------------------------------------------ wide block columns
+@pytest.mark.parametrize("nb", [768, 1024])
+@pytest.mark.parametrize("n", [1100, 2600])
+def test_wide_block_columns(mg, orc, n, nb):
+    """Block columns of 768 / 1024 (factored in 128-wide steps, one rank-nb
+    trailing update each): integer family bitwise, random SPD by backward
+    error."""
+    L0, A = synth.integer_exact(n, 900 + n)
+    L, info = _potrf_np(mg, A, nb)
+    assert info == 0
+    assert np.array_equal(L, L0)
+    A = synth.gram_spd_cond(n, 901 + n, 1e4)
+    B = synth.normal((n, 3), 902 + n)
+    X, info = _posv_np(mg, A, B, nb)
+    assert info == 0
+    assert np.all(orc.backward_error(A, X, B) <= 1e-12)
+
+
 # ----------------------------------------------------------- look-ahead
 @pytest.mark.parametrize("n,nb", [(1000, 128), (2100, 256), (4100, 128), (2600, 512)])
 def test_lookahead_matches_serial_schedule_bitwise(mg, orc, n, nb):
