@@ -47,8 +47,13 @@ struct SweepSync {
 
 static size_t y_bytes(int64_t n, int64_t nrhs, int es) { return align_up((size_t)n * (size_t)nrhs * es, 256); }
 
+// right-hand sides are handled in passes of 16, all passes of a sweep in one
+// launch (grid y), each with its own sweep words
+constexpr int SW_NR = 16;
+__host__ __device__ inline int64_t sweep_passes(int64_t nrhs) { return (nrhs + SW_NR - 1) / SW_NR; }
+
 size_t potrs_work_bytes(int64_t n, int64_t nrhs, int es) {
-    return (n == 0 || nrhs == 0) ? 0 : y_bytes(n, nrhs, es) + 256;
+    return (n == 0 || nrhs == 0) ? 0 : y_bytes(n, nrhs, es) + align_up(2 * sweep_passes(nrhs) * 16, 256);
 }
 
 // Signalling NaNs (quiet bit clear, non-zero payload): never produced by
@@ -67,7 +72,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_sweep_init(T* Out, int64_t ld, int64_t n, int64_t nrhs, SweepSync* sy,
                                                     const int32_t* info) {
     if (info && *info != 0) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *sy = SweepSync{0, 0, {0, 0}};
+    if (blockIdx.x == 0)
+        for (int64_t k = threadIdx.x; k < sweep_passes(nrhs); k += blockDim.x) sy[k] = SweepSync{0, 0, {0, 0}};
     const int64_t tot = n * nrhs;
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256)
         Out[idx(e % n, e / n, ld)] = sentinel((T*)nullptr);
@@ -127,6 +133,8 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t 
     __shared__ int s_t;
     if (info && *info != 0) return;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, i = lane & 15, g = lane >> 4;
+    sy += blockIdx.y;  // this pass's words; it covers right-hand sides rc0 .. rc0 + NR - 1
+    const int64_t rc0 = (int64_t)blockIdx.y * NR;
     if (tid == 0) s_t = atomicAdd(&sy->ticket, 1);
     __syncthreads();
     const int t = s_t;
@@ -143,7 +151,7 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t 
     const int ndep = FWD ? bi : nblk - 1 - bi;
     bool abort = false;
     constexpr int XPT = JB * NR / 256;  // solution values each thread moves per block
-    for (int64_t rc0 = 0; rc0 < nrhs; rc0 += NR) {
+    {
         V4<T> acc[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) acc[rt] = V4<T>{0, 0, 0, 0};
@@ -253,25 +261,26 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t 
                 if (lane < jb && rc0 + q < nrhs) store_coherent(&Out[idx(r0 + lane, rc0 + q, ldo)], v[u] / pl);
             }
         }
-        __syncthreads();  // part is reused by the next pass
+
     }
 }
 
-template <typename T, int RT>
+template <typename T>
 static mg_status sweep(hipStream_t st, int64_t n, int64_t nrhs, const T* L, int64_t lda, T* B, int64_t ldb, T* Y,
                        SweepSync* sy, const int32_t* info) {
-    const unsigned nblk = (unsigned)cdiv(n, JB);
+    const int64_t np = sweep_passes(nrhs);
+    const dim3 grid((unsigned)cdiv(n, JB), (unsigned)np);
     const unsigned gfill = (unsigned)std::min<int64_t>(std::max<int64_t>(1, cdiv(n * nrhs, 256)), 2048);
     hipLaunchKernelGGL((k_sweep_init<T>), dim3(gfill), dim3(256), 0, st, Y, n, n, nrhs, sy, info);
     MG_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_sweep<T, RT, true>), dim3(nblk), dim3(256), 0, st, L, lda, n, nrhs, (const T*)B, ldb, Y,
-                       n, sy, info);
+    hipLaunchKernelGGL((k_sweep<T, 1, true>), grid, dim3(256), 0, st, L, lda, n, nrhs, (const T*)B, ldb, Y, n, sy,
+                       info);
     MG_LAUNCH_CHECK();
     // B has been read; it now receives X
-    hipLaunchKernelGGL((k_sweep_init<T>), dim3(gfill), dim3(256), 0, st, B, ldb, n, nrhs, sy + 1, info);
+    hipLaunchKernelGGL((k_sweep_init<T>), dim3(gfill), dim3(256), 0, st, B, ldb, n, nrhs, sy + np, info);
     MG_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_sweep<T, RT, false>), dim3(nblk), dim3(256), 0, st, L, lda, n, nrhs, (const T*)Y, n, B,
-                       ldb, sy + 1, info);
+    hipLaunchKernelGGL((k_sweep<T, 1, false>), grid, dim3(256), 0, st, L, lda, n, nrhs, (const T*)Y, n, B, ldb,
+                       sy + np, info);
     MG_LAUNCH_CHECK();
     return MG_OK;
 }
@@ -284,9 +293,7 @@ mg_status potrs_impl(mg_handle_t h, int64_t n, int64_t nrhs, const T* L, int64_t
     mg_status rc;
     if ((rc = prof_begin(h, MG_PROF_SOLVE, st))) return rc;
     SweepSync* sy = (SweepSync*)((char*)Y + y_bytes(n, nrhs, (int)sizeof(T)));
-    if (nrhs <= 16) rc = sweep<T, 1>(st, n, nrhs, L, lda, B, ldb, Y, sy, info);
-    else if (nrhs <= 32) rc = sweep<T, 2>(st, n, nrhs, L, lda, B, ldb, Y, sy, info);
-    else rc = sweep<T, 4>(st, n, nrhs, L, lda, B, ldb, Y, sy, info);
+    rc = sweep<T>(st, n, nrhs, L, lda, B, ldb, Y, sy, info);
     if (rc) return rc;
     const double nd = (double)n;
     return prof_end(h, MG_PROF_SOLVE, 2.0 * nd * nd * (double)nrhs,
