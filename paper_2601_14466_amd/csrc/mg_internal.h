@@ -23,7 +23,7 @@ struct mg_handle_s {
     int lookahead = 1;       // 0 serial; 1 look-ahead; 2 look-ahead with one CU per XCD kept for the panel
     int side_mode = 0;       // look-ahead mode the bulk stream was created for
     int trail_lo = 1;        // FP32 trailing update: 1 plain, 2 operands rounded to bfloat16
-    void* bf16_panel = nullptr;  // bfloat16 mode: two n x 512 row-major panel buffers
+    void* bf16_panel = nullptr;  // bfloat16 mode: three n x 512 row-major panel buffers
     int profiling = 0;
     mg_prof_counter prof[MG_PROF_KINDS];
     // second stream and events for the look-ahead schedule (created on first use)
@@ -60,7 +60,7 @@ mg_status potrs_impl(mg_handle_t h, int64_t n, int64_t nrhs, const T* L, int64_t
                      int64_t ldb, T* ywork, const int32_t* info);
 size_t potrs_work_bytes(int64_t n, int64_t nrhs, int es);
 size_t mixed_work_bytes(int64_t n, int64_t nrhs, int fallback, int lo);
-inline size_t bf16_panel_bytes(int64_t n) { return 2 * (size_t)n * 512 * 2; }
+inline size_t bf16_panel_bytes(int64_t n) { return 3 * (size_t)n * 512 * 2; }
 mg_status posv_backward_impl(mg_handle_t h, int64_t n, int64_t nrhs, const double* L, int64_t lda,
                              const double* X, int64_t ldx, const double* GX, int64_t ldgx, double* GB,
                              int64_t ldgb, double* GA, int64_t ldga, int mode, void* work, const int32_t* info);

@@ -5,7 +5,7 @@
 // Step k of the factorisation (block columns of width nb):
 //   1. k_factor_block : L_kk = chol(A_kk), one workgroup, FP64 arithmetic.
 //   2. k_trsm_panel   : L_ik = A_ik L_kk^{-T} for the m = n - (k+1) nb rows
-//                       below, one wave per 16 rows, MFMA + shuffle solves.
+//                       below, one wave per 32 rows, MFMA + shuffle solves.
 //   3. k_syrk_lower   : lower(A_22) -= L_ik L_ik^T, FP64 MFMA on 128 x 128
 //                       tiles (about n^3/3 of the n^3/3 + O(n^2) flops).
 #include <algorithm>
@@ -189,12 +189,14 @@ __global__ __launch_bounds__(64 * W) void k_factor_block(S* __restrict__ A, int6
 // lower, NB <= FB_MAX).  The NB/16 (NB/16 + 1)/2 lower 16 x 16 tiles of L_kk
 // are staged once per workgroup in LDS (diagonal tiles pre-scaled by their
 // pivots), laid out so that each MFMA operand is one conflict-free LDS read.
-// Each wave owns 16 panel rows and keeps their NB/16 tiles in registers:
-// tile t receives -X_p L_tp^T from every solved tile p < t (the k index of
-// step ks in lane group g is tcol(g, ks), exactly the column tile p keeps in
-// its register ks, so that operand comes straight from registers), then is
-// solved against L_tt by substitution (solve16s).  Exact for integer data
-// with power-of-two pivots.
+// Each wave owns 32 panel rows, two 16-row blocks whose NB/16 tiles it keeps
+// in registers and carries through the same steps side by side (the solve
+// is a chain of dependent latencies; two independent chains fill each
+// other's stalls): tile t receives -X_p L_tp^T from every solved tile p < t
+// (the k index of step ks in lane group g is tcol(g, ks), exactly the column
+// tile p keeps in its register ks, so that operand comes straight from
+// registers), then is solved against L_tt by substitution (solve16s2).
+// Exact for integer data with power-of-two pivots.
 // ---------------------------------------------------------------------------
 template <typename S, int NB>
 __global__ __launch_bounds__(256) void k_trsm_panel(S* __restrict__ P, const S* __restrict__ Lkk,
@@ -219,24 +221,35 @@ __global__ __launch_bounds__(256) void k_trsm_panel(S* __restrict__ P, const S* 
         Lt[tt][rr * 17 + cc] = v;
     }
     __syncthreads();
+    // each wave solves two 16-row blocks side by side (rows R and R + 16)
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, g = l >> 4;
-    const int64_t R = ((int64_t)blockIdx.x * 4 + w) * 16;
+    const int64_t R = ((int64_t)blockIdx.x * 4 + w) * 32;
     if (R >= m) return;
-    V4<S> x[NT];
+    V4<S> x[NT], u[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) load_tile<S, S>(x[t], P, lda, R, 16 * t, m, NB, false, false);
+    for (int t = 0; t < NT; ++t) {
+        load_tile<S, S>(x[t], P, lda, R, 16 * t, m, NB, false, false);
+        load_tile<S, S>(u[t], P, lda, R + 16, 16 * t, m, NB, false, false);  // rows past m load as 0
+    }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
 #pragma unroll
         for (int p = 0; p < t; ++p) {
             const S* Z = Lt[t * (t + 1) / 2 + p] + i * 17;
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) x[t] = mma_xzt(x[t], x[p][ks], -Z[tcol<S>(g, ks)]);
+            for (int ks = 0; ks < 4; ++ks) {
+                const S zv = -Z[tcol<S>(g, ks)];
+                x[t] = mma_xzt(x[t], x[p][ks], zv);
+                u[t] = mma_xzt(u[t], u[p][ks], zv);
+            }
         }
-        solve16s<S, 17>(x[t], Lt[t * (t + 1) / 2 + t], Pv[t]);
+        solve16s2<S, 17>(x[t], u[t], Lt[t * (t + 1) / 2 + t], Pv[t]);
     }
 #pragma unroll
-    for (int t = 0; t < NT; ++t) store_tile<S, S>(x[t], P, lda, R, 16 * t, m, NB, false);
+    for (int t = 0; t < NT; ++t) {
+        store_tile<S, S>(x[t], P, lda, R, 16 * t, m, NB, false);
+        store_tile<S, S>(u[t], P, lda, R + 16, 16 * t, m, NB, false);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -255,8 +268,8 @@ __global__ __launch_bounds__(256) void k_trsm_panel(S* __restrict__ P, const S* 
 // (binary32 storage only) each operand is rounded to bfloat16 before its
 // MFMA, so the products are those of bfloat16 inputs accumulated in FP32.
 // Tile order is XCD-aware: workgroup b runs on XCD b % 8, and each XCD
-// receives a contiguous run of row-major tiles so that the panel rows they
-// share stay in its L2.
+// receives a contiguous run of tiles, numbered so that the workgroups it
+// holds at once share panel rows in its L2.
 // ---------------------------------------------------------------------------
 constexpr int SY_BM = 128;
 
@@ -287,6 +300,57 @@ __host__ __device__ __forceinline__ void slab_tile_coords(int64_t t, int64_t j0,
     }
     I += j0;
     J += j0;
+}
+
+// The whole lower triangle of a TT x TT tile grid in grouped order: bands of
+// SY_GROUP tile rows; inside a band, its full columns of SY_GROUP tiles come
+// first (column by column), then the band's own diagonal triangle (row by
+// row).  Workgroups resident together on one XCD then cover a square patch
+// of the triangle and share both its panel row blocks and its panel column
+// blocks in L2, instead of one row block and many column blocks.
+constexpr int SY_GROUP = 8;
+struct TileIJ {
+    int64_t I, J;
+};
+__host__ __device__ __forceinline__ int64_t band_start(int64_t b) {
+    return (int64_t)SY_GROUP * SY_GROUP * b * (b - 1) / 2 + b * (int64_t)(SY_GROUP * (SY_GROUP + 1) / 2);
+}
+__host__ __device__ __forceinline__ TileIJ grouped_tile_coords(int64_t t, int64_t TT) {
+    constexpr double G = SY_GROUP;
+    int64_t b = (int64_t)((sqrt((G + 1) * (G + 1) / 4 + 2.0 * (double)t) - (G + 1) / 2) / G);
+    if (b < 0) b = 0;
+    while (b > 0 && band_start(b) > t) --b;
+    while (band_start(b + 1) <= t) ++b;
+    const int64_t u = t - band_start(b), r0 = b * SY_GROUP, h = TT - r0 < SY_GROUP ? TT - r0 : SY_GROUP;
+    if (u < h * r0) return {r0 + u % h, u / h};
+    int64_t I, J;
+    lower_tile_coords(u - h * r0, I, J);
+    return {r0 + I, r0 + J};
+}
+
+// Tile t of the trailing update over tile columns [j0, j0 + wj) of a T x T
+// grid: grouped order when the slab is the whole remaining triangle (the
+// large updates), row order for narrow slabs (whose few column blocks stay
+// in L2 anyway).
+__host__ __device__ __forceinline__ TileIJ trailing_tile_coords(int64_t t, int64_t T, int64_t j0, int64_t wj) {
+    TileIJ c;
+    if (wj >= T - j0) {
+        c = grouped_tile_coords(t, T - j0);
+        c.I += j0;
+        c.J += j0;
+    } else {
+        slab_tile_coords(t, j0, wj, c.I, c.J);
+    }
+    return c;
+}
+
+// The same on the device, with the result held in scalar registers: the
+// inputs are uniform, and making that explicit keeps the tile's buffer
+// resources scalar (tile indices stay below 2^31).
+__device__ __forceinline__ void trailing_tile(int64_t t, int64_t T, int64_t j0, int64_t wj, int64_t& I, int64_t& J) {
+    const TileIJ c = trailing_tile_coords(t, T, j0, wj);
+    I = __builtin_amdgcn_readfirstlane((int)c.I);
+    J = __builtin_amdgcn_readfirstlane((int)c.J);
 }
 
 // bfloat16 rounding (nearest-even on the bit pattern) of a binary32 value,
@@ -332,7 +396,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_lower(S* __restrict__ Cm, const
     const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (t >= ntiles) return;
     int64_t I, J;
-    slab_tile_coords(t, j0, wj, I, J);
+    trailing_tile(t, T, j0, wj, I, J);
     constexpr int ES = (int)sizeof(S);
     const int tid = threadIdx.x, l = tid & 63, i = l & 15, g = l >> 4;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -485,7 +549,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_lower_bf16(float* __restrict__ 
     const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (t >= ntiles) return;
     int64_t I, J;
-    slab_tile_coords(t, j0, wj, I, J);
+    trailing_tile(t, T, j0, wj, I, J);
     constexpr int ES = 4;
     const int tid = threadIdx.x, l = tid & 63, i = l & 15, g = l >> 4;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -571,7 +635,7 @@ int64_t potrf_block_size(mg_handle_t h, int64_t n, int es) {
 template <typename S>
 static mg_status launch_trsm(hipStream_t st, int64_t nb, S* P, const S* Lkk, int64_t lda, int64_t m,
                              const int32_t* info) {
-    const dim3 grid((unsigned)cdiv(m, 64)), block(256);
+    const dim3 grid((unsigned)cdiv(m, 128)), block(256);  // 4 waves x 32 rows
     switch (nb) {
         case 64: hipLaunchKernelGGL((k_trsm_panel<S, 64>), grid, block, 0, st, P, Lkk, lda, m, info); break;
         case 128: hipLaunchKernelGGL((k_trsm_panel<S, 128>), grid, block, 0, st, P, Lkk, lda, m, info); break;
@@ -628,16 +692,17 @@ static mg_status trailing(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int6
                          const int32_t* info, int64_t j0, int64_t wj);
 
 // bfloat16 mode: the row-major bfloat16 copy of block column k0's panel
-// (block columns of 256 or 512 only; two buffers alternate between
-// consecutive block columns, so packing column k + 1 never overwrites the
-// copy that the update of column k is still reading), or null.
+// (block columns of 256 or 512 only), or null.  Three buffers rotate over
+// consecutive block columns: the chain stream packs column k + 3 only after
+// waiting for the update stream's rest_a(k + 1), which that stream runs after
+// rest_b(k), the last reader of column k's copy.
 template <typename T>
 static const __bf16* bf16_panel_of(mg_handle_t h, int64_t n, int64_t k0, int64_t nb, int64_t kb) {
     if constexpr (sizeof(T) != 4) {
         return nullptr;
     } else {
         if (h->trail_lo != 2 || !h->bf16_panel || kb != nb || nb % 256 != 0 || nb > 512) return nullptr;
-        return (const __bf16*)h->bf16_panel + (size_t)((k0 / nb) & 1) * (size_t)n * 512;
+        return (const __bf16*)h->bf16_panel + (size_t)((k0 / nb) % 3) * (size_t)n * 512;
     }
 }
 
@@ -756,14 +821,19 @@ mg_status potrf_impl(mg_handle_t h, int64_t n, T* A, int64_t lda, int32_t* info)
     }
     // Look-ahead: a chain stream updates the next block column with panel k,
     // then factors it and solves its panel while the second stream applies
-    // panel k to everything to the right of that column:
+    // panel k to everything to the right of that column, the block column
+    // after next first:
     //   chain : wait(ev_rest) -> next(k) -> [ev_panel] -> panel(k+1)
-    //   side  : wait(ev_panel) -> rest(k) -> [ev_rest]
-    // The remainder is released only once next(k) is done, so the one-
-    // workgroup diagonal factor of block k+1 becomes runnable together with
-    // it and is dispatched before the remainder's workgroups fill the chip.
-    // Both streams are the handle's own, non-blocking, and fork from / join
-    // into the caller's stream by events.
+    //   side  : wait(ev_panel) -> rest_a(k) -> [ev_rest] -> rest_b(k)
+    // next(k+1) writes only block column k+2, which rest_a(k) finishes, so
+    // the chain resumes while rest_b(k) still runs and the update stream
+    // never idles on it.  The remainder is released only once next(k) is
+    // done, so the one-workgroup diagonal factor of block k+1 becomes
+    // runnable together with it and is dispatched before the remainder's
+    // workgroups fill the chip.  Both streams are the handle's own,
+    // non-blocking, and fork from / join into the caller's stream by events
+    // (the side stream's last work precedes the chain's last ev_rest wait
+    // or, for the final step, is empty).
     if ((rc = ensure_side(h))) return rc;
     hipStream_t ch = h->chain;
     MG_HIP(hipEventRecord(h->ev_fork, st));
@@ -775,11 +845,14 @@ mg_status potrf_impl(mg_handle_t h, int64_t n, T* A, int64_t lda, int32_t* info)
         if ((rc = trailing<T>(h, ch, A, lda, n, k0, nb, info, 0, wnext))) return rc;
         MG_HIP(hipEventRecord(h->ev_panel, ch));             // panel k applied to block column k+1
         MG_HIP(hipStreamWaitEvent(h->side, h->ev_panel, 0));
-        if ((rc = trailing<T>(h, h->side, A, lda, n, k0, nb, info, wnext, -1))) return rc;
+        if ((rc = trailing<T>(h, h->side, A, lda, n, k0, nb, info, wnext, wnext))) return rc;
+        MG_HIP(hipEventRecord(h->ev_rest, h->side));         // block column k+2 has every update but panel k+1's
+        if ((rc = trailing<T>(h, h->side, A, lda, n, k0, nb, info, 2 * wnext, -1))) return rc;
         if ((rc = panel_block<T>(h, ch, A, lda, n, k0 + nb, nb, info))) return rc;
-        MG_HIP(hipEventRecord(h->ev_rest, h->side));         // rest(k) done
         MG_HIP(hipStreamWaitEvent(ch, h->ev_rest, 0));
     }
+    MG_HIP(hipEventRecord(h->ev_rest, h->side));             // the side stream's last rest_b
+    MG_HIP(hipStreamWaitEvent(ch, h->ev_rest, 0));
     MG_HIP(hipEventRecord(h->ev_join, ch));
     MG_HIP(hipStreamWaitEvent(st, h->ev_join, 0));
     return MG_OK;

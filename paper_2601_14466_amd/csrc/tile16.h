@@ -182,6 +182,33 @@ __device__ __forceinline__ void solve16s(V4<C>& y, const C* Lsc, const C* piv) {
     for (int r = 0; r < 4; ++r) y[r] = y[r] / piv[tcol<C>(g, r)];
 }
 
+// solve16s on two independent tiles at once (same L): their dependency
+// chains interleave, so one wave hides most of the latency of either.
+template <typename C, int LDL>
+__device__ __forceinline__ void solve16s2(V4<C>& y, V4<C>& u, const C* Lsc, const C* piv) {
+    const int l = lane_id(), g = (l & 63) >> 4;
+#pragma unroll
+    for (int c = 0; c < 15; ++c) {
+        const int gc = tgrp<C>(c), rc = treg<C>(c);
+        const C yc = rowbcast(y[rc], gc), uc = rowbcast(u[rc], gc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = tcol<C>(g, r);
+            if (j > c) {
+                const C lv = Lsc[j * LDL + c];
+                y[r] = y[r] - yc * lv;
+                u[r] = u[r] - uc * lv;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const C pv = piv[tcol<C>(g, r)];
+        y[r] = y[r] / pv;
+        u[r] = u[r] / pv;
+    }
+}
+
 // Column-scaled copy of a lower-triangular 16x16 L held in LDS (Ls, row-major
 // with leading dimension LDL): Lsc(j,c) = L(j,c)/L(c,c) for j > c, 0
 // elsewhere; piv[c] = L(c,c).  One thread per entry; callers synchronise.
