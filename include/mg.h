@@ -285,6 +285,10 @@ mg_status mg_logdet(mg_handle_t handle, mg_dtype dtype, int64_t n, const void *L
  * mg_profile_query synchronises on the last recorded event, returns the
  * summed event time (ms), the number of launches and the summed flops and
  * algorithmic bytes, and resets the counter when reset != 0.
+ * mg_set_profiling switches every kind on (enable != 0) or off;
+ * mg_set_profiling_kinds selects kinds by bit mask (bit k = kind k), so that
+ * a timed run can bracket one kernel kind without adding events to the
+ * latency-bound look-ahead chain.
  */
 #define MG_PROF_TRAILING 0
 #define MG_PROF_DIAG 1
@@ -296,6 +300,8 @@ mg_status mg_logdet(mg_handle_t handle, mg_dtype dtype, int64_t n, const void *L
 #define MG_PROF_KINDS 7
 /* Errors: -1 NULL handle. */
 mg_status mg_set_profiling(mg_handle_t handle, int32_t enable);
+/* Errors: -1 NULL handle, -2 a bit at or above MG_PROF_KINDS. */
+mg_status mg_set_profiling_kinds(mg_handle_t handle, uint32_t kinds);
 /* Errors: -1 NULL handle, -2 bad kind, -3..-6 NULL outputs. */
 mg_status mg_profile_query(mg_handle_t handle, int32_t kind, double *total_ms, int64_t *launches,
                            double *flops, double *bytes, int32_t reset);

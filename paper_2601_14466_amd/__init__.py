@@ -71,8 +71,13 @@ class Handle:
         call("mg_get_block_size", self.h, dtype_code, int(n), ctypes.byref(out))
         return out.value
 
-    def set_profiling(self, on: bool):
-        call("mg_set_profiling", self.h, 1 if on else 0)
+    def set_profiling(self, on: bool, kinds=None):
+        """Bracket launches with events: every kind (on=True), none, or the
+        kinds listed in `kinds` (MG_PROF_* values)."""
+        if kinds is None:
+            call("mg_set_profiling", self.h, 1 if on else 0)
+        else:
+            call("mg_set_profiling_kinds", self.h, sum(1 << int(k) for k in kinds) if on else 0)
 
     def profile(self, kind: int, reset: bool = True):
         ms, cnt, fl, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()

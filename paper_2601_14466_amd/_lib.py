@@ -58,6 +58,7 @@ SIGNATURES = {
     "mg_batch_plan_destroy": (i32, [vp]),
     "mg_logdet": (i32, [vp, i32, i64, vp, i64, vp, vp]),
     "mg_set_profiling": (i32, [vp, i32]),
+    "mg_set_profiling_kinds": (i32, [vp, ctypes.c_uint32]),
     "mg_profile_query": (i32, [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                ctypes.POINTER(dbl), i32]),
 }

@@ -11,7 +11,7 @@ using namespace mg;
 namespace mg {
 
 mg_status prof_begin(mg_handle_t h, int kind, hipStream_t st) {
-    if (!h->profiling) return MG_OK;
+    if (!((h->profiling >> kind) & 1u)) return MG_OK;
     mg_prof_counter& pc = h->prof[kind];
     if (pc.used == pc.start.size()) {
         hipEvent_t a, b;
@@ -25,7 +25,7 @@ mg_status prof_begin(mg_handle_t h, int kind, hipStream_t st) {
 }
 
 mg_status prof_end(mg_handle_t h, int kind, double flops, double bytes, hipStream_t st) {
-    if (!h->profiling) return MG_OK;
+    if (!((h->profiling >> kind) & 1u)) return MG_OK;
     mg_prof_counter& pc = h->prof[kind];
     MG_HIP(hipEventRecord(pc.stop[pc.used], st));
     ++pc.used;
@@ -260,7 +260,14 @@ mg_status mg_logdet(mg_handle_t h, mg_dtype dt, int64_t n, const void* L, int64_
 
 mg_status mg_set_profiling(mg_handle_t h, int32_t enable) {
     if (!h) return -1;
-    h->profiling = enable ? 1 : 0;
+    h->profiling = enable ? (1u << MG_PROF_KINDS) - 1u : 0u;
+    return MG_OK;
+}
+
+mg_status mg_set_profiling_kinds(mg_handle_t h, uint32_t kinds) {
+    if (!h) return -1;
+    if (kinds >> MG_PROF_KINDS) return -2;
+    h->profiling = kinds;
     return MG_OK;
 }
 

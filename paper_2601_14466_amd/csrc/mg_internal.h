@@ -24,7 +24,7 @@ struct mg_handle_s {
     int side_mode = 0;       // look-ahead mode the bulk stream was created for
     int trail_lo = 1;        // FP32 trailing update: 1 plain, 2 operands rounded to bfloat16
     void* bf16_panel = nullptr;  // bfloat16 mode: three n x 512 row-major panel buffers
-    int profiling = 0;
+    uint32_t profiling = 0;  // bit k set: launches of kind k are bracketed by events
     mg_prof_counter prof[MG_PROF_KINDS];
     // second stream and events for the look-ahead schedule (created on first use)
     hipStream_t side = nullptr;   // look-ahead: bulk trailing update

@@ -5,7 +5,7 @@
 // Step k of the factorisation (block columns of width nb):
 //   1. k_factor_block : L_kk = chol(A_kk), one workgroup, FP64 arithmetic.
 //   2. k_trsm_panel   : L_ik = A_ik L_kk^{-T} for the m = n - (k+1) nb rows
-//                       below, one wave per 32 rows, MFMA + shuffle solves.
+//                       below, one wave per 16 or 32 rows, MFMA + shuffle solves.
 //   3. k_syrk_lower   : lower(A_22) -= L_ik L_ik^T, FP64 MFMA on 128 x 128
 //                       tiles (about n^3/3 of the n^3/3 + O(n^2) flops).
 #include <algorithm>
@@ -189,16 +189,16 @@ __global__ __launch_bounds__(64 * W) void k_factor_block(S* __restrict__ A, int6
 // lower, NB <= FB_MAX).  The NB/16 (NB/16 + 1)/2 lower 16 x 16 tiles of L_kk
 // are staged once per workgroup in LDS (diagonal tiles pre-scaled by their
 // pivots), laid out so that each MFMA operand is one conflict-free LDS read.
-// Each wave owns 32 panel rows, two 16-row blocks whose NB/16 tiles it keeps
-// in registers and carries through the same steps side by side (the solve
-// is a chain of dependent latencies; two independent chains fill each
-// other's stalls): tile t receives -X_p L_tp^T from every solved tile p < t
+// Each wave owns RB (1 or 2) 16-row blocks of the panel, whose NB/16 tiles
+// it keeps in registers and carries through the same steps side by side
+// (the solve is a chain of dependent latencies; two independent chains fill
+// each other's stalls): tile t receives -X_p L_tp^T from every solved tile p < t
 // (the k index of step ks in lane group g is tcol(g, ks), exactly the column
 // tile p keeps in its register ks, so that operand comes straight from
-// registers), then is solved against L_tt by substitution (solve16s2).
+// registers), then is solved against L_tt by substitution (solve16s / solve16s2).
 // Exact for integer data with power-of-two pivots.
 // ---------------------------------------------------------------------------
-template <typename S, int NB>
+template <typename S, int NB, int RB>
 __global__ __launch_bounds__(256) void k_trsm_panel(S* __restrict__ P, const S* __restrict__ Lkk,
                                                     int64_t lda, int64_t m, const int32_t* info) {
     constexpr int NT = NB / 16, NTT = NT * (NT + 1) / 2;
@@ -221,15 +221,16 @@ __global__ __launch_bounds__(256) void k_trsm_panel(S* __restrict__ P, const S* 
         Lt[tt][rr * 17 + cc] = v;
     }
     __syncthreads();
-    // each wave solves two 16-row blocks side by side (rows R and R + 16)
+    // each wave solves RB 16-row blocks side by side (rows R and R + 16)
+    static_assert(RB == 1 || RB == 2, "one or two row blocks per wave");
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, g = l >> 4;
-    const int64_t R = ((int64_t)blockIdx.x * 4 + w) * 32;
+    const int64_t R = ((int64_t)blockIdx.x * 4 + w) * 16 * RB;
     if (R >= m) return;
     V4<S> x[NT], u[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         load_tile<S, S>(x[t], P, lda, R, 16 * t, m, NB, false, false);
-        load_tile<S, S>(u[t], P, lda, R + 16, 16 * t, m, NB, false, false);  // rows past m load as 0
+        if constexpr (RB == 2) load_tile<S, S>(u[t], P, lda, R + 16, 16 * t, m, NB, false, false);  // rows past m load as 0
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -240,15 +241,16 @@ __global__ __launch_bounds__(256) void k_trsm_panel(S* __restrict__ P, const S* 
             for (int ks = 0; ks < 4; ++ks) {
                 const S zv = -Z[tcol<S>(g, ks)];
                 x[t] = mma_xzt(x[t], x[p][ks], zv);
-                u[t] = mma_xzt(u[t], u[p][ks], zv);
+                if constexpr (RB == 2) u[t] = mma_xzt(u[t], u[p][ks], zv);
             }
         }
-        solve16s2<S, 17>(x[t], u[t], Lt[t * (t + 1) / 2 + t], Pv[t]);
+        if constexpr (RB == 2) solve16s2<S, 17>(x[t], u[t], Lt[t * (t + 1) / 2 + t], Pv[t]);
+        else solve16s<S, 17>(x[t], Lt[t * (t + 1) / 2 + t], Pv[t]);
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         store_tile<S, S>(x[t], P, lda, R, 16 * t, m, NB, false);
-        store_tile<S, S>(u[t], P, lda, R + 16, 16 * t, m, NB, false);
+        if constexpr (RB == 2) store_tile<S, S>(u[t], P, lda, R + 16, 16 * t, m, NB, false);
     }
 }
 
@@ -632,15 +634,22 @@ int64_t potrf_block_size(mg_handle_t h, int64_t n, int es) {
     return 64;
 }
 
+constexpr int64_t TRSM_TWO_ROWS = 12288;  // panel rows from which waves take two row blocks
+
 template <typename S>
 static mg_status launch_trsm(hipStream_t st, int64_t nb, S* P, const S* Lkk, int64_t lda, int64_t m,
                              const int32_t* info) {
-    const dim3 grid((unsigned)cdiv(m, 128)), block(256);  // 4 waves x 32 rows
-    switch (nb) {
-        case 64: hipLaunchKernelGGL((k_trsm_panel<S, 64>), grid, block, 0, st, P, Lkk, lda, m, info); break;
-        case 128: hipLaunchKernelGGL((k_trsm_panel<S, 128>), grid, block, 0, st, P, Lkk, lda, m, info); break;
-        default: return MG_ERR_UNSUPPORTED;
-    }
+    // Tall panels (the look-ahead regime, where the solve shares the chip
+    // with the trailing update) take two row blocks per wave, halving the
+    // wave-time the solve holds; short ones one, for the shortest latency.
+    const dim3 block(256);
+    const bool two = m >= TRSM_TWO_ROWS;
+    const dim3 grid((unsigned)cdiv(m, two ? 128 : 64));
+    if (nb == 64 && two) hipLaunchKernelGGL((k_trsm_panel<S, 64, 2>), grid, block, 0, st, P, Lkk, lda, m, info);
+    else if (nb == 64) hipLaunchKernelGGL((k_trsm_panel<S, 64, 1>), grid, block, 0, st, P, Lkk, lda, m, info);
+    else if (nb == 128 && two) hipLaunchKernelGGL((k_trsm_panel<S, 128, 2>), grid, block, 0, st, P, Lkk, lda, m, info);
+    else if (nb == 128) hipLaunchKernelGGL((k_trsm_panel<S, 128, 1>), grid, block, 0, st, P, Lkk, lda, m, info);
+    else return MG_ERR_UNSUPPORTED;
     MG_LAUNCH_CHECK();
     return MG_OK;
 }

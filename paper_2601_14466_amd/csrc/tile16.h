@@ -131,12 +131,40 @@ __device__ __forceinline__ void store_tile(const V4<C>& y, S* M, int64_t ld, int
     }
 }
 
+// p^(-1/2) for p > 0: the hardware estimate refined by two Newton steps on
+// FMAs (y += y/2 (1 - p y^2)), within one unit in the last place; exact when
+// p is an even power of two (the Newton residual is then exact and the step
+// lands on 2^-k).  Replaces a square root followed by a division on the
+// factor's critical path.
+__device__ __forceinline__ double rsqrt_nr(double p) {
+    double y = __builtin_amdgcn_rsq(p);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double py = p * y;
+        y = __builtin_fma(0.5 * y, __builtin_fma(-py, y, 1.0), y);
+    }
+    return y;
+}
+__device__ __forceinline__ float rsqrt_nr(float p) {
+    float y = __builtin_amdgcn_rsqf(p);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const float py = p * y;
+        y = __builtin_fmaf(0.5f * y, __builtin_fmaf(-py, y, 1.0f), y);
+    }
+    return y;
+}
+
 // In-register Cholesky of a 16x16 SPD tile (lower part significant).  Column
-// by column: the pivot is broadcast by a lane shuffle, column c is divided by
-// its square root, and the columns to its right receive the rank-1 update.
-// Returns 0, or c+1 for the first local column whose pivot is not > 0 (NaN
-// included); the decision is uniform across the wave.  Entries above the
-// diagonal are left unspecified.
+// by column: the pivot p is read from its lane, column c is scaled by
+// p^(-1/2) (its diagonal entry becomes p p^(-1/2)), and the columns to its
+// right receive the rank-1 update; the lane shuffles that fetch L[j][c] are
+// issued starting with the register that holds column c + 1, the next step's
+// dependency.  Returns 0, or c+1 for the first local column whose pivot is
+// not > 0 (NaN included); the decision is uniform across the wave.  Entries
+// above the diagonal are left unspecified.  (The per-column exit also keeps
+// the compiler from scheduling across columns, which measured faster when
+// the factor shares its SIMDs with the trailing update.)
 template <typename C>
 __device__ __forceinline__ int factor16(V4<C>& y) {
     const int l = lane_id(), i = l & 15, g = l >> 4;
@@ -145,12 +173,14 @@ __device__ __forceinline__ int factor16(V4<C>& y) {
         const int gc = tgrp<C>(c), rc = treg<C>(c);
         const C p = readlane(y[rc], gc * 16 + c);
         if (!(p > (C)0)) return c + 1;
-        const C s = sqrt(p);
+        const C rs = rsqrt_nr(p);
         const C v = rowbcast(y[rc], gc);   // Y[i][c]
-        const C lic = (i > c) ? v / s : (i == c ? s : (C)0);
+        const C lic = (i > c) ? v * rs : (i == c ? p * rs : (C)0);
         if (g == gc) y[rc] = lic;
+        const int rn = c < 15 ? treg<C>(c + 1) : 0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int q = 0; q < 4; ++q) {
+            const int r = (rn + q) & 3;
             const int j = tcol<C>(g, r);
             const C ljc = shfl(lic, j);         // L[j][c] sits in lane j (group 0)
             if (j > c) y[r] = y[r] - lic * ljc;
