@@ -151,14 +151,23 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t 
     const int ndep = FWD ? bi : nblk - 1 - bi;
     bool abort = false;
     constexpr int XPT = JB * NR / 256;  // solution values each thread moves per block
-    {
-        V4<T> acc[RT];
+    // this block's right-hand sides (a lane per row, wave w takes q = w + 4 u),
+    // requested now so that their latency is off the critical path
+    T vin[QW];
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt] = V4<T>{0, 0, 0, 0};
+    for (int u = 0; u < QW; ++u) {
+        const int q = w + 4 * u;
+        vin[u] = (lane < jb && rc0 + q < nrhs) ? In[idx(r0 + lane, rc0 + q, ldi)] : (T)0;
+    }
+    {
+        // two accumulators (even and odd k-steps) halve the chain of
+        // dependent MFMAs after the last dependency arrives
+        V4<T> acc[RT], acc2[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[rt] = acc2[rt] = V4<T>{0, 0, 0, 0};
         // Software pipeline over the dependency blocks: the L values (per
         // lane, one per k-step) and the solution values of block d + 1 are
-        // requested before block d is multiplied, so memory latency is paid
-        // once per sweep step, not once per block.
+        // requested before block d is multiplied.
         T lc[JB / 4], ln[JB / 4], xc[XPT], xn[XPT];
         auto load_l = [&](T* dst, int d) {
             const int j = FWD ? d : nblk - 1 - d;
@@ -202,13 +211,28 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t 
                 }
                 if (__syncthreads_and(ok) || abort) break;
                 // give up (uniformly across the workgroup) past the spin limit
-                // or once another workgroup has given up
-                if (__syncthreads_or(spins > SWEEP_SPIN_LIMIT || load_coherent(&sy->err) != 0)) {
-                    abort = true;
-                    if (tid == 0) atomicExch(&sy->err, 1);
-                    break;
+                // or once another workgroup has given up; the error word is
+                // read by one thread every 32 spins, so that a poll normally
+                // costs one round trip (the reload below), not two
+                if ((spins & 31) == 31) {
+                    const int e = (tid == 0) ? load_coherent(&sy->err) : 0;
+                    if (__syncthreads_or(spins > SWEEP_SPIN_LIMIT || e != 0)) {
+                        abort = true;
+                        if (tid == 0) atomicExch(&sy->err, 1);
+                        break;
+                    }
                 }
-                __builtin_amdgcn_s_sleep(1);
+                // Every workgroup soon catches up with the block being
+                // solved, so hundreds would poll the same few kilobytes:
+                // those with more of their own dependencies still to go
+                // after this one (and so with slack) poll less often, which
+                // keeps the round trips of the next block's poll short.
+                const int ahead = ndep - 1 - d;
+                if (ahead == 0) {
+                    __builtin_amdgcn_s_sleep(1);
+                } else {
+                    for (int z = 0; z < (ahead < 4 ? ahead : 4); ++z) __builtin_amdgcn_s_sleep(32);
+                }
                 load_x(xc, d);
             }
             // acc += L_ij X_j (forward) or L_ji^T X_j (backward), 16 k-steps
@@ -216,7 +240,10 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t 
             for (int ks = 0; ks < JB / 4; ++ks) {
                 const int c = 4 * ks + g;
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt) acc[rt] = mma_xzt(acc[rt], lc[ks], xs[c * XP + 16 * rt + i]);
+                for (int rt = 0; rt < RT; ++rt) {
+                    if (ks & 1) acc2[rt] = mma_xzt(acc2[rt], lc[ks], xs[c * XP + 16 * rt + i]);
+                    else acc[rt] = mma_xzt(acc[rt], lc[ks], xs[c * XP + 16 * rt + i]);
+                }
             }
 #pragma unroll
             for (int ks = 0; ks < JB / 4; ++ks) lc[ks] = ln[ks];
@@ -228,7 +255,7 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t 
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) part[(16 * w + i) * XP + 16 * rt + tcol<T>(g, r)] = acc[rt][r];
+            for (int r = 0; r < 4; ++r) part[(16 * w + i) * XP + 16 * rt + tcol<T>(g, r)] = acc[rt][r] + acc2[rt][r];
         __syncthreads();
         // diagonal block by substitution: a lane per row, wave w takes the
         // right-hand sides q = w + 4 u
@@ -236,10 +263,7 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t 
             const T pl = piv[lane];
             T v[QW];
 #pragma unroll
-            for (int u = 0; u < QW; ++u) {
-                const int q = w + 4 * u;
-                v[u] = (lane < jb && rc0 + q < nrhs) ? In[idx(r0 + lane, rc0 + q, ldi)] - part[lane * XP + q] : (T)0;
-            }
+            for (int u = 0; u < QW; ++u) v[u] = vin[u] - part[lane * XP + w + 4 * u];
             if (FWD) {
 #pragma unroll 8
                 for (int c = 0; c < JB; ++c) {
