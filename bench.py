@@ -39,15 +39,18 @@ HBM_PEAK_GBS = 8000.0
 # same counter reads for an 8 GiB device-to-device copy (FETCH_SIZE reads half
 # the bytes moved, WRITE_SIZE all of them).  Valid only for the kernel source
 # it was measured on: reported as null once that source changes.
-SYRK_TRAFFIC = dict(fetch_kib=1863985.3, write_kib=699267.1, fetch_scale=2.0, write_scale=1.0,
-                    kernel_sha1="27a48ab921ed0e0a005f0108ed491441cba0650e")
+SYRK_TRAFFIC = dict(fetch_kib=650234.3, write_kib=469937.5, fetch_scale=2.0, write_scale=1.0,
+                    kernel_sha1="92d551f3ea3bffa98076597d6cdcee84dca4e2d0")
 
 
 def syrk_traffic_bytes():
     import hashlib
     src = open(os.path.join(ROOT, "paper_2601_14466_amd", "csrc", "potrf.hip")).read()
-    a = src.find("template <typename S, bool FOLD>")
-    b = src.find("\n}\n", a) + 3 if a >= 0 else -1  # the kernel's text, through its closing brace
+    # the kernel's text with the tile-order and buffer helpers above it:
+    # from the tile size through the kernel's closing brace
+    a = src.find("constexpr int SY_BM")
+    k = src.find("template <typename S, bool FOLD>", a) if a >= 0 else -1
+    b = src.find("\n}\n", k) + 3 if k >= 0 else -1
     if a < 0 or b < 3 or hashlib.sha1(src[a:b].encode()).hexdigest() != SYRK_TRAFFIC["kernel_sha1"]:
         return None
     t = SYRK_TRAFFIC
