@@ -137,7 +137,7 @@ __device__ __forceinline__ int solve_one(T* __restrict__ A, int64_t lda, int n, 
             for (int u = 0; u < 2; ++u) {
                 const int I = I0 + 4 * u;
                 if (I >= nt) continue;
-                solve16s<T, 17>(acc[u], Lsc, piv);
+                solve16s<T, 17, true>(acc[u], Lsc, piv);
                 store_tile<T, T>(acc[u], A, lda, 16 * I, 16 * j, n, n, false);
                 // b_I -= L_Ij y_j (each lane: its row, its 4 columns; reduce over groups)
                 for (int r = 0; r < nrhs; ++r) {

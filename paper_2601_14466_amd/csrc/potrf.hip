@@ -74,7 +74,12 @@ __device__ __forceinline__ int factor_publish(V4<C>& d, int j, C* Lsc, C* piv) {
 }
 
 template <typename S, int W, int SMAX>
-__global__ __launch_bounds__(64 * W) void k_factor_block(S* __restrict__ A, int64_t lda, int s, int64_t col0,
+// (At most 256 registers per wave, VGPRs and AGPRs together: the look-ahead
+// runs this kernel while the trailing update holds two 256-register waves on
+// every SIMD, and a wave that needs more than half a SIMD's registers can
+// only start once the update drains a whole SIMD, which starved it for
+// milliseconds at a time.)
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) void k_factor_block(S* __restrict__ A, int64_t lda, int s, int64_t col0,
                                                          int32_t* info) {
     typedef double C;
     constexpr int NTM = SMAX / 16;  // tile rows at most
@@ -199,7 +204,8 @@ __global__ __launch_bounds__(64 * W) void k_factor_block(S* __restrict__ A, int6
 // Exact for integer data with power-of-two pivots.
 // ---------------------------------------------------------------------------
 template <typename S, int NB, int RB>
-__global__ __launch_bounds__(256) void k_trsm_panel(S* __restrict__ P, const S* __restrict__ Lkk,
+// (At most 256 registers per wave, for the same reason as k_factor_block.)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_trsm_panel(S* __restrict__ P, const S* __restrict__ Lkk,
                                                     int64_t lda, int64_t m, const int32_t* info) {
     constexpr int NT = NB / 16, NTT = NT * (NT + 1) / 2;
     __shared__ S Lt[NTT][16 * 17];  // tile (t, p), p <= t, at t (t + 1) / 2 + p: row r, column c at r*17 + c

@@ -176,26 +176,27 @@ __device__ __forceinline__ int factor16(V4<C>& y) {
         const C rs = rsqrt_nr(p);
         const C v = rowbcast(y[rc], gc);   // Y[i][c]
         const C lic = (i > c) ? v * rs : (i == c ? p * rs : (C)0);
-        if (g == gc) y[rc] = lic;
+        y[rc] = (g == gc) ? lic : y[rc];
         const int rn = c < 15 ? treg<C>(c + 1) : 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = (rn + q) & 3;
             const int j = tcol<C>(g, r);
             const C ljc = shfl(lic, j);         // L[j][c] sits in lane j (group 0)
-            if (j > c) y[r] = y[r] - lic * ljc;
+            const C t = y[r] - lic * ljc;
+            y[r] = (j > c) ? t : y[r];
         }
     }
     return 0;
 }
 
 // X = Y L^{-T} with L pre-scaled by columns: Lsc[j*LDL + c] = L(j,c)/L(c,c)
-// for j > c (0 elsewhere) and piv[c] = L(c,c).  Column c of Y is final after
+// for j > c, exactly 0 elsewhere (relied on: see below), and piv[c] = L(c,c).  Column c of Y is final after
 // the updates from the columns before it; it is broadcast along its row and
 // applied to the columns after it (one shuffle and up to four FMAs), and each
 // column is divided by its pivot once at the end.  Exact for integer data
 // with power-of-two pivots.
-template <typename C, int LDL>
+template <typename C, int LDL, bool GUARDED = false>
 __device__ __forceinline__ void solve16s(V4<C>& y, const C* Lsc, const C* piv) {
     const int l = lane_id(), i = l & 15, g = l >> 4;
 #pragma unroll
@@ -205,7 +206,18 @@ __device__ __forceinline__ void solve16s(V4<C>& y, const C* Lsc, const C* piv) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int j = tcol<C>(g, r);
-            if (j > c) y[r] = y[r] - yc * Lsc[j * LDL + c];
+            if constexpr (GUARDED) {
+                if (j > c) y[r] = y[r] - yc * Lsc[j * LDL + c];
+            } else {
+                // Applied to every column: Lsc holds exact zeros for j <= c,
+                // so those columns keep their (finite) values.  A guard on
+                // j > c differs between lane groups, and the compiler turns
+                // it into a branch with the LDS read of L inside, unhoisted,
+                // which left every step waiting for LDS.  The guarded form
+                // holds fewer values in registers, for callers that are
+                // short of them.
+                y[r] = y[r] - yc * Lsc[j * LDL + c];
+            }
         }
     }
 #pragma unroll
@@ -223,6 +235,8 @@ __device__ __forceinline__ void solve16s2(V4<C>& y, V4<C>& u, const C* Lsc, cons
         const C yc = rowbcast(y[rc], gc), uc = rowbcast(u[rc], gc);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+            // guarded (unlike solve16s): with two tiles in flight, hoisting
+            // every read of L would take this past 256 registers per wave
             const int j = tcol<C>(g, r);
             if (j > c) {
                 const C lv = Lsc[j * LDL + c];
