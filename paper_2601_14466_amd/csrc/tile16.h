@@ -161,18 +161,19 @@ __device__ __forceinline__ float rsqrt_nr(float p) {
 // right receive the rank-1 update; the lane shuffles that fetch L[j][c] are
 // issued starting with the register that holds column c + 1, the next step's
 // dependency.  Returns 0, or c+1 for the first local column whose pivot is
-// not > 0 (NaN included); the decision is uniform across the wave.  Entries
-// above the diagonal are left unspecified.  (The per-column exit also keeps
-// the compiler from scheduling across columns, which measured faster when
-// the factor shares its SIMDs with the trailing update.)
+// not > 0 (NaN included); the decision is uniform across the wave.  The
+// columns after a failing one are computed on meaningless values (no exit
+// per column, so the compiler can schedule across columns) and, like the
+// entries above the diagonal, are unspecified.
 template <typename C>
 __device__ __forceinline__ int factor16(V4<C>& y) {
     const int l = lane_id(), i = l & 15, g = l >> 4;
+    int fail = 0;
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
         const int gc = tgrp<C>(c), rc = treg<C>(c);
         const C p = readlane(y[rc], gc * 16 + c);
-        if (!(p > (C)0)) return c + 1;
+        if (fail == 0 && !(p > (C)0)) fail = c + 1;
         const C rs = rsqrt_nr(p);
         const C v = rowbcast(y[rc], gc);   // Y[i][c]
         const C lic = (i > c) ? v * rs : (i == c ? p * rs : (C)0);
@@ -187,7 +188,7 @@ __device__ __forceinline__ int factor16(V4<C>& y) {
             y[r] = (j > c) ? t : y[r];
         }
     }
-    return 0;
+    return fail;
 }
 
 // X = Y L^{-T} with L pre-scaled by columns: Lsc[j*LDL + c] = L(j,c)/L(c,c)
