@@ -88,12 +88,11 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t cnt, unsigned long lon
 // Pass 1 (k_sym_rowprod): the grid is (64-row strips) x RSPLIT column ranges.
 // Each workgroup's four waves take the 64 x 64 tiles of its range in turn;
 // a lane owns one row of the strip and streams that row of the tile from
-// memory: stored tiles (J <= I) down their columns (coalesced across lanes),
-// tiles above the diagonal (J > I) as the transposed stored tile, each lane
-// walking its own column.  The x values of the tile arrive one per lane and
-// are broadcast by readlane.  No LDS staging and no barrier inside the loop;
-// the loads of the next 16 columns are issued before the current 16 are
-// used.  The four waves' sums are added in a fixed order and written as one
+// memory: stored tiles (J <= I) down their columns (coalesced across lanes);
+// tiles above the diagonal (J > I) are the transposed stored tile, read in
+// coalesced 16 x 4 pieces and transposed through a per-wave LDS buffer (no
+// workgroup barrier).  The x values of the tile arrive one per lane and are
+// broadcast by readlane.  The four waves' sums are added in a fixed order and written as one
 // partial per (strip, range).
 // Pass 2 (k_sym_finish): R = B - sum of the partials over the ranges (fixed
 // order), and the column maxima.  The result does not depend on the launch.
@@ -112,6 +111,7 @@ __global__ __launch_bounds__(256) void k_sym_rowprod(const double* __restrict__ 
                                                      int64_t nrhs, int64_t rc0, const double* __restrict__ X,
                                                      int64_t ldx, double* __restrict__ Pp, int absmode) {
     __shared__ double red[4][RPT][RS];
+    __shared__ double tr[4][RS][17];  // per wave: a transposed 64 x 16 piece of a tile above the diagonal
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int64_t strip = blockIdx.x, I0 = strip * RS;
     const int64_t nt = (n + RS - 1) / RS;
@@ -138,15 +138,38 @@ __global__ __launch_bounds__(256) void k_sym_rowprod(const double* __restrict__ 
 #pragma unroll
         for (int c0 = 0; c0 < RS; c0 += 16) {
             double av[16];
+            if (above) {
+                // Stored rows J0 + c0 .. + 15 of columns I0 .. I0 + 63, read
+                // sixteen rows by four columns per instruction (coalesced),
+                // transposed through this wave's LDS piece so that lane b
+                // receives its row's sixteen values.  Read directly, each
+                // lane would walk its own column: 64 cache lines per load.
+                const int a = lane & 15, b0 = lane >> 4;
+                const bool aok = c0 + a < jw;
+                double tv[16];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                const int cc = c0 + c;
-                const int64_t gj = J0 + (cc < jw ? cc : 0);
-                double v;
-                if (below) v = A[idx(gic, gj, lda)];
-                else if (above) v = A[idx(gj, gic, lda)];
-                else v = (gic >= gj) ? A[idx(gic, gj, lda)] : A[idx(gj, gic, lda)];
-                av[c] = (cc < jw && rin) ? v : 0.0;
+                for (int q = 0; q < 16; ++q) {
+                    const int64_t gi2 = I0 + 4 * q + b0;
+                    tv[q] = (aok && gi2 < n) ? A[idx(J0 + c0 + a, gi2, lda)] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < 16; ++q) tr[w][4 * q + b0][a] = tv[q];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                for (int c = 0; c < 16; ++c) av[c] = tr[w][lane][c];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            } else {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    const int cc = c0 + c;
+                    const int64_t gj = J0 + (cc < jw ? cc : 0);
+                    const double v = (below || gic >= gj) ? A[idx(gic, gj, lda)] : A[idx(gj, gic, lda)];
+                    av[c] = (cc < jw && rin) ? v : 0.0;
+                }
             }
 #pragma unroll
             for (int c = 0; c < 16; ++c) {
