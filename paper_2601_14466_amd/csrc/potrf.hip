@@ -393,10 +393,10 @@ __device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, int vo
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
 }
 
-template <typename S, bool FOLD>
+template <typename S, bool FOLD, int RG, bool BF>
 __global__ __launch_bounds__(256, 2) void k_syrk_lower(S* __restrict__ Cm, const S* __restrict__ P,
                                                        int64_t lda, int64_t m, int kdim, int64_t j0, int64_t wj,
-                                                       int bf16, const int32_t* info) {
+                                                       const int32_t* info) {
     if (*info != 0) return;
     const int64_t T = (m + SY_BM - 1) / SY_BM;
     const int64_t ntiles = slab_tiles(T, j0, wj);
@@ -453,9 +453,12 @@ __global__ __launch_bounds__(256, 2) void k_syrk_lower(S* __restrict__ Cm, const
         zo[b] = ((int)sc0 + min(16 * b + i, cmax) + g * ld) * ES;
     }
     const int nks = kdim / 4;
-    // ring of four k-steps of operands; step kn lives in slot kn % 4 and is
-    // fetched three steps before its MFMAs
-    S xq[4][4], zq[4][4];
+    // ring of RG k-steps of operands; step kn lives in slot kn % RG and is
+    // fetched RG - 1 steps before its MFMAs (RG = 8 for binary32, whose
+    // MFMAs take half as long, so that the prefetch still covers a round
+    // trip to memory)
+    static_assert(RG == 4 || RG == 8, "ring of 4 or 8 k-steps");
+    S xq[RG][4], zq[RG][4];
     auto fetch = [&](int slot, int kn) {
         const int soff = (kn < nks ? kn : nks - 1) * 4 * ld * ES;  // steps past the end re-read the last one
 #pragma unroll
@@ -464,19 +467,18 @@ __global__ __launch_bounds__(256, 2) void k_syrk_lower(S* __restrict__ Cm, const
             zq[slot][b] = buf_ld((S*)nullptr, prs, zo[b], soff);
         }
     };
-    fetch(0, 0);
-    fetch(1, 1);
-    fetch(2, 2);
-    // k-steps ks .. ks + 3 (ks % 4 == 0)
+#pragma unroll
+    for (int p = 0; p < RG - 1; ++p) fetch(p, p);
+    // k-steps ks .. ks + RG - 1 (ks % RG == 0)
     auto body = [&](int ks) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            fetch((s + 3) & 3, ks + s + 3);
+        for (int s = 0; s < RG; ++s) {
+            fetch((s + RG - 1) % RG, ks + s + RG - 1);
             S xv[4], zv[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                xv[b] = lo_round(xq[s][b], bf16);
-                zv[b] = lo_round(zq[s][b], bf16);
+                xv[b] = BF ? lo_round(xq[s][b], 1) : xq[s][b];
+                zv[b] = BF ? lo_round(zq[s][b], 1) : zq[s][b];
             }
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi)
@@ -490,18 +492,18 @@ __global__ __launch_bounds__(256, 2) void k_syrk_lower(S* __restrict__ Cm, const
         // it is subtracted.  C's HBM traffic thus overlaps the matrix pipe
         // instead of forming a prologue that every resident workgroup issues
         // at once.
-        const int per_q = nks / 64;
+        const int per_q = nks / (16 * RG);  // the host keeps nks a multiple of 16 RG
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             V4<S> cv;
 #pragma unroll
             for (int r = 0; r < 4; ++r) cv[r] = c_load(q >> 2, q & 3, r);
-            for (int u = 0; u < per_q; ++u) body((q * per_q + u) * 4);
+            for (int u = 0; u < per_q; ++u) body((q * per_q + u) * RG);
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[q >> 2][q & 3][r] -= cv[r];
         }
     } else {
-        for (int ks = 0; ks < nks; ks += 4) body(ks);
+        for (int ks = 0; ks < nks; ks += RG) body(ks);
     }
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
@@ -672,12 +674,28 @@ mg_status syrk_lower_launch(hipStream_t st, S* Cm, const S* P, int64_t lda, int6
     // must fit in 31 bits
     if ((m + (kdim + 64) * lda) * (int64_t)sizeof(S) >= ((int64_t)1 << 31) - 65536 || kdim % 16 != 0)
         return MG_ERR_UNSUPPORTED;
-    if (kdim % 256 == 0)
-        hipLaunchKernelGGL((k_syrk_lower<S, true>), dim3((unsigned)grid), dim3(256), 0, st, Cm, P, lda, m, (int)kdim,
-                           j0, wj, bf16, info);
-    else
-        hipLaunchKernelGGL((k_syrk_lower<S, false>), dim3((unsigned)grid), dim3(256), 0, st, Cm, P, lda, m,
-                           (int)kdim, j0, wj, bf16, info);
+#define MG_SYRK(FOLD_, RG_, BF_)                                                                             \
+    hipLaunchKernelGGL((k_syrk_lower<S, FOLD_, RG_, BF_>), dim3((unsigned)grid), dim3(256), 0, st, Cm, P, lda, m, \
+                       (int)kdim, j0, wj, info)
+    // rank-256/512 updates fold C into the k-loop (which needs kdim a
+    // multiple of 16 ring depths); binary32 rank-512 updates use the deeper
+    // ring (not with bfloat16 rounding, which would then spill); the
+    // bfloat16 rounding of binary32 operands is a template switch
+    if constexpr (sizeof(S) == 4) {
+        if (kdim % 512 == 0 && !bf16) {
+            MG_SYRK(true, 8, false);
+        } else if (kdim % 256 == 0) {
+            if (bf16) MG_SYRK(true, 4, true);
+            else MG_SYRK(true, 4, false);
+        } else {
+            if (bf16) MG_SYRK(false, 4, true);
+            else MG_SYRK(false, 4, false);
+        }
+    } else {
+        if (kdim % 256 == 0) MG_SYRK(true, 4, false);
+        else MG_SYRK(false, 4, false);
+    }
+#undef MG_SYRK
     MG_LAUNCH_CHECK();
     return MG_OK;
 }
