@@ -15,8 +15,7 @@
 //     A_Ij - sum_p L_Ip L_jp^T on the matrix pipe, the diagonal tile is
 //     factored in registers (factor16) and the tiles below are solved
 //     (solve16s); the forward substitution L y = b is fused into the same
-//     sweep, then the backward substitution L^T x = y runs block by block;
-//   - systems with n <= lds_n are copied to LDS first and factored there.
+//     sweep, then the backward substitution L^T x = y runs block by block.
 // Per-system info: 0, or the first failing column (1-based); a failing system
 // leaves its right-hand side untouched and does not affect the others.
 #include <algorithm>
