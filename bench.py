@@ -33,14 +33,14 @@ METRIC = "potrf+potrs TFLOP/s: FP64 vs mixed-precision+IR at 1e-12 backward erro
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 matrix peak (public specification)
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of the rank-512 trailing-update kernel, k_syrk_lower<double, true>,
+# HBM traffic of the rank-512 trailing-update kernel, k_syrk_lower<double, true, 4, false>,
 # from two rocprofv3 --pmc runs of this benchmark (profiles/k_syrk_lower_n32768_hbm_traffic.md):
 # average FETCH_SIZE and WRITE_SIZE per dispatch in KiB, each scaled by what the
 # same counter reads for an 8 GiB device-to-device copy (FETCH_SIZE reads half
 # the bytes moved, WRITE_SIZE all of them).  Valid only for the kernel source
 # it was measured on: reported as null once that source changes.
-SYRK_TRAFFIC = dict(fetch_kib=650234.3, write_kib=469937.5, fetch_scale=2.0, write_scale=1.0,
-                    kernel_sha1="92d551f3ea3bffa98076597d6cdcee84dca4e2d0")
+SYRK_TRAFFIC = dict(fetch_kib=650335.8, write_kib=469937.5, fetch_scale=2.0, write_scale=1.0,
+                    kernel_sha1="58b5967db306b75585bd919d2d57994bd68a0289")
 
 
 def syrk_traffic_bytes():
@@ -49,7 +49,7 @@ def syrk_traffic_bytes():
     # the kernel's text with the tile-order and buffer helpers above it:
     # from the tile size through the kernel's closing brace
     a = src.find("constexpr int SY_BM")
-    k = src.find("template <typename S, bool FOLD>", a) if a >= 0 else -1
+    k = src.find("template <typename S, bool FOLD", a) if a >= 0 else -1
     b = src.find("\n}\n", k) + 3 if k >= 0 else -1
     if a < 0 or b < 3 or hashlib.sha1(src[a:b].encode()).hexdigest() != SYRK_TRAFFIC["kernel_sha1"]:
         return None
@@ -396,7 +396,7 @@ def main():
         traffic = syrk_traffic_bytes() if (args.n == 32768 and r["nb"] == 512) else None
         roof = dict(bound="mfma", achieved=round(r["trailing_tflops"], 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(r["trailing_tflops"] / FP64_PEAK_TFLOPS, 4), traffic=traffic,
-                    kernel="k_syrk_lower<double, true>", launches=tr["launches"],
+                    kernel="k_syrk_lower<double, true, 4, false>", launches=tr["launches"],
                     flops_per_launch=tr["flops"] / tr["launches"],
                     algorithmic_bytes_per_launch=tr["bytes"] / tr["launches"],
                     avg_launch_ms=tr["ms"] / tr["launches"])
