@@ -329,6 +329,41 @@ def bench_adjoint(torch, mg, synth, n: int = 8192, nrhs: int = 64, reps: int = 5
                 backward_tflops=round(bflops / (b / 1e3) / 1e12, 3), info=int(info))
 
 
+def bench_gp(torch, mg, synth, n: int = 16384, nrhs: int = 1, reps: int = 3, seed: int = 7700):
+    """Gaussian-process marginal log likelihood (factor, solve, log det and
+    the per-column combination) at n = 16384 for one observation vector,
+    A = G G^T/n + delta I (cond 1e4), nonzero mean.  TFLOP/s uses the posv
+    nominal flops."""
+    from paper_2601_14466_amd import _lib
+    A0 = synth.torch_gram_spd_cond(n, seed, 1e4)
+    Yc = synth.torch_normal((nrhs, n), seed + 1)         # column-major n x nrhs
+    Mc = synth.torch_normal((nrhs, n), seed + 2)
+    A = A0.clone()
+    Al = torch.empty_like(Yc)
+    ll = torch.empty(nrhs, dtype=torch.float64, device=A.device)
+    info = torch.zeros((), dtype=torch.int32, device=A.device)
+    h = mg.handle()
+    h.set_block_size(0)
+    wb = ctypes.c_size_t()
+    _lib.call("mg_gp_loglik_buffer_size", h.h, n, nrhs, ctypes.byref(wb))
+    work = torch.empty(max(1, wb.value), dtype=torch.uint8, device=A.device)
+    ts = []
+    for r in range(reps + 1):
+        A.copy_(A0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _lib.call("mg_gp_loglik", h.sync_stream(), n, nrhs, _p(A), n, _p(Yc), n, _p(Mc), n, _p(Al), n, _p(ll),
+                  _p(work), wb.value, _p(info))
+        e1.record()
+        torch.cuda.synchronize()
+        if r >= 1:
+            ts.append(e0.elapsed_time(e1))
+    t = _median(ts)
+    return dict(n=n, nrhs=nrhs, ms=round(t, 3), tflops=round(nominal_flops(n, nrhs) / (t / 1e3) / 1e12, 3),
+                loglik=float(ll[0]), info=int(info))
+
+
 def cpu_baseline(torch, synth, n: int = 8192, nrhs: int = 16, seed: int = 4242):
     import oracle  # CPU oracle: baseline leg only
     A = synth.torch_gram_spd_cond(n, seed, 1e4)
@@ -385,6 +420,8 @@ def main():
             log(f"[bench] {key}: {extras[key]}")
         extras["adjoint_n8192"] = bench_adjoint(torch, mg, synth)
         log(f"[bench] adjoint: {extras['adjoint_n8192']}")
+        extras["gp_loglik_n16384"] = bench_gp(torch, mg, synth)
+        log(f"[bench] gp_loglik: {extras['gp_loglik_n16384']}")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

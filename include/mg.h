@@ -267,6 +267,37 @@ mg_status mg_logdet(mg_handle_t handle, mg_dtype dtype, int64_t n, const void *L
                     double *out, const int32_t *info);
 
 /*
+ * Gaussian-process marginal log likelihood (paper: Research Impact Statement,
+ * "Scientific applications", Cholesky solve): for each column j of Y,
+ *   loglik[j] = -1/2 r_j^T A^{-1} r_j - 1/2 log det A - n/2 log(2 pi),
+ *   r_j = y_j - m_j,
+ * with A = K + Sigma the n x n SPD covariance, FP64.  One factorisation
+ * serves every column: A = L L^T in place, alpha_j = A^{-1} r_j by the two
+ * triangular sweeps, log det A = 2 sum_j log L_jj, and (r_j, alpha_j) summed
+ * in a fixed order (results do not depend on the launch).
+ *   A       n x n, column-major, lower triangle read; overwritten by L (the
+ *           strict upper triangle is never touched).  Caller-owned.
+ *   Y       n x nrhs observations (ldy >= n), read only.
+ *   M       n x nrhs means (ldm >= n), read only, or NULL for zero mean.
+ *   Alpha   n x nrhs output (ldalpha >= n): A^{-1}(y_j - m_j); holds
+ *           y_j - m_j when the factorisation fails.
+ *   loglik  device double[nrhs]: the values; NaN when info != 0.
+ *   work    device workspace of mg_gp_loglik_buffer_size bytes (0 when n or
+ *           nrhs is 0); work may be NULL then.
+ *   info    device int32: 0, or the first column (1-based) whose pivot is
+ *           not positive (as mg_potrf).  With nrhs == 0 only A is factored;
+ *           with n == 0 every loglik is 0.
+ * Errors (checked before any launch): -1 handle, -2 n < 0, -3 nrhs < 0,
+ * -4 A NULL, -5 lda, -6 Y NULL, -7 ldy, -9 ldm (M given), -10 Alpha NULL,
+ * -11 ldalpha, -12 loglik NULL, -13 work NULL, -14 work_bytes too small,
+ * -15 info NULL.  Positive values: runtime errors as elsewhere.
+ */
+mg_status mg_gp_loglik_buffer_size(mg_handle_t handle, int64_t n, int64_t nrhs, size_t *bytes);
+mg_status mg_gp_loglik(mg_handle_t handle, int64_t n, int64_t nrhs, double *A, int64_t lda, const double *Y,
+                       int64_t ldy, const double *M, int64_t ldm, double *Alpha, int64_t ldalpha, double *loglik,
+                       void *work, size_t work_bytes, int32_t *info);
+
+/*
  * Profiling.  When enabled, every launch of the kernel kinds below is
  * bracketed by a pair of HIP events on the handle's stream, and the
  * algorithmic work of each launch is accumulated.

@@ -20,7 +20,7 @@ from ._lib import MgError, call, load, raw  # noqa: F401
 
 __all__ = [
     "Handle", "handle", "potrf", "potrs", "posv", "posv_mixed", "posv_backward", "PosvFunction", "BatchPlan",
-    "posv_batched", "logdet", "colmajor",
+    "posv_batched", "logdet", "gp_loglik", "colmajor",
     "MgError", "load", "call", "raw",
 ]
 
@@ -187,6 +187,42 @@ def posv(A, B, nb: int | None = None):
             h.set_block_size(0)
     X = Xc.T
     return (X.reshape(n) if flat else X), info
+
+
+def gp_loglik(A, Y, M=None):
+    """Gaussian-process marginal log likelihood of each column of Y (or of
+    the vector Y) under covariance A (FP64, SPD, lower triangle read) and
+    mean M (same shape as Y, or None for zero mean):
+    -1/2 (y-m)^T A^{-1} (y-m) - 1/2 log det A - n/2 log(2 pi).
+    Returns (loglik, alpha, L, info): loglik has one entry per column (a
+    0-d tensor for vector Y), alpha = A^{-1}(y - m), L the Cholesky factor
+    (lower triangle significant).  A, Y and M are not modified."""
+    torch = _torch()
+    _check_cuda(A, Y)
+    if A.dtype != torch.float64 or Y.dtype != torch.float64 or (M is not None and M.dtype != torch.float64):
+        raise TypeError("gp_loglik takes FP64 A, Y and M")
+    flat = Y.dim() == 1
+    n = A.shape[0]
+    nrhs = 1 if flat else Y.shape[1]
+    if M is not None and tuple(M.shape) != tuple(Y.shape):
+        raise ValueError("M must have the shape of Y")
+    h = handle()
+    Lc = A.T.clone(memory_format=torch.contiguous_format)
+    Yc = (Y.reshape(n, 1) if flat else Y).T.contiguous()
+    Mc = None if M is None else (M.reshape(n, 1) if flat else M).T.contiguous()
+    Al = torch.empty((nrhs, n), dtype=torch.float64, device=A.device)
+    ll = torch.empty(nrhs, dtype=torch.float64, device=A.device)
+    wb = ctypes.c_size_t()
+    call("mg_gp_loglik_buffer_size", h.h, n, nrhs, ctypes.byref(wb))
+    work = torch.empty(max(1, wb.value), dtype=torch.uint8, device=A.device)
+    info = torch.zeros((), dtype=torch.int32, device=A.device)
+    call("mg_gp_loglik", h.h, n, nrhs, _ptr(Lc), max(1, n), _ptr(Yc), max(1, n),
+         None if Mc is None else _ptr(Mc), max(1, n), _ptr(Al), max(1, n), _ptr(ll),
+         _ptr(work), wb.value, _ptr(info))
+    alpha = Al.T
+    if flat:
+        return ll[0], alpha.reshape(n), Lc.T, info
+    return ll, alpha, Lc.T, info
 
 
 def posv_mixed(A, B, precision: str = "fp32", tol: float = 1e-12, max_iter: int = 30, fallback: bool = True):

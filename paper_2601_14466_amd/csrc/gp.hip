@@ -1,0 +1,128 @@
+// gp.hip -- Gaussian-process marginal log likelihood on the Cholesky path.
+//
+// The paper's application section (Research Impact Statement, "Scientific
+// applications", Cholesky solve) writes the marginal log likelihood of
+// observations y with mean m under covariance A = K + Sigma as
+//   log L = -1/2 (y - m)^T A^{-1} (y - m) - 1/2 log det A - N/2 log(2 pi),
+// so it needs one solve against A and A's log determinant.  Both come from a
+// single factorisation here: A = L L^T in place (potrf), alpha = A^{-1}(y - m)
+// by the two triangular sweeps (potrs), log det A = 2 sum_j log L_jj, and one
+// workgroup per column forms (y - m)^T alpha in a fixed summation order and
+// combines the three terms.  Columns of Y are independent observation
+// vectors sharing the covariance.
+#include <algorithm>
+#include <cmath>
+
+#include "mg_internal.h"
+
+using namespace mg;
+
+namespace mg {
+
+// Alpha = Y - M (M may be null: zero mean), n x nrhs, column-major.
+__global__ __launch_bounds__(256) void k_gp_center(const double* __restrict__ Y, int64_t ldy,
+                                                   const double* __restrict__ M, int64_t ldm,
+                                                   double* __restrict__ Al, int64_t lda_, int64_t n, int64_t nrhs) {
+    const int64_t tot = n * nrhs;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e % n, j = e / n;
+        const double mv = M ? M[i + j * ldm] : 0.0;
+        Al[i + j * lda_] = Y[i + j * ldy] - mv;
+    }
+}
+
+// One workgroup per column j: q = sum_i (y_ij - m_ij) alpha_ij, each thread
+// over rows tid, tid + 256, ... in order, then a fixed tree over the 256
+// partial sums; loglik[j] = -q/2 - logdet/2 - n/2 log(2 pi), NaN after a
+// failed factorisation.
+__global__ __launch_bounds__(256) void k_gp_combine(const double* __restrict__ Y, int64_t ldy,
+                                                    const double* __restrict__ M, int64_t ldm,
+                                                    const double* __restrict__ Al, int64_t lda_, int64_t n,
+                                                    const double* __restrict__ logdet, double* __restrict__ loglik,
+                                                    const int32_t* __restrict__ info) {
+    __shared__ double part[256];
+    const int64_t j = blockIdx.x;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double mv = M ? M[i + j * ldm] : 0.0;
+        s += (Y[i + j * ldy] - mv) * Al[i + j * lda_];
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) part[threadIdx.x] += part[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double two_pi_log = 1.8378770664093454835606594728112353;  // log(2 pi)
+        loglik[j] = (*info != 0) ? (double)NAN : -0.5 * part[0] - 0.5 * (*logdet) - 0.5 * (double)n * two_pi_log;
+    }
+}
+
+__global__ void k_gp_zero(double* v, int64_t k) {
+    for (int64_t e = threadIdx.x; e < k; e += blockDim.x) v[e] = 0.0;
+}
+
+static size_t gp_work_bytes(int64_t n, int64_t nrhs) {
+    if (n == 0 || nrhs == 0) return 0;
+    return potrs_work_bytes(n, nrhs, 8) + 256;  // sweeps' workspace, then the log determinant
+}
+
+}  // namespace mg
+
+extern "C" {
+
+mg_status mg_gp_loglik_buffer_size(mg_handle_t h, int64_t n, int64_t nrhs, size_t* bytes) {
+    if (!h) return -1;
+    if (n < 0) return -2;
+    if (nrhs < 0) return -3;
+    if (!bytes) return -4;
+    *bytes = gp_work_bytes(n, nrhs);
+    return MG_OK;
+}
+
+mg_status mg_gp_loglik(mg_handle_t h, int64_t n, int64_t nrhs, double* A, int64_t lda, const double* Y, int64_t ldy,
+                       const double* M, int64_t ldm, double* Alpha, int64_t ldalpha, double* loglik, void* work,
+                       size_t work_bytes, int32_t* info) {
+    if (!h) return -1;
+    if (n < 0) return -2;
+    if (nrhs < 0) return -3;
+    const bool any = n > 0 && nrhs > 0;
+    if (!A && n > 0) return -4;
+    if (lda < std::max<int64_t>(1, n)) return -5;
+    if (!Y && any) return -6;
+    if (ldy < std::max<int64_t>(1, n)) return -7;
+    if (M && ldm < std::max<int64_t>(1, n)) return -9;
+    if (!Alpha && any) return -10;
+    if (ldalpha < std::max<int64_t>(1, n)) return -11;
+    if (!loglik && nrhs > 0) return -12;
+    const size_t need = gp_work_bytes(n, nrhs);
+    if (need > 0 && !work) return -13;
+    if (work_bytes < need) return -14;
+    if (!info) return -15;
+    mg_status rc;
+    if ((rc = potrf_impl<double>(h, n, A, lda, info))) return rc;  // info = 0 when n == 0
+    if (!any) {
+        if (nrhs > 0) {
+            // n == 0: log L = 0 for every column (empty sum, det of the empty
+            // matrix 1); a fill kernel, not a memset, so that graph capture
+            // of the call records no memset node
+            hipLaunchKernelGGL(k_gp_zero, dim3(1), dim3(256), 0, h->stream, loglik, nrhs);
+            MG_LAUNCH_CHECK();
+        }
+        return MG_OK;
+    }
+    hipStream_t st = h->stream;
+    const unsigned grid = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (n * nrhs + 255) / 256), 4096);
+    hipLaunchKernelGGL(k_gp_center, dim3(grid), dim3(256), 0, st, Y, ldy, M, ldm, Alpha, ldalpha, n, nrhs);
+    MG_LAUNCH_CHECK();
+    if ((rc = potrs_impl<double>(h, n, nrhs, A, lda, Alpha, ldalpha, (double*)work, info))) return rc;
+    double* ld = (double*)((char*)work + potrs_work_bytes(n, nrhs, 8));
+    if ((rc = mg_logdet(h, MG_F64, n, A, lda, ld, info))) return rc;
+    hipLaunchKernelGGL(k_gp_combine, dim3((unsigned)nrhs), dim3(256), 0, st, Y, ldy, M, ldm, Alpha, ldalpha, n, ld,
+                       loglik, info);
+    MG_LAUNCH_CHECK();
+    return MG_OK;
+}
+
+}  // extern "C"

@@ -359,3 +359,68 @@ def test_planted_mistakes_are_caught():
     for v in ("transpose", "sign", "drop_last"):
         with np.errstate(all="ignore"):
             assert not np.array_equal(chol(A, v), L0)
+
+
+# ---------------------------------------------------------------- GP likelihood
+# The paper (Research Impact Statement, "Scientific applications", Cholesky
+# solve) defines log L = -1/2 r^T A^{-1} r - 1/2 log det A - N/2 log(2 pi),
+# r = y - m.  The pins below evaluate that formula in closed form, without
+# the oracle's factor or solve.
+def _lehmer_inverse_quadform(r):
+    """r^T A^{-1} r for the Lehmer matrix, from its tridiagonal inverse:
+    (A^{-1})_ii = 4 i^3 / (4 i^2 - 1) for i < n, (A^{-1})_nn = n^2 / (2n - 1),
+    (A^{-1})_{i,i+1} = -i (i + 1) / (2 i + 1) (1-based)."""
+    n = len(r)
+    terms = []
+    for i in range(1, n + 1):
+        d = 4.0 * i ** 3 / (4.0 * i * i - 1.0) if i < n else n * n / (2.0 * n - 1.0)
+        terms.append(d * r[i - 1] * r[i - 1])
+        if i < n:
+            terms.append(2.0 * (-i * (i + 1.0) / (2.0 * i + 1.0)) * r[i - 1] * r[i])
+    return math.fsum(terms)
+
+
+def test_gp_loglik_diagonal_closed_form(orc):
+    n = 300
+    d = 0.5 + synth.rng(31).random(n) * 3.0
+    y = synth.normal((n, 3), 32)
+    m = synth.normal((n, 3), 33)
+    ll, alpha, info = orc.gp_loglik(np.diag(d), y, m)
+    assert info == 0
+    for j in range(3):
+        r = y[:, j] - m[:, j]
+        want = (-0.5 * math.fsum(r * r / d) - 0.5 * math.fsum(np.log(d)) - 0.5 * n * math.log(2 * math.pi))
+        assert ll[j] == pytest.approx(want, rel=1e-13)
+        assert np.allclose(alpha[:, j], r / d, rtol=1e-14, atol=0)
+
+
+def test_gp_loglik_lehmer_closed_form(orc):
+    n = 200
+    A = synth.lehmer(n)
+    y = synth.normal(n, 34)
+    ll, alpha, info = orc.gp_loglik(A, y)
+    ld = math.fsum(math.log((2.0 * j - 1.0) / (j * j)) for j in range(1, n + 1))
+    want = -0.5 * _lehmer_inverse_quadform(y) - 0.5 * ld - 0.5 * n * math.log(2 * math.pi)
+    assert info == 0
+    assert ll == pytest.approx(want, rel=1e-11)
+
+
+def test_gp_loglik_special_cases(orc):
+    n = 50
+    # A = I, y = m: only the normalisation remains
+    y = synth.normal(n, 35)
+    ll, _, info = orc.gp_loglik(np.eye(n), y, y.copy())
+    assert info == 0 and ll == -0.5 * n * math.log(2 * math.pi)
+    # n = 1 by hand
+    ll1, a1, _ = orc.gp_loglik(np.array([[4.0]]), np.array([3.0]))
+    assert ll1 == pytest.approx(-0.5 * 9.0 / 4.0 - 0.5 * math.log(4.0) - 0.5 * math.log(2 * math.pi), rel=1e-15)
+    assert a1[0] == 0.75
+    # a mean is the same as subtracting it from the observations
+    A = synth.gram_spd(n, 36)
+    m = synth.normal(n, 37)
+    assert orc.gp_loglik(A, y, m)[0] == pytest.approx(orc.gp_loglik(A, y - m)[0], rel=1e-14)
+    # not positive definite: NaN and the centred observations
+    B = np.eye(n)
+    B[7, 7] = -1.0
+    llb, ab, infob = orc.gp_loglik(B, y, m)
+    assert infob == 8 and math.isnan(llb) and np.array_equal(ab, y - m)
