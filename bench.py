@@ -364,6 +364,39 @@ def bench_gp(torch, mg, synth, n: int = 16384, nrhs: int = 1, reps: int = 3, see
                 loglik=float(ll[0]), info=int(info))
 
 
+def bench_gp_grad(torch, mg, synth, n: int = 4096, nrhs: int = 1, reps: int = 3, seed: int = 7800):
+    """Gradient of the GP log likelihood from a stored factor (A^{-1} by the
+    two sweeps with n right-hand sides, then the symmetric combination) at
+    n = 4096.  TFLOP/s counts the 2 n^3 flops of the two triangular solves
+    against n right-hand sides."""
+    from paper_2601_14466_amd import _lib
+    A = synth.torch_gram_spd(n, seed)
+    Y = synth.torch_normal((n, nrhs), seed + 1)
+    ll, alpha, L, info = mg.gp_loglik(A, Y)
+    Lc = L.T.contiguous()
+    Ac = alpha.T.contiguous()
+    g = torch.ones(nrhs, dtype=torch.float64, device=A.device)
+    gA = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    gY = torch.empty((nrhs, n), dtype=torch.float64, device=A.device)
+    h = mg.handle()
+    wb = ctypes.c_size_t()
+    _lib.call("mg_gp_loglik_grad_buffer_size", h.h, n, ctypes.byref(wb))
+    work = torch.empty(max(1, wb.value), dtype=torch.uint8, device=A.device)
+    ts = []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _lib.call("mg_gp_loglik_grad", h.sync_stream(), n, nrhs, _p(Lc), n, _p(Ac), n, _p(g), _p(gA), n, _p(gY), n,
+                  None, n, _p(work), wb.value, _p(info))
+        e1.record()
+        torch.cuda.synchronize()
+        if r >= 1:
+            ts.append(e0.elapsed_time(e1))
+    t = _median(ts)
+    return dict(n=n, nrhs=nrhs, ms=round(t, 3), tflops=round(2.0 * n ** 3 / (t / 1e3) / 1e12, 3), info=int(info))
+
+
 def cpu_baseline(torch, synth, n: int = 8192, nrhs: int = 16, seed: int = 4242):
     import oracle  # CPU oracle: baseline leg only
     A = synth.torch_gram_spd_cond(n, seed, 1e4)
@@ -422,6 +455,8 @@ def main():
         log(f"[bench] adjoint: {extras['adjoint_n8192']}")
         extras["gp_loglik_n16384"] = bench_gp(torch, mg, synth)
         log(f"[bench] gp_loglik: {extras['gp_loglik_n16384']}")
+        extras["gp_loglik_grad_n4096"] = bench_gp_grad(torch, mg, synth)
+        log(f"[bench] gp_loglik_grad: {extras['gp_loglik_grad_n4096']}")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

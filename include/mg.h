@@ -298,6 +298,34 @@ mg_status mg_gp_loglik(mg_handle_t handle, int64_t n, int64_t nrhs, double *A, i
                        void *work, size_t work_bytes, int32_t *info);
 
 /*
+ * Gradient of sum_j g_j loglik[j] (mg_gp_loglik) with respect to A, Y and M,
+ * from the factor and alpha that mg_gp_loglik returned (the log-det term's
+ * adjoint is -A^{-1}/2, the quadratic term's alpha alpha^T/2):
+ *   gA = sum_j g_j alpha_j alpha_j^T / 2 - (sum_j g_j) A^{-1} / 2
+ *        (full n x n, exactly symmetric: the gradient with respect to the
+ *        symmetric matrix, as MG_GRAD_SYM of mg_posv_backward),
+ *   gY[:, j] = -g_j alpha_j,   gM[:, j] = g_j alpha_j.
+ * A^{-1} = L^{-T} L^{-1} I is formed by the triangular sweeps with n
+ * right-hand sides (O(n^3) work, n^2 doubles of it in the workspace).
+ *   L       n x n factor from mg_gp_loglik (lower triangle read), lda >= n.
+ *   Alpha   n x nrhs from mg_gp_loglik (ldalpha >= n).
+ *   g       device double[nrhs]: the upstream gradient of each loglik.
+ *   gA      n x n output (ldga >= n); gY n x nrhs output (ldgy >= n);
+ *   gM      n x nrhs output (ldgm >= n) or NULL.
+ *   work    device workspace of mg_gp_loglik_grad_buffer_size bytes.
+ *   info    device int32 from mg_gp_loglik; nonzero makes every output NaN.
+ * Errors: -1 handle, -2 n < 0, -3 nrhs < 0, -4 L NULL, -5 lda, -6 Alpha NULL,
+ * -7 ldalpha, -8 g NULL, -9 gA NULL, -10 ldga, -11 gY NULL, -12 ldgy,
+ * -14 ldgm (gM given), -15 work NULL, -16 work_bytes too small, -17 info NULL;
+ * MG_ERR_UNSUPPORTED when n > 16 * 65535.
+ */
+mg_status mg_gp_loglik_grad_buffer_size(mg_handle_t handle, int64_t n, size_t *bytes);
+mg_status mg_gp_loglik_grad(mg_handle_t handle, int64_t n, int64_t nrhs, const double *L, int64_t lda,
+                            const double *Alpha, int64_t ldalpha, const double *g, double *gA, int64_t ldga,
+                            double *gY, int64_t ldgy, double *gM, int64_t ldgm, void *work, size_t work_bytes,
+                            const int32_t *info);
+
+/*
  * Profiling.  When enabled, every launch of the kernel kinds below is
  * bracketed by a pair of HIP events on the handle's stream, and the
  * algorithmic work of each launch is accumulated.

@@ -29,6 +29,9 @@ optionally with log det):
                    Impact Statement, "Scientific applications", Cholesky
                    solve): -1/2 r^T A^{-1} r - 1/2 log det A - N/2 log(2 pi),
                    r = y - m, per column.
+* ``gp_loglik_grad`` -- its gradient weighted by g: dA = sum_j g_j
+                   (alpha_j alpha_j^T - A^{-1}) / 2 (symmetric), dY = -g alpha,
+                   dM = g alpha.
 """
 from __future__ import annotations
 
@@ -250,3 +253,28 @@ def gp_loglik(A, Y, M=None):
     ll = np.array([-0.5 * math.fsum(R[:, j] * alpha[:, j]) - 0.5 * ld - 0.5 * n * math.log(2.0 * math.pi)
                    for j in range(k)])
     return (ll[0] if flat else ll), (alpha.ravel() if flat else alpha), 0
+
+
+def gp_loglik_grad(A, Y, M=None, g=None):
+    """Gradient of sum_j g_j log L_j (gp_loglik) with respect to the
+    symmetric A, to Y and to M, from the definitions: alpha_j = A^{-1} r_j,
+    A^{-1} from the factor by solving against the identity (its lower
+    triangle mirrored, so the result is exactly symmetric), then
+    dA = sum_j g_j alpha_j alpha_j^T / 2 - (sum_j g_j) A^{-1} / 2,
+    dY = -g alpha, dM = g alpha.  Returns (dA, dY, dM, info)."""
+    L, info = potrf(A)
+    Y2, flat = _as2d(Y)
+    R = _f64(Y2).copy(order="F")
+    if M is not None:
+        R = R - _f64(_as2d(M)[0])
+    n, k = R.shape
+    gv = np.ones(k) if g is None else np.asarray(g, dtype=np.float64).reshape(k)
+    if info != 0:
+        nanv = np.full(R.shape, np.nan)
+        return np.full((n, n), np.nan), (nanv.ravel() if flat else nanv), (nanv.ravel() if flat else nanv), info
+    alpha = potrs(L, R)
+    Ainv = potrs(L, np.eye(n))
+    Ainv = np.tril(Ainv) + np.tril(Ainv, -1).T
+    dA = 0.5 * (alpha * gv) @ alpha.T - 0.5 * gv.sum() * Ainv
+    dY = -alpha * gv
+    return dA, (dY.ravel() if flat else dY), (-dY.ravel() if flat else -dY), 0

@@ -20,7 +20,7 @@ from ._lib import MgError, call, load, raw  # noqa: F401
 
 __all__ = [
     "Handle", "handle", "potrf", "potrs", "posv", "posv_mixed", "posv_backward", "PosvFunction", "BatchPlan",
-    "posv_batched", "logdet", "gp_loglik", "colmajor",
+    "posv_batched", "logdet", "gp_loglik", "gp_loglik_grad", "GPLogLik", "colmajor",
     "MgError", "load", "call", "raw",
 ]
 
@@ -225,6 +225,34 @@ def gp_loglik(A, Y, M=None):
     return ll, alpha, Lc.T, info
 
 
+def gp_loglik_grad(L, alpha, g, info, with_mean: bool = True):
+    """Gradients of sum_j g_j loglik_j (see gp_loglik) from its factor L
+    and alpha: returns (gA, gY, gM) with gA the full symmetric n x n
+    gradient (alpha alpha^T - A^{-1}) / 2 weighted by g, gY = -g alpha and
+    gM = g alpha (None unless with_mean)."""
+    torch = _torch()
+    flat = alpha.dim() == 1
+    n = L.shape[0]
+    nrhs = 1 if flat else alpha.shape[1]
+    h = handle()
+    Lc = L.T.contiguous()
+    Ac = (alpha.reshape(n, 1) if flat else alpha).T.contiguous()
+    gv = torch.as_tensor(g, dtype=torch.float64, device=L.device).reshape(nrhs).contiguous()
+    gA = torch.empty((n, n), dtype=torch.float64, device=L.device)
+    gY = torch.empty((nrhs, n), dtype=torch.float64, device=L.device)
+    gM = torch.empty((nrhs, n), dtype=torch.float64, device=L.device) if with_mean else None
+    wb = ctypes.c_size_t()
+    call("mg_gp_loglik_grad_buffer_size", h.h, n, ctypes.byref(wb))
+    work = torch.empty(max(1, wb.value), dtype=torch.uint8, device=L.device)
+    call("mg_gp_loglik_grad", h.h, n, nrhs, _ptr(Lc), max(1, n), _ptr(Ac), max(1, n), _ptr(gv), _ptr(gA),
+         max(1, n), _ptr(gY), max(1, n), None if gM is None else _ptr(gM), max(1, n), _ptr(work), wb.value,
+         _ptr(info))
+    gY = gY.T.reshape(n) if flat else gY.T
+    if gM is not None:
+        gM = gM.T.reshape(n) if flat else gM.T
+    return gA, gY, gM   # gA is symmetric, so its row-major buffer is also the column-major one
+
+
 def posv_mixed(A, B, precision: str = "fp32", tol: float = 1e-12, max_iter: int = 30, fallback: bool = True):
     """Solve A X = B (FP64 A, B) with a binary32 (``precision="fp32"``) or
     bfloat16-update (``"bf16"``) factor and FP64 iterative refinement.
@@ -309,16 +337,46 @@ def _make_posv_function():
     return PosvFunction
 
 
+def _make_gp_function():
+    import torch
+
+    class GPLogLik(torch.autograd.Function):
+        """log L = gp_loglik(A, Y, M) (one value per column of Y) with a
+        hand-written adjoint from the stored factor: dA = (alpha alpha^T -
+        A^{-1}) / 2 (symmetric), dY = -alpha, dM = alpha.  ``M`` may be
+        None (zero mean)."""
+
+        @staticmethod
+        def forward(ctx, A, Y, M=None):
+            ll, alpha, L, info = gp_loglik(A, Y, M)
+            ctx.save_for_backward(L, alpha, info)
+            ctx.with_mean = M is not None
+            return ll
+
+        @staticmethod
+        def backward(ctx, g):
+            L, alpha, info = ctx.saved_tensors
+            gA, gY, gM = gp_loglik_grad(L, alpha, g, info, with_mean=ctx.with_mean)
+            return gA, gY, gM
+
+    return GPLogLik
+
+
 class _LazyFunction:
-    _cls = None
+    def __init__(self, make):
+        self._make = make
+        self._cls = None
 
     def __getattr__(self, name):
-        if _LazyFunction._cls is None:
-            _LazyFunction._cls = _make_posv_function()
-        return getattr(_LazyFunction._cls, name)
+        if name.startswith("_"):
+            raise AttributeError(name)
+        if self._cls is None:
+            self._cls = self._make()
+        return getattr(self._cls, name)
 
 
-PosvFunction = _LazyFunction()
+PosvFunction = _LazyFunction(_make_posv_function)
+GPLogLik = _LazyFunction(_make_gp_function)
 
 
 class BatchPlan:

@@ -59,6 +59,8 @@ SIGNATURES = {
     "mg_logdet": (i32, [vp, i32, i64, vp, i64, vp, vp]),
     "mg_gp_loglik_buffer_size": (i32, [vp, i64, i64, ctypes.POINTER(sz)]),
     "mg_gp_loglik": (i32, [vp, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, vp, sz, vp]),
+    "mg_gp_loglik_grad_buffer_size": (i32, [vp, i64, ctypes.POINTER(sz)]),
+    "mg_gp_loglik_grad": (i32, [vp, i64, i64, vp, i64, vp, i64, vp, vp, i64, vp, i64, vp, i64, vp, sz, vp]),
     "mg_set_profiling": (i32, [vp, i32]),
     "mg_set_profiling_kinds": (i32, [vp, ctypes.c_uint32]),
     "mg_profile_query": (i32, [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl),

@@ -105,3 +105,62 @@ def test_not_spd_and_edges(mg):
     # n = 0: log L = 0 for every column
     ll0, _, _, info0 = mg.gp_loglik(_dev(np.zeros((0, 0))), _dev(np.zeros((0, 3))))
     assert int(info0) == 0 and ll0.shape == (3,) and torch.equal(ll0, torch.zeros(3, dtype=torch.float64, device="cuda"))
+
+
+# ------------------------------------------------------------------ gradient
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (65, 3), (300, 1), (300, 4)])
+def test_gradient_parity(mg, orc, n, nrhs):
+    """gA = sum_j g_j (alpha_j alpha_j^T - A^{-1}) / 2 against the oracle
+    (relative Frobenius error <= 1e-11; A is well conditioned), gY and gM
+    element by element, gA exactly symmetric."""
+    A = synth.gram_spd(n, 70 + n)
+    Y = synth.normal((n, nrhs), 71 + n)
+    M = synth.normal((n, nrhs), 72 + n)
+    g = synth.normal(nrhs, 73 + n)
+    ll, alpha, L, info = mg.gp_loglik(_dev(A), _dev(Y), _dev(M))
+    gA, gY, gM = mg.gp_loglik_grad(L, alpha, _dev(g), info)
+    dA, dY, dM, oinfo = orc.gp_loglik_grad(A, Y, M, g)
+    assert int(info) == 0 and oinfo == 0
+    assert torch.equal(gA, gA.T)
+    gAh = gA.cpu().numpy()
+    assert np.linalg.norm(gAh - dA) <= 1e-11 * np.linalg.norm(dA)
+    assert np.allclose(gY.cpu().numpy(), dY, rtol=1e-12, atol=1e-14 * np.abs(dY).max())
+    assert np.allclose(gM.cpu().numpy(), dM, rtol=1e-12, atol=1e-14 * np.abs(dM).max())
+
+
+def test_autograd_and_finite_differences(mg, orc):
+    n, nrhs = 24, 2
+    A0 = synth.gram_spd(n, 80)
+    Y0 = synth.normal((n, nrhs), 81)
+    M0 = synth.normal((n, nrhs), 82)
+    w = np.array([0.6, -1.7])
+    A = _dev(A0).requires_grad_(True)
+    Y = _dev(Y0).requires_grad_(True)
+    M = _dev(M0).requires_grad_(True)
+    ll = mg.GPLogLik.apply(A, Y, M)
+    (ll * _dev(w)).sum().backward()
+    dA, dY, dM, _ = orc.gp_loglik_grad(A0, Y0, M0, w)
+    assert np.linalg.norm(A.grad.cpu().numpy() - dA) <= 1e-11 * np.linalg.norm(dA)
+    assert np.allclose(Y.grad.cpu().numpy(), dY, rtol=1e-12) and np.allclose(M.grad.cpu().numpy(), dM, rtol=1e-12)
+
+    def f(Ah):
+        return float((mg.gp_loglik(_dev(Ah), _dev(Y0), _dev(M0))[0].cpu().numpy() * w).sum())
+
+    h = 1e-6
+    gA = A.grad.cpu().numpy()
+    for i, j in [(0, 0), (5, 2), (23, 23), (17, 9), (23, 0)]:
+        E = np.zeros((n, n))
+        E[i, j] = E[j, i] = 1.0
+        fd = (f(A0 + h * E) - f(A0 - h * E)) / (2 * h)
+        want = gA[i, j] if i == j else gA[i, j] + gA[j, i]
+        assert fd == pytest.approx(want, rel=1e-6, abs=1e-8)
+
+
+def test_gradient_after_failed_factor_is_nan(mg):
+    n = 50
+    A = np.eye(n)
+    A[10, 10] = -1.0
+    y = synth.normal(n, 90)
+    ll, alpha, L, info = mg.gp_loglik(_dev(A), _dev(y))
+    gA, gY, gM = mg.gp_loglik_grad(L, alpha, _dev(np.ones(1)), info)
+    assert int(info) == 11 and torch.isnan(gA).all() and torch.isnan(gY).all() and torch.isnan(gM).all()

@@ -424,3 +424,38 @@ def test_gp_loglik_special_cases(orc):
     B[7, 7] = -1.0
     llb, ab, infob = orc.gp_loglik(B, y, m)
     assert infob == 8 and math.isnan(llb) and np.array_equal(ab, y - m)
+
+
+def test_gp_loglik_grad_closed_forms_and_finite_differences(orc):
+    # diagonal A: alpha = r / d, dA = g (alpha alpha^T - diag(1 / d)) / 2, dY = -g r / d
+    n = 40
+    d = 0.5 + synth.rng(60).random(n) * 3.0
+    y = synth.normal(n, 61)
+    dA, dY, dM, info = orc.gp_loglik_grad(np.diag(d), y, None, g=[2.0])
+    assert info == 0
+    assert np.allclose(dA, np.outer(y / d, y / d) - np.diag(1.0 / d), rtol=1e-13, atol=1e-15)
+    assert np.allclose(dY, -2.0 * y / d, rtol=1e-14) and np.allclose(dM, 2.0 * y / d, rtol=1e-14)
+    # A = I: dA = (r r^T - I) / 2
+    dA, _, _, _ = orc.gp_loglik_grad(np.eye(n), y)
+    assert np.allclose(dA, 0.5 * (np.outer(y, y) - np.eye(n)), rtol=1e-14, atol=1e-15)
+    # central differences of the oracle's own log L along symmetric directions
+    n = 10
+    A = synth.gram_spd(n, 62)
+    Y = synth.normal((n, 2), 63)
+    M = synth.normal((n, 2), 64)
+    g = np.array([0.7, -1.3])
+    dA, dY, dM, _ = orc.gp_loglik_grad(A, Y, M, g)
+    f = lambda A_, Y_, M_: float(np.dot(g, orc.gp_loglik(A_, Y_, M_)[0]))
+    h = 1e-6
+    for i in range(n):
+        for j in range(i + 1):
+            E = np.zeros((n, n))
+            E[i, j] = E[j, i] = 1.0
+            fd = (f(A + h * E, Y, M) - f(A - h * E, Y, M)) / (2 * h)
+            want = dA[i, j] if i == j else dA[i, j] + dA[j, i]
+            assert fd == pytest.approx(want, rel=1e-6, abs=1e-8)
+    for i in range(n):
+        E = np.zeros((n, 2))
+        E[i, 1] = 1.0
+        assert (f(A, Y + h * E, M) - f(A, Y - h * E, M)) / (2 * h) == pytest.approx(dY[i, 1], rel=1e-6, abs=1e-8)
+        assert (f(A, Y, M + h * E) - f(A, Y, M - h * E)) / (2 * h) == pytest.approx(dM[i, 1], rel=1e-6, abs=1e-8)
