@@ -72,9 +72,11 @@ mg_status mg_set_block_size(mg_handle_t handle, int64_t nb);
  * diagonal block and panel can be factored right away, and the remainder,
  * applied concurrently.  The two run on two non-blocking streams owned by the
  * handle, which fork from and join into the handle's stream by events.  0
- * runs every step in sequence on the handle's stream.  The result is bitwise
- * the same either way.
- * Errors: -1 NULL handle. */
+ * runs every step in sequence on the handle's stream; 2 is the look-ahead
+ * with the remainder's stream CU-masked to leave one CU per XCD to the
+ * next block column's factor (measured no faster; kept as an option).  The
+ * result is bitwise the same in every mode.
+ * Errors: -1 NULL handle, -2 mode not 0, 1 or 2. */
 mg_status mg_set_lookahead(mg_handle_t handle, int32_t enable);
 
 /* Block size potrf would use for (dtype, n).  Errors: -1, -2, -3 (n < 0), -4 NULL. */

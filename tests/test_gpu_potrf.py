@@ -239,19 +239,23 @@ def test_wide_block_columns(mg, orc, n, nb):
 # ----------------------------------------------------------- look-ahead
 @pytest.mark.parametrize("n,nb", [(1000, 128), (2100, 256), (4100, 128), (2600, 512)])
 def test_lookahead_matches_serial_schedule_bitwise(mg, orc, n, nb):
-    """The look-ahead schedule only reorders launches across two streams; every
-    tile sees the same arithmetic, so the factor is bitwise identical."""
+    """The look-ahead schedule only reorders launches across two streams (in
+    mode 2 the second one CU-masked); every tile sees the same arithmetic, so
+    the factor is bitwise identical to the serial schedule's."""
     A = synth.gram_spd_cond(n, 77 + n, 1e4)
     h = mg.handle()
     outs = []
-    for la in (1, 0):
-        assert mg.raw("mg_set_lookahead", h.h, la) == 0
-        L, info = mg.potrf(torch.from_numpy(A).cuda(), nb=nb)
-        torch.cuda.synchronize()
-        assert int(info) == 0
-        outs.append(np.tril(L.cpu().numpy()))
-    assert mg.raw("mg_set_lookahead", h.h, 1) == 0
+    try:
+        for la in (1, 0, 2):
+            assert mg.raw("mg_set_lookahead", h.h, la) == 0
+            L, info = mg.potrf(torch.from_numpy(A).cuda(), nb=nb)
+            torch.cuda.synchronize()
+            assert int(info) == 0
+            outs.append(np.tril(L.cpu().numpy()))
+    finally:
+        assert mg.raw("mg_set_lookahead", h.h, 1) == 0
     assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[2], outs[1])
     Lo, _ = orc.potrf(A)
     kappa = np.linalg.cond(A)
     assert np.linalg.norm(outs[0] - Lo) / np.linalg.norm(Lo) <= 8 * kappa * n * EPS
