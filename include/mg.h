@@ -233,7 +233,7 @@ mg_status mg_posv_backward(mg_handle_t handle, int64_t n, int64_t nrhs, const do
 typedef struct mg_batch_plan_s *mg_batch_plan_t;
 typedef struct {
     int32_t autotune;     /* 1: time the candidates (default), 0: use the fields below */
-    int32_t grid_per_cu;  /* workgroups per CU (1 or 2); 0 = default */
+    int32_t grid_per_cu;  /* workgroups per CU (1..8; the autotuner tries 1 to 3); 0 = default */
     int32_t order;        /* 0 longest first, 1 input order, -1 default */
     const char *cache_path;  /* tuning cache file or NULL */
 } mg_tune_opts;

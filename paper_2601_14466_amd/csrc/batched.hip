@@ -204,8 +204,12 @@ __device__ __forceinline__ int solve_one(T* __restrict__ A, int64_t lda, int n, 
     return 0;
 }
 
+// Two workgroups per CU for binary64 (256 VGPRs and the 75 KB row block of L
+// in LDS); three for binary32, whose smaller LDS footprint lets the register
+// cap of 168 decide: the solve is bound by memory latency, and the third
+// workgroup hides more of it than the few spilled registers cost.
 template <typename T, int NRHS_MAX>
-__global__ __launch_bounds__(256, 2) void k_batched_posv(BatchArgs<T> a) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_batched_posv(BatchArgs<T> a) {
     __shared__ T Zs[16][BMAX + 1];
     __shared__ T Ls[16 * 17], Lsc[16 * 17], piv[16];
     __shared__ T bv[NRHS_MAX * BMAX];
@@ -433,7 +437,7 @@ static mg_status autotune(mg_batch_plan_s* p, hipStream_t st) {
         }
         double best = 1e300;
         PlanCfg bestc = p->cfg;
-        for (int gpc = 1; gpc <= 2 && rc == MG_OK; ++gpc) {
+        for (int gpc = 1; gpc <= 3 && rc == MG_OK; ++gpc) {
             for (int ord = 0; ord <= 1 && rc == MG_OK; ++ord) {
                 p->cfg.grid_per_cu = gpc;
                 p->cfg.order = ord;

@@ -109,7 +109,7 @@ def test_autotune_and_cache(mg, orc, tmp_path):
     cache = str(tmp_path / "tune.txt")
     plan = mg.BatchPlan(sizes, nrhs=1, autotune=True, cache_path=cache)
     inf = plan.info()
-    assert inf["grid_per_cu"] in (1, 2) and inf["order"] in (0, 1) and inf["tuned_ms"] > 0
+    assert inf["grid_per_cu"] in (1, 2, 3) and inf["order"] in (0, 1) and inf["tuned_ms"] > 0
     assert os.path.exists(cache)
     plan2 = mg.BatchPlan(sizes, nrhs=1, autotune=True, cache_path=cache)
     assert plan2.info() == inf            # served from the cache
