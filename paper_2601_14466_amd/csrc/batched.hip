@@ -72,7 +72,7 @@ __device__ __forceinline__ int solve_one(T* __restrict__ A, int64_t lda, int n, 
                     d = mma_xzt(d, Zs[i][kk], -Zs[i][kk]);
                 }
             }
-            const int f = factor16<T>(d);
+            const int f = factor16<T, sizeof(T) == 8>(d);  // binary32: within the 168-register cap
             if (f) {
                 if (l == 0) *s_fail = 16 * j + f;
             } else {

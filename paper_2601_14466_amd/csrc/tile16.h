@@ -156,25 +156,37 @@ __device__ __forceinline__ float rsqrt_nr(float p) {
 }
 
 // In-register Cholesky of a 16x16 SPD tile (lower part significant).  Column
-// by column: the pivot p is read from its lane, column c is scaled by
-// p^(-1/2) (its diagonal entry becomes p p^(-1/2)), and the columns to its
-// right receive the rank-1 update; the lane shuffles that fetch L[j][c] are
-// issued starting with the register that holds column c + 1, the next step's
-// dependency.  Returns 0, or c+1 for the first local column whose pivot is
-// not > 0 (NaN included); the decision is uniform across the wave.  The
-// columns after a failing one are computed on meaningless values (no exit
-// per column, so the compiler can schedule across columns) and, like the
-// entries above the diagonal, are unspecified.
-template <typename C>
+// by column: column c is scaled by p^(-1/2) (its diagonal entry becomes
+// p p^(-1/2)), and the columns to its right receive the rank-1 update; the
+// lane shuffles that fetch L[j][c] are issued starting with the register that
+// holds column c + 1.  The next pivot, Y[c+1][c+1] - L[c+1][c]^2, is formed
+// from two lane reads taken before the update, with the same fused
+// multiply-add the lanes apply (so it is bitwise the value the lane then
+// holds), which keeps the shuffles off the chain of pivots (PIVOT_AHEAD;
+// without it each pivot is read from its lane after the update, for callers
+// whose register cap leaves no room for the extra live values).  Returns 0, or
+// c+1 for the first local column whose pivot is not > 0 (NaN included); the
+// decision is uniform across the wave.  The columns after a failing one are
+// computed on meaningless values (no exit per column, so the compiler can
+// schedule across columns) and, like the entries above the diagonal, are
+// unspecified.
+template <typename C, bool PIVOT_AHEAD = true>
 __device__ __forceinline__ int factor16(V4<C>& y) {
     const int l = lane_id(), i = l & 15, g = l >> 4;
     int fail = 0;
+    C p = readlane(y[treg<C>(0)], tgrp<C>(0) * 16);
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
         const int gc = tgrp<C>(c), rc = treg<C>(c);
-        const C p = readlane(y[rc], gc * 16 + c);
+        if constexpr (!PIVOT_AHEAD) p = readlane(y[rc], gc * 16 + c);
         if (fail == 0 && !(p > (C)0)) fail = c + 1;
         const C rs = rsqrt_nr(p);
+        C pn = (C)0;
+        if (PIVOT_AHEAD && c < 15) {
+            const C ynn = readlane(y[treg<C>(c + 1)], tgrp<C>(c + 1) * 16 + c + 1);  // Y[c+1][c+1]
+            const C lnc = readlane(y[rc], gc * 16 + c + 1) * rs;                       // L[c+1][c]
+            pn = __builtin_fma(-lnc, lnc, ynn);
+        }
         const C v = rowbcast(y[rc], gc);   // Y[i][c]
         const C lic = (i > c) ? v * rs : (i == c ? p * rs : (C)0);
         y[rc] = (g == gc) ? lic : y[rc];
@@ -184,9 +196,11 @@ __device__ __forceinline__ int factor16(V4<C>& y) {
             const int r = (rn + q) & 3;
             const int j = tcol<C>(g, r);
             const C ljc = shfl(lic, j);         // L[j][c] sits in lane j (group 0)
-            const C t = y[r] - lic * ljc;
+            // (the early pivot must equal this value bit for bit: same fma)
+            const C t = PIVOT_AHEAD ? __builtin_fma(-lic, ljc, y[r]) : y[r] - lic * ljc;
             y[r] = (j > c) ? t : y[r];
         }
+        if constexpr (PIVOT_AHEAD) p = pn;
     }
     return fail;
 }
