@@ -159,36 +159,42 @@ __device__ __forceinline__ float rsqrt_nr(float p) {
 // by column: column c is scaled by p^(-1/2) (its diagonal entry becomes
 // p p^(-1/2)), and the columns to its right receive the rank-1 update; the
 // lane shuffles that fetch L[j][c] are issued starting with the register that
-// holds column c + 1.  The next pivot, Y[c+1][c+1] - L[c+1][c]^2, is formed
-// from two lane reads taken before the update, with the same fused
-// multiply-add the lanes apply (so it is bitwise the value the lane then
-// holds), which keeps the shuffles off the chain of pivots (PIVOT_AHEAD;
-// without it each pivot is read from its lane after the update, for callers
-// whose register cap leaves no room for the extra live values).  Returns 0, or
-// c+1 for the first local column whose pivot is not > 0 (NaN included); the
-// decision is uniform across the wave.  The columns after a failing one are
-// computed on meaningless values (no exit per column, so the compiler can
-// schedule across columns) and, like the entries above the diagonal, are
-// unspecified.
+// holds column c + 1.  With PIVOT_AHEAD the next column is also formed
+// directly, in every lane group:
+//   Y[i][c+1] - L[i][c] L[c+1][c],
+// from its row broadcast taken before the update and the lane read of
+// L[c+1][c]. It uses the same fused multiply-add as the lanes' update, so it
+// is bitwise the value the lanes end up holding; its entry c+1 is the next
+// pivot. The chain from column to column then runs through lane reads and
+// FMAs only, and the shuffles have a column of slack. Without PIVOT_AHEAD
+// (for callers whose register cap leaves no room for the carried column),
+// each column is broadcast from the updated registers.  Returns 0, or c+1 for
+// the first local column whose pivot is not > 0 (NaN included); the decision
+// is uniform across the wave.  The columns after a failing one are computed
+// on meaningless values (no exit per column, so the compiler can schedule
+// across columns) and, like the entries above the diagonal, are unspecified.
 template <typename C, bool PIVOT_AHEAD = true>
 __device__ __forceinline__ int factor16(V4<C>& y) {
     const int l = lane_id(), i = l & 15, g = l >> 4;
     int fail = 0;
-    C p = readlane(y[treg<C>(0)], tgrp<C>(0) * 16);
+    C p = readlane(y[treg<C>(0)], tgrp<C>(0) * 16);  // pivot of column c
+    C vc = rowbcast(y[treg<C>(0)], tgrp<C>(0));      // column c: Y[i][c] in lane group g, row i
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
         const int gc = tgrp<C>(c), rc = treg<C>(c);
-        if constexpr (!PIVOT_AHEAD) p = readlane(y[rc], gc * 16 + c);
+        if constexpr (!PIVOT_AHEAD) {
+            p = readlane(y[rc], gc * 16 + c);
+            vc = rowbcast(y[rc], gc);
+        }
         if (fail == 0 && !(p > (C)0)) fail = c + 1;
         const C rs = rsqrt_nr(p);
-        C pn = (C)0;
+        const C lic = (i > c) ? vc * rs : (i == c ? p * rs : (C)0);
+        C vn = (C)0;
         if (PIVOT_AHEAD && c < 15) {
-            const C ynn = readlane(y[treg<C>(c + 1)], tgrp<C>(c + 1) * 16 + c + 1);  // Y[c+1][c+1]
-            const C lnc = readlane(y[rc], gc * 16 + c + 1) * rs;                       // L[c+1][c]
-            pn = __builtin_fma(-lnc, lnc, ynn);
+            const C yb = rowbcast(y[treg<C>(c + 1)], tgrp<C>(c + 1));  // Y[i][c+1] before the update
+            const C lnc = readlane(lic, c + 1);                           // L[c+1][c]
+            vn = __builtin_fma(-lic, lnc, yb);
         }
-        const C v = rowbcast(y[rc], gc);   // Y[i][c]
-        const C lic = (i > c) ? v * rs : (i == c ? p * rs : (C)0);
         y[rc] = (g == gc) ? lic : y[rc];
         const int rn = c < 15 ? treg<C>(c + 1) : 0;
 #pragma unroll
@@ -196,11 +202,16 @@ __device__ __forceinline__ int factor16(V4<C>& y) {
             const int r = (rn + q) & 3;
             const int j = tcol<C>(g, r);
             const C ljc = shfl(lic, j);         // L[j][c] sits in lane j (group 0)
-            // (the early pivot must equal this value bit for bit: same fma)
+            // (the carried column must equal this value bit for bit: same fma)
             const C t = PIVOT_AHEAD ? __builtin_fma(-lic, ljc, y[r]) : y[r] - lic * ljc;
             y[r] = (j > c) ? t : y[r];
         }
-        if constexpr (PIVOT_AHEAD) p = pn;
+        if constexpr (PIVOT_AHEAD) {
+            if (c < 15) {
+                vc = vn;
+                p = readlane(vn, c + 1);
+            }
+        }
     }
     return fail;
 }
