@@ -425,8 +425,8 @@ def main():
                     help="skip the mixed-precision, batched, adjoint and n=1024 measurements")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}); "
-              "the multi-GPU layout is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py: the solver runs on exactly one GPU (asked for --gpus {args.gpus}); "
+              "a multi-GPU layout is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2601_14466_amd as mg

@@ -637,7 +637,7 @@ int64_t potrf_block_size(mg_handle_t h, int64_t n, int es) {
     (void)es;
     if (h && h->nb > 0) return h->nb;
     // measured switch points (FP64 posv, look-ahead on): 64 is fastest up to
-    // n ~ 4096, 128 around 6144-8192, 256 from ~12288, 512 from ~24576
+    // n = 4096, 128 at 6144-8192, 256 at 12288, 512 at 24576 and above
     if (n >= 24576) return 512;
     if (n >= 10240) return 256;
     if (n >= 5120) return 128;
