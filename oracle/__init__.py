@@ -22,8 +22,13 @@ optionally with log det):
                    normwise backward error eta_j = |r_j|inf / (|A|inf |x_j|inf
                    + |b_j|inf).
 * ``logdet``    -- 2 sum log L_jj.
-* ``posv_ir``   -- single-precision (or bfloat16-operand) factor plus FP64
-                   iterative refinement; falls back to FP64 when it stalls.
+* ``potrf_lo``  -- low-precision factor: the column algorithm in binary32,
+                   or the blocked reading (FP64 diagonal blocks, binary32
+                   panel solve, operands of the trailing products rounded to
+                   binary32 or bfloat16, binary32 sums).
+* ``round_bf16``-- nearest-even rounding of binary32 values to bfloat16.
+* ``posv_ir``   -- low-precision factor plus FP64 iterative refinement;
+                   falls back to FP64 when it stalls.
 * ``posv_backward`` -- gB = A^{-1} gX, gA = -1/2 (gB X^T + X gB^T).
 * ``gp_loglik`` -- Gaussian-process marginal log likelihood (paper: Research
                    Impact Statement, "Scientific applications", Cholesky
@@ -84,8 +89,12 @@ def _load():
     lib.or_potrf_lo.restype = _i64
     lib.or_potrs_lo.argtypes = [_i64, _i64, _fp, _i64, _fp, _i64]
     lib.or_potrs_lo.restype = None
+    lib.or_potrf_lo_blocked.argtypes = [_i64, _fp, _i64, ctypes.c_int, _i64]
+    lib.or_potrf_lo_blocked.restype = _i64
+    lib.or_round_bf16_array.argtypes = [_i64, _fp, _fp]
+    lib.or_round_bf16_array.restype = None
     lib.or_posv_ir.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64,
-                               ctypes.c_int, ctypes.c_double, ctypes.c_int, _ip, _ip, _dp]
+                               ctypes.c_int, ctypes.c_double, ctypes.c_int, _i64, _ip, _ip, _dp, _dp, _ip]
     lib.or_posv_ir.restype = _i64
     lib.or_posv_backward.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64,
                                      _dp, _i64, _dp, _i64, ctypes.c_int]
@@ -179,19 +188,39 @@ def backward_error(A, X, B) -> np.ndarray:
     return residual(A, X, B)[1]
 
 
-def potrf_lo(A, lo: int = 1):
-    """Low-precision factor of fl32(A): lo=1 binary32, lo=2 bfloat16 operands."""
+def potrf_lo(A, lo: int = 1, nb: int = 0):
+    """Low-precision factor of fl32(A): lo=1 binary32, lo=2 bfloat16
+    operands in the trailing products.  nb = 0: the column algorithm with
+    every operation in binary32; nb > 0: the blocked reading (FP64 diagonal
+    blocks of nb columns stored rounded, binary32 panel solve, trailing
+    update with operands rounded to the working precision)."""
     lib = _load()
     W = np.asfortranarray(np.asarray(A, dtype=np.float64).astype(np.float32))
     n = W.shape[0]
-    info = lib.or_potrf_lo(n, _ptr(W, _fp), _ld(W), int(lo))
+    if nb > 0:
+        info = lib.or_potrf_lo_blocked(n, _ptr(W, _fp), _ld(W), int(lo), int(nb))
+    else:
+        info = lib.or_potrf_lo(n, _ptr(W, _fp), _ld(W), int(lo))
     return np.tril(W), int(info)
 
 
-def posv_ir(A, B, lo: int = 1, tol: float = 1e-12, max_iter: int = 30):
-    """Mixed-precision solve with FP64 iterative refinement.
+def round_bf16(x) -> np.ndarray:
+    """bfloat16 rounding (nearest-even) of binary32 values, widened back to
+    binary32 (bit patterns pass through unconverted, NaN payloads included)."""
+    lib = _load()
+    v = np.ascontiguousarray(np.asarray(x, dtype=np.float32)).ravel()
+    out = np.empty_like(v)
+    lib.or_round_bf16_array(v.size, _ptr(v, _fp), _ptr(out, _fp))
+    return out.reshape(np.shape(x))
 
-    Returns (X, dict(iters, fell_back, eta, info))."""
+
+def posv_ir(A, B, lo: int = 1, tol: float = 1e-12, max_iter: int = 30, nb: int = 128):
+    """Mixed-precision solve with FP64 iterative refinement; the
+    low-precision factor is the blocked one with block nb (0: the column
+    algorithm).
+
+    Returns (X, dict(iters, fell_back, eta, info, hist)); hist lists the
+    largest eta of every residual the refinement loop evaluated."""
     lib = _load()
     Af = _f64(A)
     B2, flat = _as2d(B)
@@ -200,10 +229,13 @@ def posv_ir(A, B, lo: int = 1, tol: float = 1e-12, max_iter: int = 30):
     X = np.zeros((n, nrhs), dtype=np.float64, order="F")
     iters, fb = ctypes.c_int(0), ctypes.c_int(0)
     eta = ctypes.c_double(0.0)
+    hist = np.zeros(max(1, int(max_iter) + 1), dtype=np.float64)
+    nh = ctypes.c_int(0)
     info = lib.or_posv_ir(n, nrhs, _ptr(Af), _ld(Af), _ptr(Bf), _ld(Bf), _ptr(X), _ld(X),
-                          int(lo), float(tol), int(max_iter),
-                          ctypes.byref(iters), ctypes.byref(fb), ctypes.byref(eta))
-    stats = dict(iters=iters.value, fell_back=bool(fb.value), eta=eta.value, info=int(info))
+                          int(lo), float(tol), int(max_iter), int(nb),
+                          ctypes.byref(iters), ctypes.byref(fb), ctypes.byref(eta), _ptr(hist), ctypes.byref(nh))
+    stats = dict(iters=iters.value, fell_back=bool(fb.value), eta=eta.value, info=int(info),
+                 hist=hist[:nh.value].tolist())
     return (X.ravel() if flat else X), stats
 
 

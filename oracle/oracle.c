@@ -25,6 +25,15 @@
  *                eta_j = |r_j|_inf / (|A|_inf |x_j|_inf + |b_j|_inf), the
  *                Rigal-Gaches normwise backward error of column j.
  *   or_logdet  : log det A = 2 sum_j log L_jj (the paper's optional output).
+ *   or_potrf_lo_blocked: the low-precision factor of the mixed-precision
+ *                reading (the paper is silent on precision): right-looking
+ *                blocks of nb columns; each diagonal block is promoted to
+ *                FP64, factored by or_potrf and stored rounded to binary32;
+ *                the panel below it is solved by substitution in binary32;
+ *                the trailing matrix receives the block's rank-nb product
+ *                with its operands rounded to the working precision
+ *                (binary32, or bfloat16 when lo == 2) and the products
+ *                summed in binary32.
  *   or_posv_ir : mixed-precision iterative refinement (the paper is silent;
  *                this is the classic scheme of Langou et al., SC'06): factor
  *                a single-precision copy, solve, then repeat
@@ -221,8 +230,10 @@ double or_residual(int64_t n, int64_t nrhs, const double *A, int64_t lda,
 
 /* --------------------------------------------- mixed precision refinement */
 /* Round a binary32 value to bfloat16 (8-bit significand), nearest-even, on
- * the bit pattern, and return it widened back to binary32. */
-static float round_bf16(float x)
+ * the bit pattern, and return it widened back to binary32.  Infinities and
+ * NaNs pass through unchanged; a finite value above the largest bfloat16
+ * number (by at least half an ulp) becomes an infinity. */
+float or_round_bf16(float x)
 {
     uint32_t u;
     memcpy(&u, &x, 4);
@@ -233,6 +244,14 @@ static float round_bf16(float x)
     float y;
     memcpy(&y, &u, 4);
     return y;
+}
+
+/* or_round_bf16 over an array (bit patterns in and out untouched by any
+ * host-side conversion). */
+void or_round_bf16_array(int64_t n, const float *in, float *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = or_round_bf16(in[i]);
 }
 
 /* Low-precision Cholesky of the binary32 copy W (lower, in place).  Every
@@ -249,10 +268,10 @@ int64_t or_potrf_lo(int64_t n, float *W, int64_t ldw, int lo)
             int64_t i0 = j + (m * t) / nt, i1 = j + (m * (t + 1)) / nt;
             for (int64_t k = 0; k < j; ++k) {
                 float b = AT(W, ldw, j, k);
-                if (lo == 2) b = round_bf16(b);
+                if (lo == 2) b = or_round_bf16(b);
                 for (int64_t i = i0; i < i1; ++i) {
                     float a = AT(W, ldw, i, k);
-                    if (lo == 2) a = round_bf16(a);
+                    if (lo == 2) a = or_round_bf16(a);
                     AT(W, ldw, i, j) = AT(W, ldw, i, j) - a * b;
                 }
             }
@@ -265,6 +284,66 @@ int64_t or_potrf_lo(int64_t n, float *W, int64_t ldw, int lo)
         for (int64_t i = j + 1; i < n; ++i)
             AT(W, ldw, i, j) = AT(W, ldw, i, j) / d;
     }
+    return 0;
+}
+
+/* Blocked low-precision factor of the binary32 copy W (lower, in place),
+ * block width nb >= 1:
+ *   for each block column [k0, k1):
+ *     1. W_kk (FP32) -> FP64, Cholesky by or_potrf, stored rounded to FP32;
+ *        a failing pivot returns k0 + its local column (1-based);
+ *     2. rows i >= k1: L_ic = (W_ic - sum_{k0<=p<c} L_ip L_cp) / L_cc for
+ *        c = k0 .. k1-1, every operation in binary32, p increasing;
+ *     3. lower trailing entries (i >= j >= k1):
+ *        W_ij = W_ij - s,  s = sum_{p=k0}^{k1-1} r(L_ip) r(L_jp)
+ *        accumulated in binary32 from 0, p increasing, where r rounds to
+ *        bfloat16 when lo == 2 and is the identity otherwise.
+ * With nb >= n the whole matrix is one diagonal block: the result is the
+ * FP64 factor of fl32(A) rounded to binary32. */
+int64_t or_potrf_lo_blocked(int64_t n, float *W, int64_t ldw, int lo, int64_t nb)
+{
+    if (nb < 1)
+        nb = 1;
+    double *D = (double *)malloc((size_t)nb * (size_t)nb * sizeof(double));
+    for (int64_t k0 = 0; k0 < n; k0 += nb) {
+        int64_t kb = n - k0 < nb ? n - k0 : nb, k1 = k0 + kb;
+        for (int64_t j = 0; j < kb; ++j)
+            for (int64_t i = j; i < kb; ++i)
+                D[i + j * kb] = (double)AT(W, ldw, k0 + i, k0 + j);
+        int64_t f = or_potrf(kb, D, kb);
+        if (f != 0) {
+            free(D);
+            return k0 + f;
+        }
+        for (int64_t j = 0; j < kb; ++j)
+            for (int64_t i = j; i < kb; ++i)
+                AT(W, ldw, k0 + i, k0 + j) = (float)D[i + j * kb];
+#pragma omp parallel for schedule(static) if ((n - k1) * kb > 65536)
+        for (int64_t i = k1; i < n; ++i) {
+            for (int64_t c = k0; c < k1; ++c) {
+                float t = AT(W, ldw, i, c);
+                for (int64_t p = k0; p < c; ++p)
+                    t = t - AT(W, ldw, i, p) * AT(W, ldw, c, p);
+                AT(W, ldw, i, c) = t / AT(W, ldw, c, c);
+            }
+        }
+#pragma omp parallel for schedule(dynamic, 16) if ((n - k1) * kb > 65536)
+        for (int64_t j = k1; j < n; ++j) {
+            for (int64_t i = j; i < n; ++i) {
+                float s = 0.0f;
+                for (int64_t p = k0; p < k1; ++p) {
+                    float a = AT(W, ldw, i, p), b = AT(W, ldw, j, p);
+                    if (lo == 2) {
+                        a = or_round_bf16(a);
+                        b = or_round_bf16(b);
+                    }
+                    s = s + a * b;
+                }
+                AT(W, ldw, i, j) = AT(W, ldw, i, j) - s;
+            }
+        }
+    }
+    free(D);
     return 0;
 }
 
@@ -322,7 +401,10 @@ static double ir_residual(int64_t n, int64_t nrhs, const double *A, int64_t lda,
 /*
  * Mixed-precision solve with iterative refinement.
  *   1. W = fl32(A); factor W in low precision (lo = 1: binary32,
- *      lo = 2: bfloat16 operands in the Schur-complement products).
+ *      lo = 2: bfloat16 operands in the Schur-complement products): the
+ *      blocked factor or_potrf_lo_blocked with block nb when nb > 0, the
+ *      column algorithm or_potrf_lo (every operation in binary32) when
+ *      nb == 0.
  *   2. x = solve_lo(fl32(b)), widened to FP64.
  *   3. repeat: r = b - A x in FP64; stop when max_j eta_j <= tol;
  *      otherwise d = solve_lo(fl32(r)) and x = x + d in FP64.
@@ -330,13 +412,19 @@ static double ir_residual(int64_t n, int64_t nrhs, const double *A, int64_t lda,
  *      largest eta failing to halve on two consecutive iterations.
  *   5. On a low-precision breakdown or non-convergence: plain FP64 solve,
  *      *fell_back = 1.
+ * hist (NULL, or max_iter + 1 entries) receives the largest eta of every
+ * residual evaluated by the refinement loop, in order (entry k: after k
+ * corrections); *nhist receives how many were written.
  * Returns the FP64 info of the fallback (0 unless A itself is not SPD).
  */
 int64_t or_posv_ir(int64_t n, int64_t nrhs, const double *A, int64_t lda,
                    const double *B, int64_t ldb, double *X, int64_t ldx,
-                   int lo, double tol, int max_iter,
-                   int *iters, int *fell_back, double *eta_final)
+                   int lo, double tol, int max_iter, int64_t nb,
+                   int *iters, int *fell_back, double *eta_final,
+                   double *hist, int *nhist)
 {
+    if (nhist)
+        *nhist = 0;
     *iters = 0;
     *fell_back = 0;
     *eta_final = 0.0;
@@ -350,7 +438,7 @@ int64_t or_posv_ir(int64_t n, int64_t nrhs, const double *A, int64_t lda,
         for (int64_t i = j; i < n; ++i)
             W[i + j * nn] = (float)AT(A, lda, i, j);
     int converged = 0;
-    int64_t finfo = or_potrf_lo(n, W, n, lo);
+    int64_t finfo = nb > 0 ? or_potrf_lo_blocked(n, W, n, lo, nb) : or_potrf_lo(n, W, n, lo);
     if (finfo == 0) {
         for (int64_t r = 0; r < nrhs; ++r)
             for (int64_t i = 0; i < n; ++i)
@@ -365,6 +453,8 @@ int64_t or_posv_ir(int64_t n, int64_t nrhs, const double *A, int64_t lda,
         for (int it = 0;; ++it) {
             ir_residual(n, nrhs, A, lda, X, ldx, B, ldb, anorm, R, &e);
             *eta_final = e;
+            if (hist && nhist)
+                hist[(*nhist)++] = e;
             if (e <= tol) { converged = 1; *iters = it; break; }
             if (it >= max_iter || e != e) { *iters = it; break; }
             if (it > 0 && !(e <= 0.5 * prev)) ++slow; else slow = 0;

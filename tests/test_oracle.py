@@ -459,3 +459,175 @@ def test_gp_loglik_grad_closed_forms_and_finite_differences(orc):
         E[i, 1] = 1.0
         assert (f(A, Y + h * E, M) - f(A, Y - h * E, M)) / (2 * h) == pytest.approx(dY[i, 1], rel=1e-6, abs=1e-8)
         assert (f(A, Y, M + h * E) - f(A, Y, M - h * E)) / (2 * h) == pytest.approx(dM[i, 1], rel=1e-6, abs=1e-8)
+
+
+# ------------------------------------------------ bfloat16 rounding (by hand)
+# Round-to-nearest-even from binary32 (23 fraction bits) to bfloat16 (7): the
+# upper 16 bits are kept and the lower 16 decide, 0x8000 being the tie.  Each
+# row was worked out by hand; the last column names the slip it catches.
+BF16_TABLE = [
+    (0x3F800000, 0x3F800000, "1.0 is exact (any rounding)"),
+    (0x3F807FFF, 0x3F800000, "just below half an ulp rounds down (round-half-up on a wrong bit)"),
+    (0x3F808000, 0x3F800000, "tie with an even kept part rounds down (ties away from zero)"),
+    (0x3F818000, 0x3F820000, "tie with an odd kept part rounds up (truncation)"),
+    (0x3F80C000, 0x3F810000, "three quarters of an ulp rounds up (truncation)"),
+    (0x3FFF8000, 0x40000000, "tie, odd, significand carry into the exponent (masking the carry)"),
+    (0xBF818000, 0xBF820000, "negative tie: the magnitude rounds, the sign stays (sign handling)"),
+    (0x00018000, 0x00020000, "subnormal tie with an odd kept part rounds up"),
+    (0x7F7FFFFF, 0x7F800000, "largest binary32 is past the last bfloat16 midpoint: infinity"),
+    (0x7F800000, 0x7F800000, "+infinity passes through"),
+    (0xFF800000, 0xFF800000, "-infinity passes through"),
+    (0x7F800001, 0x7F800001, "NaN with a low payload stays that NaN (rounding would make it infinity)"),
+    (0x7FC12345, 0x7FC12345, "quiet NaN passes through unchanged"),
+]
+
+
+def _bits_to_f32(b):
+    return np.array(b, dtype=np.uint32).view(np.float32)
+
+
+def test_round_bf16_hand_worked_bit_patterns(orc):
+    ins = _bits_to_f32([r[0] for r in BF16_TABLE])
+    out = orc.round_bf16(ins).view(np.uint32)
+    for (a, want, why), got in zip(BF16_TABLE, out.tolist()):
+        assert got == want, f"{a:#010x} -> {got:#010x}, want {want:#010x}: {why}"
+
+
+def test_round_bf16_table_catches_wrong_roundings():
+    """Plausible wrong roundings (truncation, ties away from zero, no
+    special-value guard) each disagree with at least one hand-worked row.
+    Implemented on throw-away Python copies, never on the oracle."""
+    def ok(u):
+        if (u & 0x7F800000) == 0x7F800000:
+            return u
+        return (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+
+    def trunc(u):
+        return u & 0xFFFF0000
+
+    def away(u):
+        if (u & 0x7F800000) == 0x7F800000:
+            return u
+        return (u + 0x8000) & 0xFFFF0000
+
+    def unguarded(u):
+        return (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+
+    assert all(ok(a) == w for a, w, _ in BF16_TABLE)
+    for bad in (trunc, away, unguarded):
+        assert any(bad(a) != w for a, w, _ in BF16_TABLE), bad.__name__
+
+
+# --------------------------------------- blocked low-precision factor reading
+def test_blocked_lo_factor_one_block_is_fp64_factor_rounded(orc):
+    """nb >= n: the whole matrix is one diagonal block, so the blocked
+    factor is the FP64 Cholesky factor of fl32(A), rounded to binary32
+    (catches a diagonal block factored in binary32, or left unrounded)."""
+    n = 90
+    A = synth.haar_spd(n, 1e3, 41)
+    A32 = A.astype(np.float32).astype(np.float64)
+    L64, info = orc.potrf(A32)
+    assert info == 0
+    for lo in (1, 2):
+        Lb, info = orc.potrf_lo(A, lo, nb=n)
+        assert info == 0
+        assert np.array_equal(Lb, L64.astype(np.float32))
+        Lb, info = orc.potrf_lo(A, lo, nb=4 * n)
+        assert np.array_equal(Lb, L64.astype(np.float32))
+
+
+@pytest.mark.parametrize("lo", [1, 2])
+@pytest.mark.parametrize("nb", [1, 16, 64, 128])
+def test_blocked_lo_factor_integer_family_bitwise(orc, lo, nb):
+    """Every intermediate of the integer family is an integer below 2^24 and
+    every division is by a power of two; |L0| <= 3 is exact in bfloat16, so
+    the blocked factor reproduces L0 in both precisions whatever nb."""
+    L0, A = synth.integer_exact(150, 60 + nb)
+    Lb, info = orc.potrf_lo(A, lo, nb=nb)
+    assert info == 0
+    assert np.array_equal(Lb.astype(np.float64), L0)
+
+
+@pytest.mark.parametrize("b_bits,b_bf16", [
+    (0x3F802000, 1.0),               # 1 + 2^-10: below half a bfloat16 ulp -> 1
+    (0x3F80C000, 1.0 + 2.0 ** -7),   # 1 + 3 2^-9: above half -> 1 + 2^-7 (truncation would give 1)
+])
+def test_blocked_lo_factor_2x2_by_hand(orc, b_bits, b_bf16):
+    """A = [[1, b], [b, 4]], nb = 1.  Block 0: L11 = 1.  Panel: L21 = b / 1 =
+    b.  Trailing: binary32 mode W22 = 4 - fl32(b^2); bfloat16 mode
+    W22 = 4 - r(b)^2 with r(b) worked out by hand.  Then L22 =
+    fl32(sqrt(W22)) taken in FP64.  The two modes must differ (a no-op
+    bfloat16 rounding fails here)."""
+    b = float(_bits_to_f32([b_bits])[0])
+    A = np.array([[1.0, b], [b, 4.0]])
+    f32 = np.float32
+    w1 = f32(f32(4.0) - f32(f32(b) * f32(b)))
+    want1 = f32(np.sqrt(np.float64(w1)))
+    w2 = f32(f32(4.0) - f32(f32(b_bf16) * f32(b_bf16)))
+    want2 = f32(np.sqrt(np.float64(w2)))
+    assert want1 != want2
+    for lo, want in ((1, want1), (2, want2)):
+        Lb, info = orc.potrf_lo(A, lo, nb=1)
+        assert info == 0
+        assert Lb[0, 0] == 1.0 and Lb[1, 0] == f32(b) and Lb[1, 1] == want, (lo, Lb)
+
+
+def test_blocked_lo_factor_error_scales_with_working_precision(orc):
+    """Random SPD: the binary32 and bfloat16 factors differ, and each is
+    within its unit roundoff times kappa of the FP64 factor (Higham, Thm
+    10.5, normwise form); bfloat16 is the looser of the two."""
+    n = 200
+    A = synth.haar_spd(n, 1e2, 43)
+    L64, _ = orc.potrf(A)
+    L1, i1 = orc.potrf_lo(A, 1, nb=64)
+    L2, i2 = orc.potrf_lo(A, 2, nb=64)
+    assert i1 == 0 and i2 == 0
+    e1 = np.linalg.norm(L1 - L64) / np.linalg.norm(L64)
+    e2 = np.linalg.norm(L2 - L64) / np.linalg.norm(L64)
+    assert not np.array_equal(L1, L2)
+    assert e1 <= 1e2 * n * 2.0 ** -24
+    assert e2 <= 1e2 * n * 2.0 ** -8
+    assert e2 > 8 * e1
+
+
+@pytest.mark.parametrize("lo", [1, 2])
+def test_blocked_lo_factor_reports_first_bad_pivot(orc, lo):
+    d = np.ones(40)
+    d[25] = -1.0
+    for nb in (1, 8, 64):
+        _, info = orc.potrf_lo(np.diag(d), lo, nb=nb)
+        assert info == 26, (nb, info)
+
+
+# ------------------------------------------------------ refinement exits
+def test_ir_stagnation_exit(orc):
+    """tol = 0 cannot be met by an inexact solution, so refinement runs until
+    the largest eta fails to halve on two consecutive corrections, then falls
+    back to FP64.  The recorded eta history fixes where that must happen
+    (catches a stagnation rule that never fires, fires after one slow step,
+    or forgets to reset after a good one)."""
+    n = 60
+    A = synth.haar_spd(n, 1e2, 44)
+    xt = synth.normal((n, 2), 45)
+    B = A @ xt
+    X, st = orc.posv_ir(A, B, lo=1, tol=0.0, max_iter=30)
+    h = st["hist"]
+    k = st["iters"]
+    assert st["fell_back"] and st["info"] == 0
+    assert len(h) == k + 1 and 2 <= k < 30
+    assert all(e > 0.0 for e in h)
+    slow = [i >= 1 and not (h[i] <= 0.5 * h[i - 1]) for i in range(len(h))]
+    assert slow[k] and slow[k - 1]
+    assert not any(slow[i] and slow[i - 1] for i in range(1, k))
+    assert np.all(orc.backward_error(A, X, B) <= 1e-12)
+
+
+def test_ir_history_and_cap(orc):
+    """max_iter caps the corrections: with tol = 0 and max_iter = 1 the loop
+    evaluates two residuals and stops at the cap."""
+    n = 50
+    A = synth.haar_spd(n, 1e4, 46)
+    B = A @ synth.normal((n, 1), 47)
+    _, st = orc.posv_ir(A, B, lo=1, tol=0.0, max_iter=1)
+    assert st["iters"] == 1 and len(st["hist"]) == 2 and st["fell_back"]
+    assert st["hist"][1] < st["hist"][0]
