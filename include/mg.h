@@ -26,6 +26,10 @@
  *   order k is not positive definite (pivot <= 0 or NaN).  Factorisation
  *   stops there; columns >= k of the result are unspecified.  Kernels
  *   enqueued after a failure see the non-zero info and do nothing.
+ *   MG_INFO_SOLVE_ABORTED (negative) when a triangular sweep's bounded wait
+ *   for an earlier block gave up (which only a stalled device produces, or
+ *   mg_set_sweep_spin_limit(h, 0) on purpose): the solution is then filled
+ *   with quiet NaNs.
  */
 #ifndef MG_H_
 #define MG_H_
@@ -44,6 +48,9 @@ typedef struct mg_handle_s *mg_handle_t;
 #define MG_ERR_HIP 1          /* a HIP runtime call or kernel launch failed */
 #define MG_ERR_UNSUPPORTED 2  /* dtype, precision or option not supported */
 #define MG_ERR_INTERNAL 3     /* inconsistent internal state */
+#define MG_ERR_ABORTED 4      /* a synchronising call saw a triangular sweep give up waiting */
+
+#define MG_INFO_SOLVE_ABORTED (-1) /* device info: a sweep's bounded wait gave up */
 
 typedef enum { MG_F64 = 0, MG_F32 = 1 } mg_dtype;
 
@@ -78,6 +85,15 @@ mg_status mg_set_block_size(mg_handle_t handle, int64_t nb);
  * result is bitwise the same in every mode.
  * Errors: -1 NULL handle, -2 mode not 0, 1 or 2. */
 mg_status mg_set_lookahead(mg_handle_t handle, int32_t enable);
+
+/* Polls a triangular-sweep block makes for an earlier block's result before
+ * it gives up (the wait is bounded so that a stalled device cannot hang the
+ * call): -1 restores the built-in limit (2^22); 0 makes every block that
+ * depends on another give up at once without waiting, which drives the
+ * give-up path (info = MG_INFO_SOLVE_ABORTED, NaN solution) from the host for
+ * tests; positive values set the limit.
+ * Errors: -1 NULL handle, -2 limit outside [-1, 2^30]. */
+mg_status mg_set_sweep_spin_limit(mg_handle_t handle, int64_t limit);
 
 /* Block size potrf would use for (dtype, n).  Errors: -1, -2, -3 (n < 0), -4 NULL. */
 mg_status mg_get_block_size(mg_handle_t handle, mg_dtype dtype, int64_t n, int64_t *nb);
@@ -116,19 +132,22 @@ mg_status mg_potrs_buffer_size(mg_handle_t handle, mg_dtype dtype, int64_t n, in
  *   B      device, ldb x nrhs, overwritten with X.
  *   work   device scratch of mg_potrs_buffer_size bytes (may be NULL when
  *          that size is 0).
- *   info   optional device int32 from a preceding mg_potrf (NULL = absent);
- *          when it holds a non-zero value B is left unmodified.
+ *   info   optional device int32, in/out (NULL = absent): on entry the info
+ *          of a preceding mg_potrf -- when it is non-zero B is left
+ *          unmodified; set to MG_INFO_SOLVE_ABORTED when a sweep gives up
+ *          (B is then all NaN, which is also what happens with info NULL).
  * Errors: -1 NULL handle, -2 dtype, -3 n < 0, -4 nrhs < 0, -5 L NULL,
  *         -6 lda, -7 B NULL, -8 ldb < max(1,n), -9 work NULL, -10 work too small.
  */
 mg_status mg_potrs(mg_handle_t handle, mg_dtype dtype, int64_t n, int64_t nrhs, const void *L,
                    int64_t lda, void *B, int64_t ldb, void *work, size_t work_bytes,
-                   const int32_t *info);
+                   int32_t *info);
 
 /*
  * posv: factor then solve (potrf + potrs) with no host synchronisation.
  * A is overwritten by L; B by X unless info > 0, in which case B is left
- * unmodified.  Workspace: mg_potrs_buffer_size bytes.
+ * unmodified (info = MG_INFO_SOLVE_ABORTED: B is all NaN, as for mg_potrs).
+ * Workspace: mg_potrs_buffer_size bytes.
  * Errors: -1 handle, -2 dtype, -3 n, -4 nrhs, -5 A, -6 lda, -7 B, -8 ldb,
  *         -9 work NULL, -10 work too small, -11 info NULL.
  */
@@ -181,6 +200,13 @@ mg_status mg_posv_mixed_buffer_size(mg_handle_t handle, mg_prec lo, int64_t n, i
  *          not positive definite.
  * The call synchronises the handle's stream once per refinement step (the
  * stopping test reads eta on the host) and returns after the solve.
+ * Without a fallback (opts->fallback == 0): if the low-precision factor
+ * breaks down (result->lo_info > 0) there is no solution, X is filled with
+ * NaN and result->eta is NaN (info stays 0: A itself was not tested); if
+ * refinement stops without converging, X is the last iterate and
+ * result->eta its backward error (> tol).  If a triangular sweep gives up
+ * waiting (see mg_set_sweep_spin_limit) the call returns MG_ERR_ABORTED
+ * with X filled with NaN and result->eta NaN.
  * Errors: -1 handle, -2 lo, -3 n, -4 nrhs, -5 A, -6 lda, -7 B, -8 ldb, -9 X,
  *         -10 ldx, -11 opts (tol < 0 or max_iter < 0), -12 work NULL,
  *         -13 work too small, -14 result NULL, -15 info NULL.
@@ -202,8 +228,9 @@ mg_status mg_posv_mixed(mg_handle_t handle, mg_prec lo, int64_t n, int64_t nrhs,
  * FP64 only.  L: lda x n factor from mg_potrf; X: ldx x nrhs forward
  * solution; gX: ldgx x nrhs upstream gradient (read only); gB: ldgb x nrhs
  * output; gA: ldga x n output.  work: mg_potrs_buffer_size(MG_F64, n, nrhs)
- * bytes.  info: optional device int32 of the factorisation; when non-zero
- * nothing is written.
+ * bytes.  info: optional device int32 of the factorisation, in/out; when it
+ * is non-zero gB and the entries of gA the mode writes are NaN; a sweep that
+ * gives up sets it to MG_INFO_SOLVE_ABORTED (with the same NaN outputs).
  * Errors: -1 handle, -2 n, -3 nrhs, -4 L, -5 lda, -6 X, -7 ldx, -8 gX, -9 ldgx,
  *         -10 gB, -11 ldgb, -12 gA, -13 ldga, -14 mode, -15 work NULL,
  *         -16 work too small.
@@ -212,7 +239,7 @@ typedef enum { MG_GRAD_SYM = 0, MG_GRAD_LOWER = 1 } mg_grad_mode;
 mg_status mg_posv_backward(mg_handle_t handle, int64_t n, int64_t nrhs, const double *L, int64_t lda,
                            const double *X, int64_t ldx, const double *gX, int64_t ldgx, double *gB, int64_t ldgb,
                            double *gA, int64_t ldga, mg_grad_mode mode, void *work, size_t work_bytes,
-                           const int32_t *info);
+                           int32_t *info);
 
 /*
  * Batched posv: many independent SPD systems of uneven order (0..512) solved
@@ -315,7 +342,8 @@ mg_status mg_gp_loglik(mg_handle_t handle, int64_t n, int64_t nrhs, double *A, i
  *   gA      n x n output (ldga >= n); gY n x nrhs output (ldgy >= n);
  *   gM      n x nrhs output (ldgm >= n) or NULL.
  *   work    device workspace of mg_gp_loglik_grad_buffer_size bytes.
- *   info    device int32 from mg_gp_loglik; nonzero makes every output NaN.
+ *   info    device int32 from mg_gp_loglik, in/out; nonzero makes every
+ *           output NaN (a sweep that gives up sets MG_INFO_SOLVE_ABORTED).
  * Errors: -1 handle, -2 n < 0, -3 nrhs < 0, -4 L NULL, -5 lda, -6 Alpha NULL,
  * -7 ldalpha, -8 g NULL, -9 gA NULL, -10 ldga, -11 gY NULL, -12 ldgy,
  * -14 ldgm (gM given), -15 work NULL, -16 work_bytes too small, -17 info NULL;
@@ -325,7 +353,7 @@ mg_status mg_gp_loglik_grad_buffer_size(mg_handle_t handle, int64_t n, size_t *b
 mg_status mg_gp_loglik_grad(mg_handle_t handle, int64_t n, int64_t nrhs, const double *L, int64_t lda,
                             const double *Alpha, int64_t ldalpha, const double *g, double *gA, int64_t ldga,
                             double *gY, int64_t ldgy, double *gM, int64_t ldgm, void *work, size_t work_bytes,
-                            const int32_t *info);
+                            int32_t *info);
 
 /*
  * Profiling.  When enabled, every launch of the kernel kinds below is

@@ -66,6 +66,11 @@ class Handle:
     def set_block_size(self, nb: int):
         call("mg_set_block_size", self.h, int(nb))
 
+    def set_sweep_spin_limit(self, limit: int = -1):
+        """Polls before a triangular-sweep wait gives up (-1: built-in limit;
+        0: give up at once, which drives the failure path for tests)."""
+        call("mg_set_sweep_spin_limit", self.h, int(limit))
+
     def block_size(self, n: int, dtype_code: int = _lib.MG_F64) -> int:
         out = ctypes.c_int64()
         call("mg_get_block_size", self.h, dtype_code, int(n), ctypes.byref(out))
@@ -147,7 +152,9 @@ def _work(h, dt, n, nrhs, device):
 
 
 def potrs(L, B, info=None):
-    """X = (L L^T)^{-1} B from a factor returned by potrf."""
+    """X = (L L^T)^{-1} B from a factor returned by potrf.  ``info`` (the
+    factor's 0-dim int32 device tensor, optional) is read and, if a sweep
+    gives up, set to MG_INFO_SOLVE_ABORTED (X is then NaN)."""
     torch = _torch()
     _check_cuda(L, B)
     flat = B.dim() == 1
@@ -166,7 +173,8 @@ def potrs(L, B, info=None):
 
 def posv(A, B, nb: int | None = None):
     """Solve A X = B (A SPD, lower triangle read).  Returns (X, info); on
-    info != 0, X holds B unchanged."""
+    info > 0 (A not positive definite) X holds B unchanged; on
+    info == MG_INFO_SOLVE_ABORTED X is NaN."""
     torch = _torch()
     _check_cuda(A, B)
     flat = B.dim() == 1
@@ -318,12 +326,15 @@ def _make_posv_function():
         ``PosvFunction.apply(A, B, mode)``: mode "sym" (default) returns the
         symmetric gradient -1/2 (gB X^T + X gB^T) for A; "lower" returns the
         exact derivative of the solver as a function of all entries of A
-        (only the lower triangle is read, so the strict upper part is 0)."""
+        (only the lower triangle is read, so the strict upper part is 0).
+        When A is not positive definite (or a sweep gave up) X is all NaN,
+        and so are the gradients; nothing synchronises to find out."""
 
         @staticmethod
         def forward(ctx, A, B, mode="sym"):
             L, info = potrf(A)
             X = potrs(L, B, info)
+            X.masked_fill_(info != 0, float("nan"))   # device-side: a failed factor leaves B in X
             ctx.save_for_backward(L, X, info)
             ctx.mode = mode
             return X

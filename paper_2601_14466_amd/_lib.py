@@ -16,6 +16,8 @@ MG_OK = 0
 MG_ERR_HIP = 1
 MG_ERR_UNSUPPORTED = 2
 MG_ERR_INTERNAL = 3
+MG_ERR_ABORTED = 4
+MG_INFO_SOLVE_ABORTED = -1
 MG_F64 = 0
 MG_F32 = 1
 MG_PREC_F32 = 1
@@ -44,6 +46,7 @@ SIGNATURES = {
     "mg_set_stream": (i32, [vp, vp]),
     "mg_set_block_size": (i32, [vp, i64]),
     "mg_set_lookahead": (i32, [vp, i32]),
+    "mg_set_sweep_spin_limit": (i32, [vp, i64]),
     "mg_get_block_size": (i32, [vp, i32, i64, ctypes.POINTER(i64)]),
     "mg_potrf": (i32, [vp, i32, i64, vp, i64, vp]),
     "mg_potrs_buffer_size": (i32, [vp, i32, i64, i64, ctypes.POINTER(sz)]),
@@ -90,7 +93,9 @@ class MgError(RuntimeError):
     def __init__(self, fn: str, code: int):
         kind = ("invalid argument %d" % -code) if code < 0 else {
             MG_ERR_HIP: "HIP runtime error", MG_ERR_UNSUPPORTED: "unsupported",
-            MG_ERR_INTERNAL: "internal error"}.get(code, "error %d" % code)
+            MG_ERR_INTERNAL: "internal error",
+            MG_ERR_ABORTED: "a triangular sweep gave up waiting (bounded wait); the result is NaN"}.get(
+                code, "error %d" % code)
         super().__init__(f"{fn}: {kind} (status {code})")
         self.code = code
 

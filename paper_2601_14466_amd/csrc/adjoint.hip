@@ -26,13 +26,14 @@ namespace mg {
 // alpha_diag on it.  Only entries with i >= j are computed into memory; with
 // mirror set each strictly-lower value is also written to (j, i), so the
 // symmetric result is exactly symmetric (the two halves of a diagonal tile
-// would otherwise be summed in different orders).
+// would otherwise be summed in different orders).  After a failed
+// factorisation or an aborted solve (info != 0) the same entries receive NaN.
 __global__ __launch_bounds__(256, 2) void k_syr2k_grad(const double* __restrict__ G, int64_t ldg,
                                                        const double* __restrict__ X, int64_t ldx, int64_t n,
                                                        int64_t nrhs, double* __restrict__ GA, int64_t ldga,
                                                        double alpha_off, double alpha_diag, int mirror,
                                                        const int32_t* info) {
-    if (info && *info != 0) return;
+    const bool bad = info && *info != 0;
     const int64_t T = (n + 127) / 128;
     const int64_t t = blockIdx.x;
     if (t >= T * (T + 1) / 2) return;
@@ -49,7 +50,7 @@ __global__ __launch_bounds__(256, 2) void k_syr2k_grad(const double* __restrict_
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = f64x4{0, 0, 0, 0};
-    const int64_t K = 2 * nrhs;
+    const int64_t K = bad ? 0 : 2 * nrhs;
     // U(i,k) = G(i,k) for k < nrhs, X(i,k-nrhs) after; V(j,k) = X(j,k), then G(j,k-nrhs)
     for (int64_t k0 = 0; k0 < K; k0 += 4) {
         const int64_t k = k0 + g;
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(256, 2) void k_syr2k_grad(const double* __restrict_
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = sr0 + 16 * bi + i, col = sc0 + 16 * bj + tcol<double>(g, r);
                 if (row < n && col < n && row >= col) {
-                    const double v = (row == col ? alpha_diag : alpha_off) * acc[bi][bj][r];
+                    const double v = bad ? (double)NAN : (row == col ? alpha_diag : alpha_off) * acc[bi][bj][r];
                     GA[idx(row, col, ldga)] = v;
                     if (mirror && row > col) GA[idx(col, row, ldga)] = v;
                 }
@@ -92,9 +93,18 @@ __global__ __launch_bounds__(256) void k_copy_rhs(const double* __restrict__ S, 
     }
 }
 
+// gB := NaN when the factorisation failed or a sweep gave up (info != 0).
+__global__ __launch_bounds__(256) void k_nan_on_info(double* __restrict__ D, int64_t ldd, int64_t n, int64_t nrhs,
+                                                     const int32_t* info) {
+    if (!info || *info == 0) return;
+    const int64_t tot = n * nrhs;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256)
+        D[idx(e % n, e / n, ldd)] = (double)NAN;
+}
+
 mg_status posv_backward_impl(mg_handle_t h, int64_t n, int64_t nrhs, const double* L, int64_t lda,
                              const double* X, int64_t ldx, const double* GX, int64_t ldgx, double* GB,
-                             int64_t ldgb, double* GA, int64_t ldga, int mode, void* work, const int32_t* info) {
+                             int64_t ldgb, double* GA, int64_t ldga, int mode, void* work, int32_t* info) {
     if (n == 0) return MG_OK;
     hipStream_t st = h->stream;
     mg_status rc;
@@ -103,13 +113,15 @@ mg_status posv_backward_impl(mg_handle_t h, int64_t n, int64_t nrhs, const doubl
         hipLaunchKernelGGL(k_copy_rhs, dim3(g1), dim3(256), 0, st, GX, ldgx, GB, ldgb, n, nrhs);
         MG_LAUNCH_CHECK();
         if ((rc = potrs_impl<double>(h, n, nrhs, L, lda, GB, ldgb, (double*)work, info))) return rc;
+        hipLaunchKernelGGL(k_nan_on_info, dim3(g1), dim3(256), 0, st, GB, ldgb, n, nrhs, (const int32_t*)info);
+        MG_LAUNCH_CHECK();
     }
     const int64_t T = cdiv(n, 128);
     const bool lower = mode == MG_GRAD_LOWER;
     const int64_t grid = T * (T + 1) / 2;
     if ((rc = prof_begin(h, MG_PROF_ADJOINT, st))) return rc;
     hipLaunchKernelGGL(k_syr2k_grad, dim3((unsigned)grid), dim3(256), 0, st, GB, ldgb, X, ldx, n, nrhs, GA, ldga,
-                       lower ? -1.0 : -0.5, -0.5, lower ? 0 : 1, info);
+                       lower ? -1.0 : -0.5, -0.5, lower ? 0 : 1, (const int32_t*)info);
     MG_LAUNCH_CHECK();
     const double nd = (double)n;
     return prof_end(h, MG_PROF_ADJOINT, 2.0 * nd * nd * 2.0 * (double)nrhs,

@@ -104,6 +104,13 @@ mg_status mg_set_block_size(mg_handle_t h, int64_t nb) {
     return MG_OK;
 }
 
+mg_status mg_set_sweep_spin_limit(mg_handle_t h, int64_t limit) {
+    if (!h) return -1;
+    if (limit < -1 || limit > ((int64_t)1 << 30)) return -2;
+    h->spin_limit = (int)limit;
+    return MG_OK;
+}
+
 mg_status mg_set_lookahead(mg_handle_t h, int32_t enable) {
     if (!h) return -1;
     if (enable < 0 || enable > 2) return -2;
@@ -158,7 +165,7 @@ static mg_status check_solve_args(mg_handle_t h, mg_dtype dt, int64_t n, int64_t
 }
 
 mg_status mg_potrs(mg_handle_t h, mg_dtype dt, int64_t n, int64_t nrhs, const void* L, int64_t lda, void* B,
-                   int64_t ldb, void* work, size_t work_bytes, const int32_t* info) {
+                   int64_t ldb, void* work, size_t work_bytes, int32_t* info) {
     mg_status rc = check_solve_args(h, dt, n, nrhs, L, lda, B, ldb, work, work_bytes);
     if (rc) return rc;
     return dt == MG_F64
@@ -219,7 +226,7 @@ mg_status mg_posv_mixed(mg_handle_t h, mg_prec lo, int64_t n, int64_t nrhs, cons
 
 mg_status mg_posv_backward(mg_handle_t h, int64_t n, int64_t nrhs, const double* L, int64_t lda, const double* X,
                            int64_t ldx, const double* gX, int64_t ldgx, double* gB, int64_t ldgb, double* gA,
-                           int64_t ldga, mg_grad_mode mode, void* work, size_t work_bytes, const int32_t* info) {
+                           int64_t ldga, mg_grad_mode mode, void* work, size_t work_bytes, int32_t* info) {
     if (!h) return -1;
     if (n < 0) return -2;
     if (nrhs < 0) return -3;

@@ -190,7 +190,7 @@ mg_status mg_gp_loglik_grad_buffer_size(mg_handle_t h, int64_t n, size_t* bytes)
 
 mg_status mg_gp_loglik_grad(mg_handle_t h, int64_t n, int64_t nrhs, const double* L, int64_t lda, const double* Alpha,
                             int64_t ldalpha, const double* g, double* gA, int64_t ldga, double* gY, int64_t ldgy,
-                            double* gM, int64_t ldgm, void* work, size_t work_bytes, const int32_t* info) {
+                            double* gM, int64_t ldgm, void* work, size_t work_bytes, int32_t* info) {
     if (!h) return -1;
     if (n < 0) return -2;
     if (nrhs < 0) return -3;

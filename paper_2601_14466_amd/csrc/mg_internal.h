@@ -23,6 +23,7 @@ struct mg_handle_s {
     int lookahead = 1;       // 0 serial; 1 look-ahead; 2 look-ahead with one CU per XCD kept for the panel
     int side_mode = 0;       // look-ahead mode the bulk stream was created for
     int trail_lo = 1;        // FP32 trailing update: 1 plain, 2 operands rounded to bfloat16
+    int spin_limit = -1;     // potrs sweeps: polls before a wait gives up (-1: the built-in limit)
     void* bf16_panel = nullptr;  // bfloat16 mode: three n x 512 row-major panel buffers
     uint32_t profiling = 0;  // bit k set: launches of kind k are bracketed by events
     mg_prof_counter prof[MG_PROF_KINDS];
@@ -57,13 +58,13 @@ template <typename T>
 mg_status potrf_impl(mg_handle_t h, int64_t n, T* A, int64_t lda, int32_t* info);
 template <typename T>
 mg_status potrs_impl(mg_handle_t h, int64_t n, int64_t nrhs, const T* L, int64_t lda, T* B,
-                     int64_t ldb, T* ywork, const int32_t* info);
+                     int64_t ldb, T* ywork, int32_t* info);
 size_t potrs_work_bytes(int64_t n, int64_t nrhs, int es);
 size_t mixed_work_bytes(int64_t n, int64_t nrhs, int fallback, int lo);
 inline size_t bf16_panel_bytes(int64_t n) { return 3 * (size_t)n * 512 * 2; }
 mg_status posv_backward_impl(mg_handle_t h, int64_t n, int64_t nrhs, const double* L, int64_t lda,
                              const double* X, int64_t ldx, const double* GX, int64_t ldgx, double* GB,
-                             int64_t ldgb, double* GA, int64_t ldga, int mode, void* work, const int32_t* info);
+                             int64_t ldgb, double* GA, int64_t ldga, int mode, void* work, int32_t* info);
 mg_status posv_mixed_impl(mg_handle_t h, int lo, int64_t n, int64_t nrhs, const double* A, int64_t lda,
                           const double* B, int64_t ldb, double* X, int64_t ldx, const mg_ir_opts* o, void* work,
                           mg_ir_result* res, int32_t* info);

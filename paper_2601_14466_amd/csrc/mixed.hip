@@ -26,20 +26,27 @@
 namespace mg {
 
 // ---------------------------------------------------------------- casts
-// W = fl32(A) on the lower triangle (column j, rows j..n-1).
+// W = fl32(A) on the lower triangle (column j, rows j..n-1); columns are
+// strided over grid y, which the host caps below the grid-y limit.
 __global__ __launch_bounds__(256) void k_cast_lower_f64_f32(const double* __restrict__ A, int64_t lda,
                                                             float* __restrict__ W, int64_t ldw, int64_t n) {
-    const int64_t j = blockIdx.y;
-    for (int64_t i = j + (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        W[idx(i, j, ldw)] = (float)A[idx(i, j, lda)];
+    for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
+        for (int64_t i = j + (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+            W[idx(i, j, ldw)] = (float)A[idx(i, j, lda)];
 }
 
-// copy the lower triangle of A (FP64) into W (FP64)
+// copy the lower triangle of A (FP64) into W (FP64), columns as above
 __global__ __launch_bounds__(256) void k_copy_lower_f64(const double* __restrict__ A, int64_t lda,
                                                         double* __restrict__ W, int64_t ldw, int64_t n) {
-    const int64_t j = blockIdx.y;
-    for (int64_t i = j + (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        W[idx(i, j, ldw)] = A[idx(i, j, lda)];
+    for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
+        for (int64_t i = j + (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+            W[idx(i, j, ldw)] = A[idx(i, j, lda)];
+}
+
+// grid for the two lower-triangle kernels: x covers a column, y strides the columns
+static inline dim3 lower_grid(int64_t n) {
+    return dim3((unsigned)std::min<int64_t>(std::max<int64_t>(1, cdiv(n, 256)), 64),
+                (unsigned)std::min<int64_t>(std::max<int64_t>(1, n), 32768));
 }
 
 // D (n x nrhs, ld n, FP32) = fl32(S) ; S FP64 with leading dimension lds
@@ -71,6 +78,13 @@ __global__ __launch_bounds__(256) void k_copy_block(const double* __restrict__ S
         const int64_t i = e % n, r = e / n;
         D[idx(i, r, ldd)] = S[idx(i, r, lds)];
     }
+}
+
+// X (n x nrhs, ldx) := quiet NaN: the result of a solve that produced none
+__global__ __launch_bounds__(256) void k_fill_nan(double* __restrict__ X, int64_t ldx, int64_t n, int64_t nrhs) {
+    const int64_t tot = n * nrhs;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256)
+        X[idx(e % n, e / n, ldx)] = (double)NAN;
 }
 
 __global__ void k_fill_u64(unsigned long long* p, int64_t cnt, unsigned long long v) {
@@ -256,7 +270,9 @@ static MixedWork mixed_layout(int64_t n, int64_t nrhs, int fallback, int lo) {
     w.o_y = take(potrs_work_bytes(n, nrhs, 8));  // potrs workspace (FP32 or FP64 fallback)
     w.o_cm = take((size_t)(3 * nrhs + 1) * 8);
     w.o_an = take(8);
-    w.o_eta = take((size_t)std::max<int64_t>(nrhs, 1) * 8);
+    // per-column eta, then one slot whose first word is the working-precision
+    // solves' info (MG_INFO_SOLVE_ABORTED after a sweep gave up); read back together
+    w.o_eta = take((size_t)(std::max<int64_t>(nrhs, 1) + 1) * 8);
     w.o_info = take(8);
     w.o_rp = take(residual_part_bytes(n, nrhs));  // residual partial sums
     // bfloat16 mode: two row-major bfloat16 copies of a block column panel
@@ -326,29 +342,31 @@ mg_status posv_mixed_impl(mg_handle_t h, int lo, int64_t n, int64_t nrhs, const 
     unsigned long long* an = (unsigned long long*)(base + L.o_an);
     double* eta_d = (double*)(base + L.o_eta);
     int32_t* info_lo = (int32_t*)(base + L.o_info);
+    int32_t* info_sw = (int32_t*)(eta_d + nrhs);  // working-precision solves
     double* Pp = (double*)(base + L.o_rp);
 
     const int saved_trail = h->trail_lo;
     h->trail_lo = (lo == MG_PREC_BF16) ? 2 : 1;
     h->bf16_panel = (lo == MG_PREC_BF16) ? (void*)(base + L.o_p16) : nullptr;
     // 1. working copy and low-precision factor
-    hipLaunchKernelGGL(k_cast_lower_f64_f32, dim3(grid1(n), (unsigned)n), dim3(256), 0, st, A, lda, Aw, n, n);
+    hipLaunchKernelGGL(k_cast_lower_f64_f32, lower_grid(n), dim3(256), 0, st, A, lda, Aw, n, n);
     MG_LAUNCH_CHECK();
     rc = potrf_impl<float>(h, n, Aw, n, info_lo);
     h->trail_lo = saved_trail;
     h->bf16_panel = nullptr;
     if (rc) return rc;
+    if ((rc = set_info_zero(st, info_sw))) return rc;
     int32_t hinfo = 0;
     MG_HIP(hipMemcpyAsync(&hinfo, info_lo, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     MG_HIP(hipStreamSynchronize(st));
     res->lo_info = hinfo;
     bool converged = false;
-    std::vector<double> eta((size_t)nrhs);
+    std::vector<double> eta((size_t)nrhs + 1);
     if (hinfo == 0) {
         // 2. first solve in working precision
         hipLaunchKernelGGL(k_to_f32, dim3(grid1(n * nrhs)), dim3(256), 0, st, B, ldb, D, n, nrhs);
         MG_LAUNCH_CHECK();
-        if ((rc = potrs_impl<float>(h, n, nrhs, Aw, n, D, n, (float*)Yw, nullptr))) return rc;
+        if ((rc = potrs_impl<float>(h, n, nrhs, Aw, n, D, n, (float*)Yw, info_sw))) return rc;
         hipLaunchKernelGGL(k_widen, dim3(grid1(n * nrhs)), dim3(256), 0, st, D, X, ldx, n, nrhs, 0);
         MG_LAUNCH_CHECK();
         // |A|_inf once
@@ -364,11 +382,23 @@ mg_status posv_mixed_impl(mg_handle_t h, int lo, int64_t n, int64_t nrhs, const 
             if ((rc = sym_residual(st, A, lda, n, nrhs, X, ldx, B, ldb, R, cm, 0, Pp))) return rc;
             hipLaunchKernelGGL(k_eta, dim3(1), dim3(256), 0, st, cm, an, nrhs, eta_d);
             MG_LAUNCH_CHECK();
-            MG_HIP(hipMemcpyAsync(eta.data(), eta_d, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+            MG_HIP(hipMemcpyAsync(eta.data(), eta_d, sizeof(double) * (nrhs + 1), hipMemcpyDeviceToHost, st));
             MG_HIP(hipStreamSynchronize(st));
+            int32_t sw = 0;
+            std::memcpy(&sw, &eta[(size_t)nrhs], sizeof(sw));
+            if (sw != 0) {
+                // a working-precision sweep gave up waiting: X is not a solution
+                hipLaunchKernelGGL(k_fill_nan, dim3(grid1(n * nrhs)), dim3(256), 0, st, X, ldx, n, nrhs);
+                MG_LAUNCH_CHECK();
+                MG_HIP(hipStreamSynchronize(st));
+                res->eta = (double)NAN;
+                res->iters = it;
+                return MG_ERR_ABORTED;
+            }
             double e = 0.0;
             bool bad = false;
-            for (double v : eta) {
+            for (int64_t r = 0; r < nrhs; ++r) {
+                const double v = eta[(size_t)r];
                 if (v != v) bad = true;
                 e = std::max(e, v);
             }
@@ -386,7 +416,7 @@ mg_status posv_mixed_impl(mg_handle_t h, int lo, int64_t n, int64_t nrhs, const 
             // 4. correction in working precision, update in FP64
             hipLaunchKernelGGL(k_to_f32, dim3(grid1(n * nrhs)), dim3(256), 0, st, R, n, D, n, nrhs);
             MG_LAUNCH_CHECK();
-            if ((rc = potrs_impl<float>(h, n, nrhs, Aw, n, D, n, (float*)Yw, nullptr))) return rc;
+            if ((rc = potrs_impl<float>(h, n, nrhs, Aw, n, D, n, (float*)Yw, info_sw))) return rc;
             hipLaunchKernelGGL(k_widen, dim3(grid1(n * nrhs)), dim3(256), 0, st, D, X, ldx, n, nrhs, 1);
             MG_LAUNCH_CHECK();
         }
@@ -394,12 +424,20 @@ mg_status posv_mixed_impl(mg_handle_t h, int lo, int64_t n, int64_t nrhs, const 
     if (!converged) {
         if (!o->fallback) {
             res->fell_back = 0;
+            if (hinfo != 0) {
+                // the low-precision factor broke down and no FP64 solve is
+                // allowed: there is no solution to return
+                hipLaunchKernelGGL(k_fill_nan, dim3(grid1(n * nrhs)), dim3(256), 0, st, X, ldx, n, nrhs);
+                MG_LAUNCH_CHECK();
+                MG_HIP(hipStreamSynchronize(st));
+                res->eta = (double)NAN;
+            }
             return MG_OK;
         }
         // 5. FP64 fallback on a copy of A (A itself is const)
         res->fell_back = 1;
         double* Ad = (double*)(base + L.o_aw);
-        hipLaunchKernelGGL(k_copy_lower_f64, dim3(grid1(n), (unsigned)n), dim3(256), 0, st, A, lda, Ad, n, n);
+        hipLaunchKernelGGL(k_copy_lower_f64, lower_grid(n), dim3(256), 0, st, A, lda, Ad, n, n);
         MG_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_copy_block, dim3(grid1(n * nrhs)), dim3(256), 0, st, B, ldb, X, ldx, n, nrhs);
         MG_LAUNCH_CHECK();
@@ -413,11 +451,17 @@ mg_status posv_mixed_impl(mg_handle_t h, int lo, int64_t n, int64_t nrhs, const 
         if ((rc = sym_residual(st, A, lda, n, nrhs, X, ldx, B, ldb, R, an, 1, Pp))) return rc;
         hipLaunchKernelGGL(k_eta, dim3(1), dim3(256), 0, st, cm, an, nrhs, eta_d);
         MG_LAUNCH_CHECK();
+        int32_t finfo = 0;
         MG_HIP(hipMemcpyAsync(eta.data(), eta_d, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+        MG_HIP(hipMemcpyAsync(&finfo, info, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         MG_HIP(hipStreamSynchronize(st));
         double e = 0.0;
-        for (double v : eta) e = (v != v || v > e) ? v : e;
+        for (int64_t r = 0; r < nrhs; ++r) {
+            const double v = eta[(size_t)r];
+            e = (v != v || v > e) ? v : e;
+        }
         res->eta = e;
+        if (finfo == MG_INFO_SOLVE_ABORTED) return MG_ERR_ABORTED;
     }
     return MG_OK;
 }

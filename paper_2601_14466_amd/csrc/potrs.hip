@@ -24,9 +24,11 @@
 //     value and the division by the pivot happens once at the end (integer
 //     data with power-of-two pivots stays exact).
 // Every wait is bounded: a block that stays unwritten past the spin limit
-// sets an error word in the workspace and the kernel drains.  Each sweep
-// reads the lower triangle once (HBM-bound, nrhs/4 flop per byte in FP64);
-// the chain of block solves is the latency floor.
+// sets an error word in the workspace and the kernel drains; after the two
+// sweeps a check kernel turns a set error word into a NaN-filled result and
+// info = MG_INFO_SOLVE_ABORTED.  Each sweep reads the lower triangle once
+// (HBM-bound, nrhs/4 flop per byte in FP64); the chain of block solves is
+// the latency floor.
 #include <algorithm>
 
 #include "mg_internal.h"
@@ -36,7 +38,7 @@ namespace mg {
 
 constexpr int JB = 64;       // rows per block
 constexpr int LDP = JB + 1;  // LDS leading dimension (bank spread)
-constexpr int SWEEP_SPIN_LIMIT = 1 << 22;
+constexpr int SWEEP_SPIN_LIMIT = 1 << 22;  // default polls before a wait gives up
 
 // Per-sweep words, kept in the workspace after Y.
 struct SweepSync {
@@ -121,10 +123,12 @@ __device__ __forceinline__ void store_coherent(T* p, T v) {
 
 // Forward (FWD): Out = L^{-1} In.  Backward: Out = L^{-T} In.  In and Out are
 // n x nrhs column-major; 16 RT right-hand sides per pass.
+// spin_limit: polls before a wait gives up (0: give up at the first
+// dependency without waiting, which exercises the give-up path).
 template <typename T, int RT, bool FWD>
 __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t lda, int64_t n, int64_t nrhs,
                                                const T* __restrict__ In, int64_t ldi, T* Out, int64_t ldo,
-                                               SweepSync* sy, const int32_t* info) {
+                                               SweepSync* sy, const int32_t* info, int spin_limit) {
     constexpr int NR = 16 * RT, XP = NR + 1, QW = NR / 4;
     __shared__ T Ls[JB * LDP];
     __shared__ T piv[JB];
@@ -150,6 +154,10 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t 
     // down to bi + 1 (backward), visited in the order they are handed out
     const int ndep = FWD ? bi : nblk - 1 - bi;
     bool abort = false;
+    if (spin_limit == 0 && ndep > 0) {
+        abort = true;
+        if (tid == 0) atomicExch(&sy->err, 1);
+    }
     constexpr int XPT = JB * NR / 256;  // solution values each thread moves per block
     // this block's right-hand sides (a lane per row, wave w takes q = w + 4 u),
     // requested now so that their latency is off the critical path
@@ -216,7 +224,7 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t 
                 // costs one round trip (the reload below), not two
                 if ((spins & 31) == 31) {
                     const int e = (tid == 0) ? load_coherent(&sy->err) : 0;
-                    if (__syncthreads_or(spins > SWEEP_SPIN_LIMIT || e != 0)) {
+                    if (__syncthreads_or(spins > spin_limit || e != 0)) {
                         abort = true;
                         if (tid == 0) atomicExch(&sy->err, 1);
                         break;
@@ -289,35 +297,57 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t 
     }
 }
 
+// After both sweeps (one workgroup): when a wait of either sweep gave up (an
+// error word is set), Out is filled with quiet NaNs and *info (when given)
+// becomes MG_INFO_SOLVE_ABORTED.  Skipped when info was non-zero on entry
+// (the sweeps did not run and their words are stale); every thread reads
+// info before the barrier that precedes the one write.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sweep_check(T* Out, int64_t ld, int64_t n, int64_t nrhs,
+                                                     const SweepSync* sy, int nwords, int32_t* info) {
+    if (info && *info != 0) return;
+    bool bad = false;
+    for (int k = 0; k < nwords; ++k) bad = bad || load_coherent(&sy[k].err) != 0;
+    if (!bad) return;
+    __syncthreads();
+    if (info && threadIdx.x == 0) *info = MG_INFO_SOLVE_ABORTED;
+    const int64_t tot = n * nrhs;
+    for (int64_t e = threadIdx.x; e < tot; e += 256) Out[idx(e % n, e / n, ld)] = (T)NAN;
+}
+
 template <typename T>
 static mg_status sweep(hipStream_t st, int64_t n, int64_t nrhs, const T* L, int64_t lda, T* B, int64_t ldb, T* Y,
-                       SweepSync* sy, const int32_t* info) {
+                       SweepSync* sy, int32_t* info, int spin_limit) {
     const int64_t np = sweep_passes(nrhs);
     const dim3 grid((unsigned)cdiv(n, JB), (unsigned)np);
     const unsigned gfill = (unsigned)std::min<int64_t>(std::max<int64_t>(1, cdiv(n * nrhs, 256)), 2048);
     hipLaunchKernelGGL((k_sweep_init<T>), dim3(gfill), dim3(256), 0, st, Y, n, n, nrhs, sy, info);
     MG_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_sweep<T, 1, true>), grid, dim3(256), 0, st, L, lda, n, nrhs, (const T*)B, ldb, Y, n, sy,
-                       info);
+                       info, spin_limit);
     MG_LAUNCH_CHECK();
     // B has been read; it now receives X
     hipLaunchKernelGGL((k_sweep_init<T>), dim3(gfill), dim3(256), 0, st, B, ldb, n, nrhs, sy + np, info);
     MG_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_sweep<T, 1, false>), grid, dim3(256), 0, st, L, lda, n, nrhs, (const T*)Y, n, B, ldb,
-                       sy + np, info);
+                       sy + np, info, spin_limit);
+    MG_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_sweep_check<T>), dim3(1), dim3(256), 0, st, B, ldb, n, nrhs, (const SweepSync*)sy,
+                       (int)(2 * np), info);
     MG_LAUNCH_CHECK();
     return MG_OK;
 }
 
 template <typename T>
 mg_status potrs_impl(mg_handle_t h, int64_t n, int64_t nrhs, const T* L, int64_t lda, T* B, int64_t ldb, T* Y,
-                     const int32_t* info) {
+                     int32_t* info) {
     if (n == 0 || nrhs == 0) return MG_OK;
     hipStream_t st = h->stream;
     mg_status rc;
     if ((rc = prof_begin(h, MG_PROF_SOLVE, st))) return rc;
     SweepSync* sy = (SweepSync*)((char*)Y + y_bytes(n, nrhs, (int)sizeof(T)));
-    rc = sweep<T>(st, n, nrhs, L, lda, B, ldb, Y, sy, info);
+    const int lim = h->spin_limit < 0 ? SWEEP_SPIN_LIMIT : h->spin_limit;
+    rc = sweep<T>(st, n, nrhs, L, lda, B, ldb, Y, sy, info, lim);
     if (rc) return rc;
     const double nd = (double)n;
     return prof_end(h, MG_PROF_SOLVE, 2.0 * nd * nd * (double)nrhs,
@@ -325,8 +355,8 @@ mg_status potrs_impl(mg_handle_t h, int64_t n, int64_t nrhs, const T* L, int64_t
 }
 
 template mg_status potrs_impl<double>(mg_handle_t, int64_t, int64_t, const double*, int64_t, double*, int64_t,
-                                      double*, const int32_t*);
+                                      double*, int32_t*);
 template mg_status potrs_impl<float>(mg_handle_t, int64_t, int64_t, const float*, int64_t, float*, int64_t,
-                                     float*, const int32_t*);
+                                     float*, int32_t*);
 
 }  // namespace mg

@@ -13,7 +13,10 @@ below follow the solver's published test configurations:
                    from a seeded power-iteration estimate of lambda_max.
 * ``haar_spd``   : A = Q diag(lam) Q^T, Q Haar-distributed (Householder QR of
                    a Gaussian matrix with the sign of R's diagonal fixed),
-                   lam log-spaced on [1/cond, 1] so cond(A) is exact.
+                   lam log-spaced on [1/cond, 1] so cond(A) is exact.  On the
+                   device, for n^2 >= 2^31 the same construction runs panel by
+                   panel so that no library call sees 2^31 or more elements
+                   (library kernels index with 32-bit integers).
 * ``batch_sizes``: n_i uniform on [16, 512].
 * closed-form families used as pins: ``lehmer``, ``laplacian_1d``,
   ``diag_1_to_n`` (the paper's own benchmark matrix), ``integer_exact``.
@@ -212,9 +215,83 @@ def torch_gram_spd_cond(n: int, seed: int, target_cond: float = 1e4, device="cud
     return A
 
 
+# Largest number of elements any single vendor-library call (QR, GEMM) made
+# by these generators may see: library kernels index with 32-bit integers.
+VENDOR_CALL_MAX = 2 ** 31 - 1
+
+
+def _rows_per_call(n: int) -> int:
+    """Rows of an n-wide row-major block such that the block stays below
+    VENDOR_CALL_MAX elements (a multiple of 1024 when n is large)."""
+    r = VENDOR_CALL_MAX // max(1, n)
+    return max(1, r // 1024 * 1024 if r >= 1024 else r)
+
+
+def torch_matmul_rows(A, X):
+    """A @ X with A split into row blocks of fewer than 2^31 elements each."""
+    import torch
+
+    n = A.shape[0]
+    step = _rows_per_call(A.shape[1])
+    if n * A.shape[1] <= VENDOR_CALL_MAX:
+        return A @ X
+    out = torch.empty((n, X.shape[1]), dtype=A.dtype, device=A.device)
+    for r0 in range(0, n, step):
+        out[r0:r0 + step] = A[r0:r0 + step] @ X
+    return out
+
+
+def _torch_haar_q_panels(n: int, gen, device, b: int = 4096):
+    """Haar Q for n^2 >= 2^31, built so that no library call sees 2^31 or
+    more elements.  Q is the orthogonal factor, with positive R diagonal,
+    of the QR factorisation of a seeded Gaussian matrix Z (Mezzadri 2007),
+    formed panel by panel: panel k of Z (b columns, drawn from the seeded
+    generator in panel order) is made orthogonal to the finished columns by
+    block Gram-Schmidt applied twice (Giraud et al. 2005: twice is enough),
+    then factored by a Householder QR of the n x b panel; R's diagonal signs
+    fix the column signs.  Columns of Q are kept as rows of Qt (row-major)
+    so every operand is a contiguous block of rows.  Returns Q row-major."""
+    import torch
+
+    Qt = torch.empty((n, n), dtype=torch.float64, device=device)
+    chunk = _rows_per_call(n)
+    for k0 in range(0, n, b):
+        k1 = min(n, k0 + b)
+        W = torch.randn((k1 - k0, n), generator=gen, device=device, dtype=torch.float64)  # columns of Z as rows
+        for _ in range(2):
+            for c0 in range(0, k0, chunk):
+                c1 = min(k0, c0 + chunk)
+                C = Qt[c0:c1] @ W.T                  # (c1-c0) x b: projections on finished columns
+                W -= C.T @ Qt[c0:c1]
+        Qk, Rk = torch.linalg.qr(W.T)               # n x b panel
+        s = torch.sign(torch.diagonal(Rk))
+        s[s == 0] = 1.0
+        Qt[k0:k1] = (Qk * s).T
+        del W, Qk, Rk
+    Q = Qt.T.contiguous()
+    del Qt
+    return Q
+
+
 def torch_haar_spd(n: int, cond: float, seed: int, device="cuda"):
     import torch
 
+    if n * n > VENDOR_CALL_MAX:
+        gen = torch.Generator(device=device)
+        gen.manual_seed(seed)
+        Q = _torch_haar_q_panels(n, gen, device)
+        lam = torch.as_tensor(logspaced_spectrum(n, cond), device=device)
+        A = torch.empty((n, n), dtype=torch.float64, device=device)
+        step = min(_rows_per_call(n), 8192)
+        for i0 in range(0, n, step):                 # lower block triangle, row blocks of Q
+            i1 = min(n, i0 + step)
+            Qi = Q[i0:i1] * lam
+            for j0 in range(0, i1, step):
+                j1 = min(n, j0 + step)
+                A[i0:i1, j0:j1] = Qi @ Q[j0:j1].T
+            del Qi
+        del Q
+        return torch_symmetrize_lower_(A)
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
     Z = torch.randn((n, n), generator=gen, device=device, dtype=torch.float64)
