@@ -31,6 +31,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "potrf+potrs TFLOP/s: FP64 vs mixed-precision+IR at 1e-12 backward error, 1 GPU"
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 matrix peak (public specification)
+FP32_PEAK_TFLOPS = 157.3     # dense FP32 matrix peak
+BF16_PEAK_TFLOPS = 2500.0    # dense bfloat16 matrix peak
 HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of the rank-512 trailing-update kernel, k_syrk_lower<double, true, 4, false>,
@@ -55,6 +57,23 @@ def syrk_traffic_bytes():
         return None
     t = SYRK_TRAFFIC
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
+
+
+def roofline_obj(kernel: str, flops: float, nbytes: float, ms: float, launches: int, peak_tflops: float,
+                 traffic=None) -> dict:
+    """Roofline entry for one kernel: algorithmic flops and bytes per launch
+    over the average launch time; the bound is whichever of the matrix peak
+    and HBM bandwidth needs more time for that work."""
+    t = ms / launches / 1e3
+    f, b = flops / launches, nbytes / launches
+    hbm = b / (HBM_PEAK_GBS * 1e9) > f / (peak_tflops * 1e12)
+    if hbm:
+        ach, peak, unit = b / t / 1e9, HBM_PEAK_GBS, "GB/s"
+    else:
+        ach, peak, unit = f / t / 1e12, peak_tflops, "TFLOP/s"
+    return dict(bound="hbm" if hbm else "mfma", achieved=round(ach, 3), peak=peak, unit=unit,
+                frac=round(ach / peak, 4), traffic=traffic, kernel=kernel, launches=launches,
+                flops_per_launch=f, algorithmic_bytes_per_launch=b, avg_launch_ms=ms / launches)
 
 
 def nominal_flops(n: int, nrhs: int) -> float:
@@ -140,11 +159,33 @@ def bench_fp64(torch, mg, synth, n: int, nrhs: int, steps: int, warmup: int, nb:
              ("diag", _lib.MG_PROF_DIAG), ("trsm", _lib.MG_PROF_TRSM), ("solve", _lib.MG_PROF_SOLVE))}
     h.set_profiling(False)
     info_max = max(info_max, int(infos.max()))
+    # potrs alone on the factor that step left in As[0] (both sweeps, median of 5)
+    Bw = B0c.clone()
+    st_ms = []
+    for r in range(6):
+        Bw.copy_(B0c)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _lib.call("mg_potrs", h.sync_stream(), _lib.MG_F64, n, nrhs, ctypes.c_void_p(As[0].data_ptr()), n,
+                  ctypes.c_void_p(Bw.data_ptr()), n, ctypes.c_void_p(work.data_ptr()), wbytes.value,
+                  ctypes.c_void_p(infos[0:1].data_ptr()))
+        e1.record()
+        torch.cuda.synchronize()
+        if r:
+            st_ms.append(e0.elapsed_time(e1))
+    solve_ms = _median(st_ms)
+    # both sweeps read the lower triangle of L once; B, Y and X move 4 n nrhs elements
+    solve_bytes = (n * (n + 1) + 4.0 * n * nrhs) * 8
+    solve = dict(n=n, nrhs=nrhs, ms=round(solve_ms, 4),
+                 roofline=roofline_obj("k_sweep<double, 1, fwd/bwd, inverse> (two launches)",
+                                       2.0 * n * n * nrhs, solve_bytes, solve_ms, 1, FP64_PEAK_TFLOPS))
+    del Bw
     ms_step = ms / steps
     tflops = nominal_flops(n, nrhs) / (ms_step / 1e3) / 1e12
     achieved = (tr["flops"] / tr["launches"]) / (tr["ms"] / tr["launches"] / 1e3) / 1e12 if tr["launches"] else None
     out = dict(ms_step=ms_step, tflops=tflops, wall_s=wall, info=info_max, eta_fp64_device=eta, nb=nb,
-               restore_in_timed=restore_in_timed, copies=ncopy, prof=prof, trailing=tr, trailing_tflops=achieved)
+               restore_in_timed=restore_in_timed, copies=ncopy, prof=prof, trailing=tr, trailing_tflops=achieved,
+               solve=solve)
     del As, Bs, A0, B0, B0c, Xt, R
     torch.cuda.empty_cache()
     return out
@@ -186,6 +227,10 @@ def bench_mixed(torch, mg, synth, n: int, nrhs: int, cond: float, precision: str
 
     run()
     torch.cuda.synchronize()
+    # the rank-512 trailing update (binary32 or bfloat16 kernel) is bracketed
+    # by events inside the timed region, as on the FP64 leg
+    h.set_profiling(True, kinds=[_lib.MG_PROF_TRAILING])
+    h.profile(_lib.MG_PROF_TRAILING, reset=True)
     times = []
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -194,7 +239,18 @@ def bench_mixed(torch, mg, synth, n: int, nrhs: int, cond: float, precision: str
         e1.record()
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))
+    tr = h.profile(_lib.MG_PROF_TRAILING, reset=True)
+    h.set_profiling(False)
     ms = _median(times)
+    roof = None
+    if tr["launches"]:
+        if precision == "fp32":
+            roof = roofline_obj("k_syrk_lower<float, true, 8, false>", tr["flops"], tr["bytes"], tr["ms"],
+                                tr["launches"], FP32_PEAK_TFLOPS)
+        else:
+            # binary32 C read and written once, the packed bfloat16 panel read once
+            roof = roofline_obj("k_syrk_lower_bf16", tr["flops"], tr["bytes"], tr["ms"], tr["launches"],
+                                BF16_PEAK_TFLOPS)
     X = Xc.T
     B = Bc.T
     R = B - A @ X
@@ -203,7 +259,7 @@ def bench_mixed(torch, mg, synth, n: int, nrhs: int, cond: float, precision: str
     out = dict(precision=precision, n=n, nrhs=nrhs, cond=cond, ms=round(ms, 3),
                tflops=round(nominal_flops(n, nrhs) / (ms / 1e3) / 1e12, 3), iters=res.iters,
                fell_back=bool(res.fell_back), lo_info=res.lo_info, eta_reported=res.eta, eta_fp64_device=eta,
-               info=int(info), reps=reps)
+               info=int(info), reps=reps, roofline=roof)
     del A, Xt, Bc, Xc, work, R, X, B
     torch.cuda.empty_cache()
     return out
@@ -282,9 +338,13 @@ def bench_batched(torch, mg, synth, dtype, reps: int = 10, seed: int = 2026):
             times.append(e0.elapsed_time(e1))
     ms = _median(times)
     flops = sum(nominal_flops(k, 1) for k in sizes)
+    # each system's lower triangle read and L written over it, b read and x written
+    nbytes = sum(k * (k + 1) + 2 * k for k in sizes) * es
+    peak = FP64_PEAK_TFLOPS if dtype == torch.float64 else FP32_PEAK_TFLOPS
     out = dict(dtype="f64" if dtype == torch.float64 else "f32", batch=len(sizes), ms=round(ms, 4),
                systems_per_s=round(len(sizes) / (ms / 1e3), 1), tflops=round(flops / (ms / 1e3) / 1e12, 3),
-               info_nonzero=int((info != 0).sum()), plan=plan.info())
+               info_nonzero=int((info != 0).sum()), plan=plan.info(),
+               roofline=roofline_obj("k_batched_posv (one replay)", flops, nbytes, ms, 1, peak))
     del plan, A, B, A0, B0
     torch.cuda.empty_cache()
     return out
@@ -307,6 +367,8 @@ def bench_adjoint(torch, mg, synth, n: int = 8192, nrhs: int = 64, reps: int = 5
     _lib.call("mg_potrs_buffer_size", h.h, _lib.MG_F64, n, nrhs, ctypes.byref(wb))
     work = torch.empty(max(1, wb.value), dtype=torch.uint8, device=A.device)
     fw, bw = [], []
+    h.set_profiling(True, kinds=[_lib.MG_PROF_ADJOINT])
+    h.profile(_lib.MG_PROF_ADJOINT, reset=True)
     for r in range(reps + 1):
         A.copy_(A0)
         Bc.copy_(Bc0)
@@ -322,11 +384,15 @@ def bench_adjoint(torch, mg, synth, n: int = 8192, nrhs: int = 64, reps: int = 5
         if r >= 1:
             fw.append(ev[0].elapsed_time(ev[1]))
             bw.append(ev[1].elapsed_time(ev[2]))
+    ad = h.profile(_lib.MG_PROF_ADJOINT, reset=True)
+    h.set_profiling(False)
     f, b = _median(fw), _median(bw)
     bflops = 2.0 * n * n * nrhs + 4.0 * n * n * nrhs
+    roof = (roofline_obj("k_syr2k_grad", ad["flops"], ad["bytes"], ad["ms"], ad["launches"], FP64_PEAK_TFLOPS)
+            if ad["launches"] else None)
     return dict(n=n, nrhs=nrhs, forward_ms=round(f, 3), backward_ms=round(b, 3),
                 forward_tflops=round(nominal_flops(n, nrhs) / (f / 1e3) / 1e12, 3),
-                backward_tflops=round(bflops / (b / 1e3) / 1e12, 3), info=int(info))
+                backward_tflops=round(bflops / (b / 1e3) / 1e12, 3), info=int(info), roofline=roof)
 
 
 def bench_gp(torch, mg, synth, n: int = 16384, nrhs: int = 1, reps: int = 3, seed: int = 7700):
@@ -397,19 +463,89 @@ def bench_gp_grad(torch, mg, synth, n: int = 4096, nrhs: int = 1, reps: int = 3,
     return dict(n=n, nrhs=nrhs, ms=round(t, 3), tflops=round(2.0 * n ** 3 / (t / 1e3) / 1e12, 3), info=int(info))
 
 
-def cpu_baseline(torch, synth, n: int = 8192, nrhs: int = 16, seed: int = 4242):
+def cpu_baseline(torch, synth, n: int = 6144, nrhs: int = 16, reps: int = 3, seed: int = 4242):
+    """The CPU oracle (plain C, FP64, OpenMP) on a bounded sample of the
+    headline recipe: median of `reps` posv runs at order n."""
     import oracle  # CPU oracle: baseline leg only
     A = synth.torch_gram_spd_cond(n, seed, 1e4)
     Xt = synth.torch_normal((n, nrhs), seed + 1)
     B = (A @ Xt).cpu().numpy()
     Ah = A.cpu().numpy()
     del A, Xt
-    t0 = time.perf_counter()
-    X, info = oracle.posv(Ah, B)
-    dt = time.perf_counter() - t0
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        X, info = oracle.posv(Ah, B)
+        ts.append(time.perf_counter() - t0)
+    dt = _median(ts)
     return dict(value=nominal_flops(n, nrhs) / dt / 1e12, unit="TFLOP/s", cores=oracle.num_threads(),
-                kind="oracle", sample=f"oracle posv (plain C FP64) on the same recipe at n={n}, nrhs={nrhs}: "
-                                      f"{dt:.1f} s", seconds=dt, info=int(info))
+                kind="oracle", sample=f"oracle posv (plain C FP64) on the same recipe at n={n}, nrhs={nrhs}, "
+                                      f"median of {reps}: {dt:.2f} s", seconds=dt, runs_s=[round(t, 3) for t in ts],
+                info=int(info))
+
+
+def cpu_library_context(torch, synth, n: int = 8192, nrhs: int = 16, reps: int = 3, seed: int = 4243):
+    """Context line, not a target: LAPACK dpotrf + dpotrs from the host's
+    scipy (OpenBLAS) on the same recipe, median of `reps`."""
+    import numpy as np
+    try:
+        from scipy.linalg import lapack
+    except ImportError:
+        return None
+    A = synth.torch_gram_spd_cond(n, seed, 1e4)
+    Xt = synth.torch_normal((n, nrhs), seed + 1)
+    B = np.asfortranarray((A @ Xt).cpu().numpy())
+    Ah = np.asfortranarray(A.cpu().numpy())
+    del A, Xt
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((d.get("num_threads") or 0) for d in threadpool_info()) or None
+    except Exception:
+        pass
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        c, inf1 = lapack.dpotrf(Ah, lower=1, clean=0, overwrite_a=0)
+        x, inf2 = lapack.dpotrs(c, B, lower=1)
+        ts.append(time.perf_counter() - t0)
+    dt = _median(ts)
+    return dict(value=nominal_flops(n, nrhs) / dt / 1e12, unit="TFLOP/s", threads=threads,
+                kind="scipy-openblas dpotrf+dpotrs", sample=f"n={n}, nrhs={nrhs}, median of {reps}: {dt:.3f} s",
+                info=int(inf1) or int(inf2))
+
+
+LEGS = ("mixed_fp32", "mixed_bf16", "small_n1024", "batched_f64", "batched_f32", "adjoint_n8192",
+        "fp64_n8192", "fp64_n16384", "gp_loglik_n16384", "gp_loglik_grad_n4096")
+
+
+def run_extra(key, torch, mg, synth, args):
+    if key == "mixed_fp32":
+        return bench_mixed(torch, mg, synth, args.n, 8, 1e4, "fp32", 3)
+    if key == "mixed_bf16":
+        return bench_mixed(torch, mg, synth, args.n, 8, 1e2, "bf16", 3)
+    if key == "small_n1024":
+        return bench_small(torch, mg, synth)
+    if key == "batched_f64":
+        return bench_batched(torch, mg, synth, torch.float64)
+    if key == "batched_f32":
+        return bench_batched(torch, mg, synth, torch.float32)
+    if key == "adjoint_n8192":
+        return bench_adjoint(torch, mg, synth)
+    if key in ("fp64_n8192", "fp64_n16384"):
+        n = int(key.split("_n")[1])
+        r = bench_fp64(torch, mg, synth, n, 16, 5, 2)
+        tr = r["trailing"]
+        return dict(n=n, nrhs=16, ms=round(r["ms_step"], 3), tflops=round(r["tflops"], 3), nb=r["nb"],
+                    eta_fp64_device=r["eta_fp64_device"], info=r["info"], solve=r["solve"],
+                    kernel_ms={k: round(v["ms"], 3) for k, v in r["prof"].items()},
+                    roofline=(roofline_obj("k_syrk_lower<double, true, 4, false>", tr["flops"], tr["bytes"],
+                                           tr["ms"], tr["launches"], FP64_PEAK_TFLOPS) if tr["launches"] else None))
+    if key == "gp_loglik_n16384":
+        return bench_gp(torch, mg, synth)
+    if key == "gp_loglik_grad_n4096":
+        return bench_gp_grad(torch, mg, synth)
+    raise ValueError(key)
 
 
 def main():
@@ -423,6 +559,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision, batched, adjoint and n=1024 measurements")
+    ap.add_argument("--only", choices=LEGS, default=None,
+                    help="run one extra measurement alone (no headline leg, no CPU baseline), e.g. for profiling")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the solver runs on exactly one GPU (asked for --gpus {args.gpus}); "
@@ -436,32 +574,27 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     mg.load()
+    if args.only:
+        out = run_extra(args.only, torch, mg, synth, args)
+        log(f"[bench] {args.only}: {out}")
+        print(json.dumps({"extra": args.only, **out}), flush=True)
+        return
 
     r = bench_fp64(torch, mg, synth, args.n, args.nrhs, args.steps, args.warmup, args.nb)
     log(f"[bench] fp64 n={args.n}: {r['ms_step']:.2f} ms/step, {r['tflops']:.2f} TFLOP/s, eta {r['eta_fp64_device']:.2e}")
     extras = None
     if not args.no_extras:
         extras = {}
-        extras["mixed_fp32"] = bench_mixed(torch, mg, synth, args.n, 8, 1e4, "fp32", 3)
-        log(f"[bench] mixed fp32: {extras['mixed_fp32']}")
-        extras["mixed_bf16"] = bench_mixed(torch, mg, synth, args.n, 8, 1e2, "bf16", 3)
-        log(f"[bench] mixed bf16: {extras['mixed_bf16']}")
-        extras["small_n1024"] = bench_small(torch, mg, synth)
-        log(f"[bench] n=1024: {extras['small_n1024']}")
-        for dt, key in ((torch.float64, "batched_f64"), (torch.float32, "batched_f32")):
-            extras[key] = bench_batched(torch, mg, synth, dt)
+        for key in LEGS:
+            extras[key] = run_extra(key, torch, mg, synth, args)
             log(f"[bench] {key}: {extras[key]}")
-        extras["adjoint_n8192"] = bench_adjoint(torch, mg, synth)
-        log(f"[bench] adjoint: {extras['adjoint_n8192']}")
-        extras["gp_loglik_n16384"] = bench_gp(torch, mg, synth)
-        log(f"[bench] gp_loglik: {extras['gp_loglik_n16384']}")
-        extras["gp_loglik_grad_n4096"] = bench_gp_grad(torch, mg, synth)
-        log(f"[bench] gp_loglik_grad: {extras['gp_loglik_grad_n4096']}")
-    cpu = None
+    cpu = cpu_lib = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         cpu = cpu_baseline(torch, synth)
         log(f"[bench] cpu baseline: {cpu['value'] * 1e3:.2f} GFLOP/s on {cpu['cores']} threads")
+        cpu_lib = cpu_library_context(torch, synth)
+        log(f"[bench] cpu library context: {cpu_lib}")
     tr = r["trailing"]
     roof = None
     if r["trailing_tflops"] is not None:
@@ -493,6 +626,8 @@ def main():
         "info": r["info"],
         "roofline": roof,
         "cpu_baseline": cpu,
+        "cpu_library_context": cpu_lib,
+        "solve": r["solve"],
         # event-summed kernel time per kind, from one extra step after the timed region
         "kernel_ms": {k: round(v["ms"], 3) for k, v in r["prof"].items()},
         "extras": extras,

@@ -95,6 +95,21 @@ mg_status mg_set_lookahead(mg_handle_t handle, int32_t enable);
  * Errors: -1 NULL handle, -2 limit outside [-1, 2^30]. */
 mg_status mg_set_sweep_spin_limit(mg_handle_t handle, int64_t limit);
 
+/* How the triangular sweeps (potrs and every solve built on it) apply a
+ * 64 x 64 diagonal block of L:
+ *   MG_SOLVE_INVERSE (default): each block's inverse is formed by the
+ *     workgroup that owns the block when it starts, while it still waits for
+ *     the blocks before it, and the block's solution is then one product on
+ *     the matrix pipe.  The result satisfies the usual backward-error bound
+ *     up to a factor of the diagonal blocks' condition number.
+ *   MG_SOLVE_SUBSTITUTION: forward/back substitution in registers, 64
+ *     dependent steps per block (longer chain); exact whenever the data and
+ *     every intermediate are representable, e.g. integer factors with
+ *     power-of-two pivots.
+ * Errors: -1 NULL handle, -2 unknown mode. */
+typedef enum { MG_SOLVE_INVERSE = 0, MG_SOLVE_SUBSTITUTION = 1 } mg_solve_mode;
+mg_status mg_set_solve_mode(mg_handle_t handle, mg_solve_mode mode);
+
 /* Block size potrf would use for (dtype, n).  Errors: -1, -2, -3 (n < 0), -4 NULL. */
 mg_status mg_get_block_size(mg_handle_t handle, mg_dtype dtype, int64_t n, int64_t *nb);
 

@@ -71,6 +71,13 @@ class Handle:
         0: give up at once, which drives the failure path for tests)."""
         call("mg_set_sweep_spin_limit", self.h, int(limit))
 
+    def set_solve_mode(self, mode: str = "inverse"):
+        """How the triangular sweeps apply a diagonal block: "inverse"
+        (default; an MFMA product with the block's inverse) or
+        "substitution" (exact on exactly representable data)."""
+        code = {"inverse": _lib.MG_SOLVE_INVERSE, "substitution": _lib.MG_SOLVE_SUBSTITUTION}[mode]
+        call("mg_set_solve_mode", self.h, code)
+
     def block_size(self, n: int, dtype_code: int = _lib.MG_F64) -> int:
         out = ctypes.c_int64()
         call("mg_get_block_size", self.h, dtype_code, int(n), ctypes.byref(out))

@@ -31,6 +31,8 @@ MG_PROF_BATCHED = 5
 MG_PROF_TRAILING_NARROW = 6
 MG_GRAD_SYM = 0
 MG_GRAD_LOWER = 1
+MG_SOLVE_INVERSE = 0
+MG_SOLVE_SUBSTITUTION = 1
 
 i32 = ctypes.c_int32
 i64 = ctypes.c_int64
@@ -47,6 +49,7 @@ SIGNATURES = {
     "mg_set_block_size": (i32, [vp, i64]),
     "mg_set_lookahead": (i32, [vp, i32]),
     "mg_set_sweep_spin_limit": (i32, [vp, i64]),
+    "mg_set_solve_mode": (i32, [vp, i32]),
     "mg_get_block_size": (i32, [vp, i32, i64, ctypes.POINTER(i64)]),
     "mg_potrf": (i32, [vp, i32, i64, vp, i64, vp]),
     "mg_potrs_buffer_size": (i32, [vp, i32, i64, i64, ctypes.POINTER(sz)]),

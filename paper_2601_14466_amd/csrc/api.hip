@@ -111,6 +111,13 @@ mg_status mg_set_sweep_spin_limit(mg_handle_t h, int64_t limit) {
     return MG_OK;
 }
 
+mg_status mg_set_solve_mode(mg_handle_t h, mg_solve_mode mode) {
+    if (!h) return -1;
+    if (mode != MG_SOLVE_INVERSE && mode != MG_SOLVE_SUBSTITUTION) return -2;
+    h->solve_mode = (int)mode;
+    return MG_OK;
+}
+
 mg_status mg_set_lookahead(mg_handle_t h, int32_t enable) {
     if (!h) return -1;
     if (enable < 0 || enable > 2) return -2;

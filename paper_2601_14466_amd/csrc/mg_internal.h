@@ -24,6 +24,7 @@ struct mg_handle_s {
     int side_mode = 0;       // look-ahead mode the bulk stream was created for
     int trail_lo = 1;        // FP32 trailing update: 1 plain, 2 operands rounded to bfloat16
     int spin_limit = -1;     // potrs sweeps: polls before a wait gives up (-1: the built-in limit)
+    int solve_mode = MG_SOLVE_INVERSE;  // potrs sweeps: diagonal blocks by inverse (MFMA) or substitution
     void* bf16_panel = nullptr;  // bfloat16 mode: three n x 512 row-major panel buffers
     uint32_t profiling = 0;  // bit k set: launches of kind k are bracketed by events
     mg_prof_counter prof[MG_PROF_KINDS];

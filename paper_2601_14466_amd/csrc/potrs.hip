@@ -16,13 +16,19 @@
 //     (16 rows of the block each) apply acc += L_ij X_j with MFMAs (forward;
 //     the backward sweep reads L down its columns for L_ji^T), L streamed
 //     from memory;
-//   * the products go through LDS to a row-per-lane layout and wave w solves
-//     the right-hand sides w, w + 4, ... by substitution in registers (each
-//     step's pivot row broadcast by readlane), with L_ii staged in LDS
-//     pre-scaled by its pivots (column c divided by L_cc for the forward
-//     sweep, row c for the backward one, diagonal 0) so a step is one FMA per
-//     value and the division by the pivot happens once at the end (integer
-//     data with power-of-two pivots stays exact).
+//   * the diagonal block is then applied in one of two ways (a handle mode):
+//     - inverse (default): when the workgroup starts, long before its last
+//       dependency arrives, it forms Z = L_ii^{-1} in LDS (one lane per
+//       column of Z); at the end v = b_i - sum goes through LDS and each
+//       wave multiplies its 16 rows of Z (Z^T backward) by v on the matrix
+//       pipe, so the chain after the last dependency is a few MFMAs;
+//     - substitution: the products go through LDS to a row-per-lane layout
+//       and wave w solves the right-hand sides w, w + 4, ... in registers
+//       (each step's pivot row broadcast by readlane), with L_ii staged in LDS
+//       pre-scaled by its pivots (column c divided by L_cc for the forward
+//       sweep, row c for the backward one, diagonal 0) so a step is one FMA
+//       per value and the division by the pivot happens once at the end
+//       (integer data with power-of-two pivots stays exact).
 // Every wait is bounded: a block that stays unwritten past the spin limit
 // sets an error word in the workspace and the kernel drains; after the two
 // sweeps a check kernel turns a set error word into a NaN-filled result and
@@ -105,6 +111,44 @@ __device__ __forceinline__ void stage_diag(T* Ls, T* piv, const T* L, int64_t ld
     }
 }
 
+// Z = L_jj^{-1} (jb x jb lower, identity-padded to 64 x 64) into
+// Ls[r*LDP + c] = Z(r, c).  L_jj is first staged column-major in the same
+// buffer (Ls[c*LDP + r] = L(r, c) on and below the diagonal) with the
+// reciprocals of its pivots in rpiv; wave 0 then forms Z a column per lane by
+// right-looking substitution on the unit columns (z_c *= 1/L(c,c), then
+// z_r -= L(r,c) z_c for r > c), z in registers and L read as LDS broadcasts
+// (the same entry for every lane).  The wave reads all of Ls before it writes
+// Z over it (LDS operations of one wave complete in program order).  All 256
+// threads take part in the staging.
+template <typename T>
+__device__ __forceinline__ void stage_inverse(T* Ls, T* rpiv, const T* L, int64_t lda, int64_t j0, int jb) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < JB * JB / 256; ++q) {
+        const int e = tid + 256 * q;
+        const int rr = e & (JB - 1), cc = e >> 6;
+        const T v = (rr < jb && cc < jb && rr >= cc) ? L[idx(j0 + rr, j0 + cc, lda)] : (T)(rr == cc ? 1 : 0);
+        Ls[cc * LDP + rr] = v;
+        if (rr == cc) rpiv[rr] = (T)1 / v;
+    }
+    __syncthreads();
+    if (tid < JB) {
+        T z[JB];
+#pragma unroll
+        for (int r = 0; r < JB; ++r) z[r] = (r == tid) ? (T)1 : (T)0;
+#pragma unroll
+        for (int c = 0; c < JB; ++c) {
+            const T zc = z[c] * rpiv[c];
+            z[c] = zc;
+#pragma unroll
+            for (int r = c + 1; r < JB; ++r) z[r] = z[r] - Ls[c * LDP + r] * zc;
+        }
+#pragma unroll
+        for (int r = 0; r < JB; ++r) Ls[r * LDP + tid] = z[r];
+    }
+    __syncthreads();
+}
+
 // Cross-workgroup traffic of the sweeps (the solution blocks and the error
 // word) uses device-coherent loads and stores, which bypass the per-XCD
 // caches, so a value stored by one workgroup is seen by the others without
@@ -125,8 +169,11 @@ __device__ __forceinline__ void store_coherent(T* p, T v) {
 // n x nrhs column-major; 16 RT right-hand sides per pass.
 // spin_limit: polls before a wait gives up (0: give up at the first
 // dependency without waiting, which exercises the give-up path).
-template <typename T, int RT, bool FWD>
-__global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t lda, int64_t n, int64_t nrhs,
+// INV: the diagonal block is applied as its inverse (formed when the
+// workgroup starts, off the chain of dependencies) by MFMA products;
+// otherwise by substitution.
+template <typename T, int RT, bool FWD, bool INV>
+__global__ __launch_bounds__(256, 2) void k_sweep(const T* __restrict__ L, int64_t lda, int64_t n, int64_t nrhs,
                                                const T* __restrict__ In, int64_t ldi, T* Out, int64_t ldo,
                                                SweepSync* sy, const int32_t* info, int spin_limit) {
     constexpr int NR = 16 * RT, XP = NR + 1, QW = NR / 4;
@@ -147,7 +194,8 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t 
     const int bi = FWD ? t : nblk - 1 - t;
     const int64_t r0 = (int64_t)bi * JB;
     const int jb = (int)(n - r0 < JB ? n - r0 : JB);
-    stage_diag<T, !FWD>(Ls, piv, L, lda, r0, jb);
+    if constexpr (INV) stage_inverse<T>(Ls, piv, L, lda, r0, jb);
+    else stage_diag<T, !FWD>(Ls, piv, L, lda, r0, jb);
     // MFMA phase: wave w owns rows 16 w .. 16 w + 15 of the block
     const int64_t rwc = (16 * w + i < jb) ? r0 + 16 * w + i : r0;  // clamped for loads
     // blocks this one depends on: j = 0 .. bi - 1 (forward) or j = nblk - 1
@@ -161,11 +209,24 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t 
     constexpr int XPT = JB * NR / 256;  // solution values each thread moves per block
     // this block's right-hand sides (a lane per row, wave w takes q = w + 4 u),
     // requested now so that their latency is off the critical path
-    T vin[QW];
+    // (substitution: a lane per row, wave w takes q = w + 4 u; inverse: the
+    // accumulator layout, row 16 w + i, right-hand side 16 rt + tcol(g, r))
+    T vin[INV ? 4 * RT : QW];
+    if constexpr (INV) {
+        const bool rok = 16 * w + i < jb;
 #pragma unroll
-    for (int u = 0; u < QW; ++u) {
-        const int q = w + 4 * u;
-        vin[u] = (lane < jb && rc0 + q < nrhs) ? In[idx(r0 + lane, rc0 + q, ldi)] : (T)0;
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t q = rc0 + 16 * rt + tcol<T>(g, r);
+                vin[4 * rt + r] = (rok && q < nrhs) ? In[idx(r0 + 16 * w + i, q, ldi)] : (T)0;
+            }
+    } else {
+#pragma unroll
+        for (int u = 0; u < QW; ++u) {
+            const int q = w + 4 * u;
+            vin[u] = (lane < jb && rc0 + q < nrhs) ? In[idx(r0 + lane, rc0 + q, ldi)] : (T)0;
+        }
     }
     {
         // two accumulators (even and odd k-steps) halve the chain of
@@ -258,6 +319,45 @@ __global__ __launch_bounds__(256) void k_sweep(const T* __restrict__ L, int64_t 
 #pragma unroll
             for (int k = 0; k < XPT; ++k) xc[k] = xn[k];
         }
+        if constexpr (INV) {
+            // v = In - sum over the dependencies, rows 16 w + i of this
+            // wave, into LDS as v(row, rhs) (rows past jb are 0) ...
+            const bool rok = 16 * w + i < jb;
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    part[(16 * w + i) * XP + 16 * rt + tcol<T>(g, r)] =
+                        rok ? vin[4 * rt + r] - (acc[rt][r] + acc2[rt][r]) : (T)0;
+            __syncthreads();
+            // ... then x = Z v (forward, Z = L_ii^{-1} lower: rows of wave w
+            // need k < 16 (w + 1)) or x = Z^T v (backward: k >= 16 w), a
+            // 16 x 16 tile per wave on the matrix pipe, two accumulators
+            V4<T> xa[RT], xb[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) xa[rt] = xb[rt] = V4<T>{0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < JB / 4; ++ks) {
+                if (FWD ? (ks >= 4 * (w + 1)) : (ks < 4 * w)) continue;  // wave-uniform
+                const int k = 4 * ks + g;
+                const T zx = FWD ? Ls[(16 * w + i) * LDP + k] : Ls[k * LDP + 16 * w + i];
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    if (ks & 1) xb[rt] = mma_xzt(xb[rt], zx, part[k * XP + 16 * rt + i]);
+                    else xa[rt] = mma_xzt(xa[rt], zx, part[k * XP + 16 * rt + i]);
+                }
+            }
+            if (16 * w + i < jb) {
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t q = rc0 + 16 * rt + tcol<T>(g, r);
+                        if (q < nrhs) store_coherent(&Out[idx(r0 + 16 * w + i, q, ldo)], xa[rt][r] + xb[rt][r]);
+                    }
+            }
+            return;
+        }
         // partial products to LDS, one row per entry: lane (i, g) holds rows
         // 16 w + i, right-hand sides 16 rt + tcol(g, r)
 #pragma unroll
@@ -315,7 +415,7 @@ __global__ __launch_bounds__(256) void k_sweep_check(T* Out, int64_t ld, int64_t
     for (int64_t e = threadIdx.x; e < tot; e += 256) Out[idx(e % n, e / n, ld)] = (T)NAN;
 }
 
-template <typename T>
+template <typename T, bool INV>
 static mg_status sweep(hipStream_t st, int64_t n, int64_t nrhs, const T* L, int64_t lda, T* B, int64_t ldb, T* Y,
                        SweepSync* sy, int32_t* info, int spin_limit) {
     const int64_t np = sweep_passes(nrhs);
@@ -323,13 +423,13 @@ static mg_status sweep(hipStream_t st, int64_t n, int64_t nrhs, const T* L, int6
     const unsigned gfill = (unsigned)std::min<int64_t>(std::max<int64_t>(1, cdiv(n * nrhs, 256)), 2048);
     hipLaunchKernelGGL((k_sweep_init<T>), dim3(gfill), dim3(256), 0, st, Y, n, n, nrhs, sy, info);
     MG_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_sweep<T, 1, true>), grid, dim3(256), 0, st, L, lda, n, nrhs, (const T*)B, ldb, Y, n, sy,
+    hipLaunchKernelGGL((k_sweep<T, 1, true, INV>), grid, dim3(256), 0, st, L, lda, n, nrhs, (const T*)B, ldb, Y, n, sy,
                        info, spin_limit);
     MG_LAUNCH_CHECK();
     // B has been read; it now receives X
     hipLaunchKernelGGL((k_sweep_init<T>), dim3(gfill), dim3(256), 0, st, B, ldb, n, nrhs, sy + np, info);
     MG_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_sweep<T, 1, false>), grid, dim3(256), 0, st, L, lda, n, nrhs, (const T*)Y, n, B, ldb,
+    hipLaunchKernelGGL((k_sweep<T, 1, false, INV>), grid, dim3(256), 0, st, L, lda, n, nrhs, (const T*)Y, n, B, ldb,
                        sy + np, info, spin_limit);
     MG_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_sweep_check<T>), dim3(1), dim3(256), 0, st, B, ldb, n, nrhs, (const SweepSync*)sy,
@@ -347,7 +447,8 @@ mg_status potrs_impl(mg_handle_t h, int64_t n, int64_t nrhs, const T* L, int64_t
     if ((rc = prof_begin(h, MG_PROF_SOLVE, st))) return rc;
     SweepSync* sy = (SweepSync*)((char*)Y + y_bytes(n, nrhs, (int)sizeof(T)));
     const int lim = h->spin_limit < 0 ? SWEEP_SPIN_LIMIT : h->spin_limit;
-    rc = sweep<T>(st, n, nrhs, L, lda, B, ldb, Y, sy, info, lim);
+    rc = h->solve_mode == MG_SOLVE_SUBSTITUTION ? sweep<T, false>(st, n, nrhs, L, lda, B, ldb, Y, sy, info, lim)
+                                                 : sweep<T, true>(st, n, nrhs, L, lda, B, ldb, Y, sy, info, lim);
     if (rc) return rc;
     const double nd = (double)n;
     return prof_end(h, MG_PROF_SOLVE, 2.0 * nd * nd * (double)nrhs,

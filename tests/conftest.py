@@ -18,3 +18,14 @@ def orc():
     import oracle
     oracle._load()
     return oracle
+
+
+@pytest.fixture
+def substitution():
+    """Run the test with the sweeps' diagonal blocks solved by substitution
+    (exact on exactly representable data) instead of by their inverses."""
+    import paper_2601_14466_amd as mg
+    h = mg.handle()
+    h.set_solve_mode("substitution")
+    yield h
+    h.set_solve_mode("inverse")

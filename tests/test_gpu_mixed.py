@@ -37,10 +37,10 @@ def _solve(mg, A, B, **kw):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("n", [65, 300, 700])
-def test_integer_family_needs_no_refinement(mg, orc, n, prec):
-    """The low-precision factor and solve are exact on the integer family
-    (all values below 2^24, power-of-two pivots, entries representable in
-    bfloat16), so x0 = x_true and no correction is taken."""
+def test_integer_family_needs_no_refinement(mg, orc, substitution, n, prec):
+    """The low-precision factor and solve (by substitution) are exact on the
+    integer family (all values below 2^24, power-of-two pivots, entries
+    representable in bfloat16), so x0 = x_true and no correction is taken."""
     L0, A = synth.integer_exact(n, 500 + n)
     xt = synth.integer_vector((n, 2), n)
     X, st = _solve(mg, A, A @ xt, precision=prec)
@@ -121,7 +121,7 @@ def block_size(mg):
 
 @pytest.mark.parametrize("nb", [256, 512])
 @pytest.mark.parametrize("n", [1100, 2600, 4100])
-def test_large_rank_integer_family_bitwise(mg, orc, block_size, n, nb):
+def test_large_rank_integer_family_bitwise(mg, orc, block_size, substitution, n, nb):
     """Block columns of 256 / 512 drive the rank-256/512 binary32 update (the
     8-deep operand ring at 512), and in bfloat16 mode the packed row-major
     panel copies (three buffers rotating over the look-ahead streams) and the
