@@ -171,6 +171,32 @@ mg_status mg_posv(mg_handle_t handle, mg_dtype dtype, int64_t n, int64_t nrhs, v
                   int32_t *info);
 
 /*
+ * posv without allocation.  For callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same operation, arguments, results and info convention as
+ * mg_posv, with no work argument: the solve's scratch (Y = L^{-1} B and the
+ * sweep words, mg_potrs_buffer_size bytes) lives in a library-owned device
+ * array of MG_NOALLOC_SCRATCH_BYTES on each GPU, created with the library's
+ * code object and held until the process ends; its device address is looked
+ * up once per device by mg_create.  The call allocates nothing (the handle's
+ * look-ahead streams are created by mg_create; mg_set_lookahead(h, 2)
+ * re-creates one at the next factorisation).
+ * The array is shared by every call on one GPU and keeps the last call's
+ * contents (the sweep words are reset by each call): calls whose work
+ * overlaps in time on one GPU -- on different streams or handles -- race on
+ * it and give undefined results, so serialise them.
+ * Errors: -1 handle, -2 dtype, -3 n < 0, -4 nrhs < 0, -5 A NULL with n > 0,
+ * -6 lda, -7 B NULL, -8 ldb < max(1,n), -9 info NULL; MG_ERR_SCRATCH_LIMIT
+ * (nothing enqueued) when mg_potrs_buffer_size(dtype, n, nrhs) exceeds
+ * MG_NOALLOC_SCRATCH_BYTES, i.e. roughly when n * nrhs * (8 for MG_F64, 4 for
+ * MG_F32) > 32 MiB.
+ */
+#define MG_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+#define MG_ERR_SCRATCH_LIMIT 5 /* mg_posv_noalloc: problem needs more than MG_NOALLOC_SCRATCH_BYTES */
+mg_status mg_posv_noalloc(mg_handle_t handle, mg_dtype dtype, int64_t n, int64_t nrhs, void *A, int64_t lda,
+                          void *B, int64_t ldb, int32_t *info);
+
+/*
  * Mixed precision with iterative refinement.  The paper is silent on
  * precision; this is the classic scheme for SPD systems (Langou et al.,
  * SC'06; Carson & Higham 2018): factor a binary32 copy of A (diagonal blocks

@@ -19,7 +19,7 @@ from . import _lib
 from ._lib import MgError, call, load, raw  # noqa: F401
 
 __all__ = [
-    "Handle", "handle", "potrf", "potrs", "posv", "posv_mixed", "posv_backward", "PosvFunction", "BatchPlan",
+    "Handle", "handle", "potrf", "potrs", "posv", "posv_noalloc", "posv_mixed", "posv_backward", "PosvFunction", "BatchPlan",
     "posv_batched", "logdet", "gp_loglik", "gp_loglik_grad", "GPLogLik", "colmajor",
     "MgError", "load", "call", "raw",
 ]
@@ -200,6 +200,27 @@ def posv(A, B, nb: int | None = None):
     finally:
         if nb is not None:
             h.set_block_size(0)
+    X = Xc.T
+    return (X.reshape(n) if flat else X), info
+
+
+def posv_noalloc(A, B):
+    """posv through mg_posv_noalloc: the solve's scratch is the library's own
+    per-GPU array, so the call allocates no device memory in the library
+    (this wrapper still allocates the column-major copies it hands over).
+    Returns (X, info) as posv; raises MgError (MG_ERR_SCRATCH_LIMIT) when
+    n * nrhs is too large for the array.  Calls that overlap in time on one
+    GPU share the array and must be serialised."""
+    torch = _torch()
+    _check_cuda(A, B)
+    flat = B.dim() == 1
+    n = A.shape[0]
+    nrhs = 1 if flat else B.shape[1]
+    h = handle()
+    Ac = A.T.clone(memory_format=torch.contiguous_format)
+    Xc = (B.reshape(n, 1) if flat else B).T.clone(memory_format=torch.contiguous_format)
+    info = torch.zeros((), dtype=torch.int32, device=A.device)
+    call("mg_posv_noalloc", h.h, _dtype_code(A), n, nrhs, _ptr(Ac), max(1, n), _ptr(Xc), max(1, n), _ptr(info))
     X = Xc.T
     return (X.reshape(n) if flat else X), info
 

@@ -17,6 +17,8 @@ MG_ERR_HIP = 1
 MG_ERR_UNSUPPORTED = 2
 MG_ERR_INTERNAL = 3
 MG_ERR_ABORTED = 4
+MG_ERR_SCRATCH_LIMIT = 5
+MG_NOALLOC_SCRATCH_BYTES = 32 << 20
 MG_INFO_SOLVE_ABORTED = -1
 MG_F64 = 0
 MG_F32 = 1
@@ -55,6 +57,7 @@ SIGNATURES = {
     "mg_potrs_buffer_size": (i32, [vp, i32, i64, i64, ctypes.POINTER(sz)]),
     "mg_potrs": (i32, [vp, i32, i64, i64, vp, i64, vp, i64, vp, sz, vp]),
     "mg_posv": (i32, [vp, i32, i64, i64, vp, i64, vp, i64, vp, sz, vp]),
+    "mg_posv_noalloc": (i32, [vp, i32, i64, i64, vp, i64, vp, i64, vp]),
     "mg_posv_mixed_buffer_size": (i32, [vp, i32, i64, i64, i32, ctypes.POINTER(sz)]),
     "mg_posv_mixed": (i32, [vp, i32, i64, i64, vp, i64, vp, i64, vp, i64, vp, vp, sz, vp, vp]),
     "mg_posv_backward": (i32, [vp, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]),
@@ -97,7 +100,9 @@ class MgError(RuntimeError):
         kind = ("invalid argument %d" % -code) if code < 0 else {
             MG_ERR_HIP: "HIP runtime error", MG_ERR_UNSUPPORTED: "unsupported",
             MG_ERR_INTERNAL: "internal error",
-            MG_ERR_ABORTED: "a triangular sweep gave up waiting (bounded wait); the result is NaN"}.get(
+            MG_ERR_ABORTED: "a triangular sweep gave up waiting (bounded wait); the result is NaN",
+            MG_ERR_SCRATCH_LIMIT: "the solve needs more than the %d-byte no-allocation scratch array"
+                                  % MG_NOALLOC_SCRATCH_BYTES}.get(
                 code, "error %d" % code)
         super().__init__(f"{fn}: {kind} (status {code})")
         self.code = code

@@ -2,6 +2,7 @@
 // posv and logdet.  Every check runs on the host before anything is enqueued.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "mg_internal.h"
 #include "tile16.h"
@@ -50,6 +51,31 @@ __global__ __launch_bounds__(256) void k_logdet(const T* L, int64_t lda, int64_t
     if (threadIdx.x == 0) *out = (info && *info != 0) ? (double)NAN : 2.0 * part[0];
 }
 
+// Scratch of mg_posv_noalloc: Y = L^{-1} B and the sweep words live in this
+// file-scope device array (one copy per GPU, created with the code object)
+// instead of a caller workspace.  In host code `scratch` names a host-side
+// stand-in; its device address on each GPU comes from hipGetSymbolAddress,
+// looked up once per device (mg_create) and kept in scratch_addr.
+static __device__ __align__(256) unsigned char scratch[MG_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex scratch_mu;
+static void* scratch_addr[MAX_DEVICES];
+
+// Device address of `scratch` on the current device (h->device), looked up on
+// the first handle created there.
+static mg_status scratch_setup(mg_handle_t h) {
+    if (h->device < 0 || h->device >= MAX_DEVICES) return MG_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_addr[h->device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MG_ERR_HIP;
+        scratch_addr[h->device] = p;
+    }
+    h->scratch = scratch_addr[h->device];
+    return MG_OK;
+}
+
 }  // namespace mg
 
 static inline int es_of(mg_dtype dt) { return dt == MG_F64 ? 8 : 4; }
@@ -71,6 +97,12 @@ mg_status mg_create(mg_handle_t* handle, void* stream) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && cus > 0)
         h->cu_count = cus;
+    mg_status rc = scratch_setup(h);
+    if (rc == MG_OK) rc = ensure_streams(h);
+    if (rc != MG_OK) {
+        mg_destroy(h);
+        return rc;
+    }
     *handle = h;
     return MG_OK;
 }
@@ -191,6 +223,28 @@ mg_status mg_posv(mg_handle_t h, mg_dtype dt, int64_t n, int64_t nrhs, void* A, 
     }
     if ((rc = potrf_impl<float>(h, n, (float*)A, lda, info))) return rc;
     return potrs_impl<float>(h, n, nrhs, (const float*)A, lda, (float*)B, ldb, (float*)work, info);
+}
+
+mg_status mg_posv_noalloc(mg_handle_t h, mg_dtype dt, int64_t n, int64_t nrhs, void* A, int64_t lda, void* B,
+                          int64_t ldb, int32_t* info) {
+    if (!h) return -1;
+    if (!dtype_ok(dt)) return -2;
+    if (n < 0) return -3;
+    if (nrhs < 0) return -4;
+    if (!A && n > 0) return -5;
+    if (lda < std::max<int64_t>(1, n)) return -6;
+    if (!B && n > 0 && nrhs > 0) return -7;
+    if (ldb < std::max<int64_t>(1, n)) return -8;
+    if (!info) return -9;
+    if (potrs_work_bytes(n, nrhs, es_of(dt)) > MG_NOALLOC_SCRATCH_BYTES) return MG_ERR_SCRATCH_LIMIT;
+    if (!h->scratch) return MG_ERR_INTERNAL;
+    mg_status rc;
+    if (dt == MG_F64) {
+        if ((rc = potrf_impl<double>(h, n, (double*)A, lda, info))) return rc;
+        return potrs_impl<double>(h, n, nrhs, (const double*)A, lda, (double*)B, ldb, (double*)h->scratch, info);
+    }
+    if ((rc = potrf_impl<float>(h, n, (float*)A, lda, info))) return rc;
+    return potrs_impl<float>(h, n, nrhs, (const float*)A, lda, (float*)B, ldb, (float*)h->scratch, info);
 }
 
 mg_status mg_posv_mixed_buffer_size(mg_handle_t h, mg_prec lo, int64_t n, int64_t nrhs, int32_t fallback,

@@ -28,7 +28,8 @@ struct mg_handle_s {
     void* bf16_panel = nullptr;  // bfloat16 mode: three n x 512 row-major panel buffers
     uint32_t profiling = 0;  // bit k set: launches of kind k are bracketed by events
     mg_prof_counter prof[MG_PROF_KINDS];
-    // second stream and events for the look-ahead schedule (created on first use)
+    void* scratch = nullptr;  // device address of the no-allocation scratch array on this device
+    // second stream and events for the look-ahead schedule (created by mg_create)
     hipStream_t side = nullptr;   // look-ahead: bulk trailing update
     hipStream_t chain = nullptr;  // look-ahead: next block column and panel chain
     hipEvent_t ev_fork = nullptr, ev_panel = nullptr, ev_rest = nullptr, ev_join = nullptr;
@@ -71,5 +72,7 @@ mg_status posv_mixed_impl(mg_handle_t h, int lo, int64_t n, int64_t nrhs, const 
                           mg_ir_result* res, int32_t* info);
 
 mg_status set_info_zero(hipStream_t s, int32_t* info);
+// Create (or re-create after a mode change) the look-ahead streams and events.
+mg_status ensure_streams(mg_handle_t h);
 
 }  // namespace mg

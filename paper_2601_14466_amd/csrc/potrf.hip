@@ -800,14 +800,15 @@ static mg_status trailing(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int6
     return prof_end(h, kind, 2.0 * b * elems, (2.0 * elems + (md - c0) * b) * sizeof(T), st);
 }
 
-// The two streams of the look-ahead schedule (created on first use).  In
+// The two streams of the look-ahead schedule (created by mg_create, and again
+// at the next factorisation after the mode changes).  In
 // mode 2 the bulk stream is created with a CU mask that leaves one CU per XCD
 // out (mask bits 33 x for x = 0..7: one per group of 32 consecutive bits and
 // one per residue mod 8, so one per XCD whichever way the bits map to XCDs),
 // so that the one-workgroup diagonal factor on the chain stream finds a CU
 // the bulk update does not occupy.  A CU-masked stream synchronises with the
 // legacy default stream, which the schedule never uses.
-static mg_status ensure_side(mg_handle_t h) {
+mg_status ensure_streams(mg_handle_t h) {
     if (h->side && h->side_mode == h->lookahead) return MG_OK;
     if (h->side) {
         MG_HIP(hipStreamSynchronize(h->side));
@@ -869,7 +870,7 @@ mg_status potrf_impl(mg_handle_t h, int64_t n, T* A, int64_t lda, int32_t* info)
     // non-blocking, and fork from / join into the caller's stream by events
     // (the side stream's last work precedes the chain's last ev_rest wait
     // or, for the final step, is empty).
-    if ((rc = ensure_side(h))) return rc;
+    if ((rc = ensure_streams(h))) return rc;
     hipStream_t ch = h->chain;
     MG_HIP(hipEventRecord(h->ev_fork, st));
     MG_HIP(hipStreamWaitEvent(ch, h->ev_fork, 0));
