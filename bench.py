@@ -207,9 +207,9 @@ def bench_mixed(torch, mg, synth, n: int, nrhs: int, cond: float, precision: str
     the same nominal FP64 count as the FP64 path."""
     from paper_2601_14466_amd import _lib
     log(f"[bench] mixed {precision}: generating n={n} nrhs={nrhs} cond={cond:g} (Haar)")
-    A = synth.torch_haar_spd(n, cond, seed + n)       # symmetric: row-major bytes == column-major
-    Xt = synth.torch_normal((n, nrhs), seed + 1 + n)
-    Bc = (A @ Xt).T.contiguous()
+    A = synth.torch_haar_spd(n, cond, seed + n, log=lambda m: log(f"[bench] mixed {precision}: {m}"))
+    Xt = synth.torch_normal((n, nrhs), seed + 1 + n)   # A symmetric: row-major bytes == column-major
+    Bc = synth.torch_matmul_rows(A, Xt).T.contiguous()
     Xc = torch.empty_like(Bc)
     h = mg.handle()
     h.set_block_size(0)
@@ -253,7 +253,7 @@ def bench_mixed(torch, mg, synth, n: int, nrhs: int, cond: float, precision: str
                                 BF16_PEAK_TFLOPS)
     X = Xc.T
     B = Bc.T
-    R = B - A @ X
+    R = B - synth.torch_matmul_rows(A, X)
     anorm = float(A.abs().sum(1).max())
     eta = (R.abs().amax(0) / (anorm * X.abs().amax(0) + B.abs().amax(0))).max().item()
     out = dict(precision=precision, n=n, nrhs=nrhs, cond=cond, ms=round(ms, 3),
@@ -515,7 +515,7 @@ def cpu_library_context(torch, synth, n: int = 8192, nrhs: int = 16, reps: int =
                 info=int(inf1) or int(inf2))
 
 
-LEGS = ("mixed_fp32", "mixed_bf16", "small_n1024", "batched_f64", "batched_f32", "adjoint_n8192",
+LEGS = ("mixed_fp32", "mixed_bf16", "mixed_fp32_n65536", "small_n1024", "batched_f64", "batched_f32", "adjoint_n8192",
         "fp64_n8192", "fp64_n16384", "gp_loglik_n16384", "gp_loglik_grad_n4096")
 
 
@@ -524,6 +524,8 @@ def run_extra(key, torch, mg, synth, args):
         return bench_mixed(torch, mg, synth, args.n, 8, 1e4, "fp32", 3)
     if key == "mixed_bf16":
         return bench_mixed(torch, mg, synth, args.n, 8, 1e2, "bf16", 3)
+    if key == "mixed_fp32_n65536":
+        return bench_mixed(torch, mg, synth, 65536, 8, 1e4, "fp32", 1)
     if key == "small_n1024":
         return bench_small(torch, mg, synth)
     if key == "batched_f64":

@@ -241,7 +241,7 @@ def torch_matmul_rows(A, X):
     return out
 
 
-def _torch_haar_q_panels(n: int, gen, device, b: int = 4096):
+def _torch_haar_q_panels(n: int, gen, device, b: int = 4096, log=None):
     """Haar Q for n^2 >= 2^31, built so that no library call sees 2^31 or
     more elements.  Q is the orthogonal factor, with positive R diagonal,
     of the QR factorisation of a seeded Gaussian matrix Z (Mezzadri 2007),
@@ -268,18 +268,22 @@ def _torch_haar_q_panels(n: int, gen, device, b: int = 4096):
         s[s == 0] = 1.0
         Qt[k0:k1] = (Qk * s).T
         del W, Qk, Rk
+        if log:
+            log(f"Q panel {k0 // b + 1}/{(n + b - 1) // b}")
     Q = Qt.T.contiguous()
     del Qt
     return Q
 
 
-def torch_haar_spd(n: int, cond: float, seed: int, device="cuda"):
+def torch_haar_spd(n: int, cond: float, seed: int, device="cuda", log=None):
+    """A = Q diag(lambda) Q^T, Haar Q, lambda log-spaced with exact cond;
+    `log` (optional) receives progress messages for the large-order path."""
     import torch
 
     if n * n > VENDOR_CALL_MAX:
         gen = torch.Generator(device=device)
         gen.manual_seed(seed)
-        Q = _torch_haar_q_panels(n, gen, device)
+        Q = _torch_haar_q_panels(n, gen, device, log=log)
         lam = torch.as_tensor(logspaced_spectrum(n, cond), device=device)
         A = torch.empty((n, n), dtype=torch.float64, device=device)
         step = min(_rows_per_call(n), 8192)
@@ -290,6 +294,8 @@ def torch_haar_spd(n: int, cond: float, seed: int, device="cuda"):
                 j1 = min(n, j0 + step)
                 A[i0:i1, j0:j1] = Qi @ Q[j0:j1].T
             del Qi
+            if log:
+                log(f"A row block {i0 // step + 1}/{(n + step - 1) // step}")
         del Q
         return torch_symmetrize_lower_(A)
     gen = torch.Generator(device=device)

@@ -246,7 +246,7 @@ def test_full_size_config2_n65536(mg, orc):
     the check are logged separately."""
     n, cond = 65536, 1e4
     print(f"[n65536] generating Haar input n={n} cond={cond:g}", flush=True)
-    A = synth.torch_haar_spd(n, cond, 700 + n)
+    A = synth.torch_haar_spd(n, cond, 700 + n, log=lambda m: print(f"[n65536] {m}", flush=True))
     Xt = synth.torch_normal((n, 8), 701 + n)
     B = synth.torch_matmul_rows(A, Xt)
     del Xt
@@ -259,6 +259,7 @@ def test_full_size_config2_n65536(mg, orc):
     Ah = A.cpu().numpy()
     del A
     torch.cuda.empty_cache()
+    print("[n65536] A copied to the host; oracle residual", flush=True)
     eta = orc.backward_error(Ah.T, X.cpu().numpy(), B.cpu().numpy())
     print(f"[n65536] oracle eta max {eta.max():.3e}", flush=True)
     assert np.all(eta <= 1e-12), eta.max()
