@@ -30,6 +30,10 @@ optionally with log det):
 * ``posv_ir``   -- low-precision factor plus FP64 iterative refinement;
                    falls back to FP64 when it stalls.
 * ``posv_backward`` -- gB = A^{-1} gX, gA = -1/2 (gB X^T + X gB^T).
+* ``potrf_backward`` -- gradient with respect to A of f(chol(A)) from
+                   gL = df/dL: sym(L^{-T} Phi(L^T gL) L^{-1}), Phi the lower
+                   triangle with the diagonal halved (Murray 2016; the paper
+                   is silent).
 * ``gp_loglik`` -- Gaussian-process marginal log likelihood (paper: Research
                    Impact Statement, "Scientific applications", Cholesky
                    solve): -1/2 r^T A^{-1} r - 1/2 log det A - N/2 log(2 pi),
@@ -99,6 +103,8 @@ def _load():
     lib.or_posv_backward.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64,
                                      _dp, _i64, _dp, _i64, ctypes.c_int]
     lib.or_posv_backward.restype = None
+    lib.or_potrf_backward.argtypes = [_i64, _dp, _i64, _dp, _i64, _dp, _i64, ctypes.c_int]
+    lib.or_potrf_backward.restype = None
     lib.or_num_threads.argtypes = []
     lib.or_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -252,6 +258,21 @@ def posv_backward(L, X, GX, mode: int = 0):
     lib.or_posv_backward(n, nrhs, _ptr(Lf), _ld(Lf), _ptr(Xf), _ld(Xf), _ptr(Gf), _ld(Gf),
                          _ptr(GB), _ld(GB), _ptr(GA), _ld(GA), int(mode))
     return (GB.ravel() if flat else GB), GA
+
+
+def potrf_backward(L, GL, mode: int = 0):
+    """Gradient with respect to A of a scalar f(L), L = chol(A), given
+    GL = df/dL (only its lower triangle is used): the symmetric matrix
+    (S + S^T)/2 with S = L^{-T} Phi(L^T GL) L^{-1} (mode 0), or the gradient
+    with respect to the lower-triangle entries of A (mode 1; the strict
+    upper triangle of the result is 0)."""
+    lib = _load()
+    Lf = _f64(L)
+    Gf = _f64(np.tril(np.asarray(GL, dtype=np.float64)))
+    n = Lf.shape[0]
+    GA = np.zeros((n, n), dtype=np.float64, order="F")
+    lib.or_potrf_backward(n, _ptr(Lf), _ld(Lf), _ptr(Gf), _ld(Gf), _ptr(GA), _ld(GA), int(mode))
+    return GA
 
 
 def posv_batched(As, Bs):

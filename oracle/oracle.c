@@ -41,6 +41,18 @@
  *   or_posv_backward: adjoint of X = A^{-1} B:  gB = A^{-1} gX and
  *                gA = -1/2 (gB X^T + X gB^T) (symmetric convention), or the
  *                gradient with respect to the lower-triangle parameters.
+ *   or_potrf_backward: adjoint of L = chol(A) (the paper is silent; the
+ *                result is Murray, "Differentiation of the Cholesky
+ *                decomposition", 2016).  From A = L L^T,
+ *                L^{-1} dA L^{-T} = L^{-1} dL + (L^{-1} dL)^T with L^{-1} dL
+ *                lower triangular, so dL = L Phi(L^{-1} dA L^{-T}), Phi taking
+ *                the lower triangle with the diagonal halved.  For a scalar
+ *                f with gradient gL (lower) with respect to L,
+ *                df = <Phi(L^T gL), L^{-1} dA L^{-T}>, hence
+ *                S = L^{-T} Phi(L^T gL) L^{-1} and, dA being symmetric,
+ *                gA = (S + S^T)/2 (mode 0), or the gradient with respect to
+ *                the lower-triangle parameters (mode 1: S_ij + S_ji below
+ *                the diagonal, S_ii on it).
  *
  * Storage: column-major, element (i, j) at A[i + j*lda]; only the lower
  * triangle of A is read and the strict upper triangle is never written.
@@ -533,6 +545,53 @@ void or_posv_backward(int64_t n, int64_t nrhs, const double *L, int64_t lda,
             AT(GA, ldga, i, j) = v;
         }
     }
+}
+
+void or_potrf_backward(int64_t n, const double *L, int64_t lda, const double *GL, int64_t ldgl,
+                       double *GA, int64_t ldga, int mode)
+{
+    if (n <= 0)
+        return;
+    double *P = (double *)calloc((size_t)n * (size_t)n, sizeof(double));
+    /* P = Phi(L^T GL): (L^T GL)_ij = sum_{k >= max(i,j)} L_ki GL_kj, lower part
+     * only, diagonal halved (GL is lower triangular: only k >= j counts) */
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = j; i < n; ++i) {
+            double s = 0.0;
+            for (int64_t k = i; k < n; ++k)
+                s = s + AT(L, lda, k, i) * AT(GL, ldgl, k, j);
+            AT(P, n, i, j) = (i == j) ? 0.5 * s : s;
+        }
+    /* Y = P L^{-1}: each row y of P solves y L = p, i.e. L^T y^T = p^T
+     * (back substitution on the row) */
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < n; ++r) {
+        for (int64_t c = n - 1; c >= 0; --c) {
+            double v = AT(P, n, r, c);
+            for (int64_t k = c + 1; k < n; ++k)
+                v = v - AT(P, n, r, k) * AT(L, lda, k, c);
+            AT(P, n, r, c) = v / AT(L, lda, c, c);
+        }
+    }
+    /* S = L^{-T} Y: each column solved by back substitution with L^T */
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c)
+        trsv_lower_trans(n, L, lda, &AT(P, n, 0, c));
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) {
+            double v;
+            if (mode == 0)
+                v = 0.5 * (AT(P, n, i, j) + AT(P, n, j, i));
+            else if (i > j)
+                v = AT(P, n, i, j) + AT(P, n, j, i);
+            else if (i == j)
+                v = AT(P, n, i, i);
+            else
+                continue;
+            AT(GA, ldga, i, j) = v;
+        }
+    free(P);
 }
 
 int or_num_threads(void)

@@ -361,6 +361,99 @@ def test_planted_mistakes_are_caught():
             assert not np.array_equal(chol(A, v), L0)
 
 
+# ------------------------------------------------------ Cholesky adjoint
+# Gradient with respect to A of f(L), L = chol(A), given gL = df/dL (Murray
+# 2016; the paper is silent).  Pins: central differences of the oracle's own
+# (independently pinned) factor over every symmetric direction, the diagonal
+# closed form derived by hand below, exact power-of-two scaling, symmetry and
+# the relation between the two modes.
+def _chol_loss(orc, A, W):
+    L, info = orc.potrf(A)
+    assert info == 0
+    return float(np.sum(np.tril(W) * L))
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 12])
+def test_potrf_backward_central_differences(orc, n):
+    A = synth.gram_spd(n, 40 + n)
+    W = synth.normal((n, n), 41 + n)
+    L, _ = orc.potrf(A)
+    g0 = orc.potrf_backward(L, W, mode=0)
+    g1 = orc.potrf_backward(L, W, mode=1)
+    assert np.array_equal(g0, g0.T)
+    h = 1e-6
+    for i in range(n):
+        for j in range(i + 1):
+            E = np.zeros((n, n))
+            E[i, j] = E[j, i] = 1.0
+            fd = (_chol_loss(orc, A + h * E, W) - _chol_loss(orc, A - h * E, W)) / (2 * h)
+            assert np.sum(g0 * E) == pytest.approx(fd, rel=1e-6, abs=1e-8), (i, j)
+            # mode 1: derivative with respect to the lower entry (i, j), which
+            # the symmetric input carries at (i, j) and (j, i)
+            assert g1[i, j] == pytest.approx(fd, rel=1e-6, abs=1e-8), (i, j)
+    assert np.all(g1[np.triu_indices(n, 1)] == 0)
+
+
+def test_potrf_backward_diagonal_closed_form(orc):
+    """A = diag(d): to first order chol(A + dA) = diag(sqrt d) + dL with
+    dL_jj = dA_jj / (2 sqrt d_j) and dL_ij = dA_ij / sqrt d_j (i > j), so
+    df = sum_j gL_jj dA_jj / (2 sqrt d_j) + sum_{i>j} gL_ij dA_ij / sqrt d_j
+    and the symmetric gradient is gA_jj = gL_jj / (2 sqrt d_j),
+    gA_ij = gA_ji = gL_ij / (2 sqrt d_j)."""
+    n = 9
+    d = 4.0 ** np.arange(-3, n - 3)                   # exact square roots
+    W = np.tril(synth.normal((n, n), 7))
+    L, _ = orc.potrf(np.diag(d))
+    g = orc.potrf_backward(L, W, mode=0)
+    sq = np.sqrt(d)
+    want = np.zeros((n, n))
+    for i in range(n):
+        for j in range(i + 1):
+            want[i, j] = want[j, i] = W[i, j] / (2 * sq[j])
+    assert np.allclose(g, want, rtol=4e-16, atol=0)
+    # 1 x 1: d sqrt(a) / da = 1 / (2 sqrt(a))
+    g1 = orc.potrf_backward(np.array([[3.0]]), np.array([[5.0]]))
+    assert g1[0, 0] == pytest.approx(5.0 / 6.0, rel=1e-15)
+
+
+def test_potrf_backward_power_of_two_scaling(orc):
+    """chol(4 A) = 2 chol(A), so f(4 A) = 2 f(A) and the gradient at 4 A is
+    the gradient at A halved, bit for bit (every intermediate scales by a
+    power of two)."""
+    n = 10
+    A = synth.gram_spd(n, 8)
+    W = synth.normal((n, n), 9)
+    L, _ = orc.potrf(A)
+    L4, _ = orc.potrf(4.0 * A)
+    assert np.array_equal(L4, 2.0 * L)
+    assert np.array_equal(orc.potrf_backward(L4, W), orc.potrf_backward(L, W) / 2.0)
+
+
+def test_potrf_backward_planted_mistakes_are_caught(orc):
+    """Plausible slips in the adjoint (no halving of the diagonal in Phi,
+    gL^T L instead of L^T gL, a missing symmetrisation) each break one of the
+    pins above.  Implemented on a throw-away numpy copy, never the oracle."""
+    def adj(L, W, variant):
+        W = np.tril(W)
+        M = W.T @ L if variant == "transpose" else L.T @ W
+        P = np.tril(M)
+        if variant != "no_half":
+            P[np.diag_indices_from(P)] *= 0.5
+        Li = np.linalg.inv(L)
+        S = Li.T @ P @ Li
+        return S if variant == "no_sym" else 0.5 * (S + S.T)
+    n = 8
+    A = synth.gram_spd(n, 21)
+    W = synth.normal((n, n), 22)
+    L, _ = orc.potrf(A)
+    ref = orc.potrf_backward(L, W)
+    assert np.allclose(adj(L, W, "ok"), ref, rtol=1e-12, atol=1e-12)
+    assert not np.allclose(adj(L, W, "no_half"), ref, rtol=1e-6)
+    assert not np.allclose(adj(L, W, "transpose"), ref, rtol=1e-6)
+    g = adj(L, W, "no_sym")
+    assert not np.array_equal(g, g.T)
+
+
 # ---------------------------------------------------------------- GP likelihood
 # The paper (Research Impact Statement, "Scientific applications", Cholesky
 # solve) defines log L = -1/2 r^T A^{-1} r - 1/2 log det A - N/2 log(2 pi),
