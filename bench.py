@@ -337,6 +337,31 @@ def bench_batched(torch, mg, synth, dtype, reps: int = 10, seed: int = 2026):
         if r >= 2:
             times.append(e0.elapsed_time(e1))
     ms = _median(times)
+    # adjoint of the same solve (mg_posv_batched_backward) from its factors
+    # and solutions, upstream gradient ~ N(0,1): one launch
+    G = torch.randn(int(boffs[-1]), generator=gen, device=dev, dtype=torch.float64).to(dtype)
+    GB = torch.empty_like(G)
+    GA = torch.empty(int(offs[-1]), dtype=dtype, device=dev)
+    gp = torch.tensor([G.data_ptr() + int(o) * es for o in boffs[:-1]], dtype=torch.int64, device=dev)
+    gbp = torch.tensor([GB.data_ptr() + int(o) * es for o in boffs[:-1]], dtype=torch.int64, device=dev)
+    gap = torch.tensor([GA.data_ptr() + int(o) * es for o in offs[:-1]], dtype=torch.int64, device=dev)
+    from paper_2601_14466_amd import _lib
+    btimes = []
+    for r in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _lib.call("mg_posv_batched_backward", mg.handle().sync_stream(), plan.p, _p(ap), _p(ld), _p(bp), _p(ld),
+                  _p(gp), _p(ld), _p(gbp), _p(ld), _p(gap), _p(ld), _lib.MG_GRAD_SYM, _p(info))
+        e1.record()
+        torch.cuda.synchronize()
+        if r >= 1:
+            btimes.append(e0.elapsed_time(e1))
+    bms = _median(btimes)
+    bbytes = sum(k * (k + 1) // 2 + k * k + 3 * k for k in sizes) * es   # read L, write gA, vectors
+    backward = dict(ms=round(bms, 4), bad=int((~torch.isfinite(GA)).sum()),
+                    roofline=roofline_obj("k_batched_backward (one launch)",
+                                          sum(6.0 * k * k for k in sizes), bbytes, bms, 1,
+                                          FP64_PEAK_TFLOPS if dtype == torch.float64 else FP32_PEAK_TFLOPS))
     flops = sum(nominal_flops(k, 1) for k in sizes)
     # each system's lower triangle read and L written over it, b read and x written
     nbytes = sum(k * (k + 1) + 2 * k for k in sizes) * es
@@ -344,8 +369,9 @@ def bench_batched(torch, mg, synth, dtype, reps: int = 10, seed: int = 2026):
     out = dict(dtype="f64" if dtype == torch.float64 else "f32", batch=len(sizes), ms=round(ms, 4),
                systems_per_s=round(len(sizes) / (ms / 1e3), 1), tflops=round(flops / (ms / 1e3) / 1e12, 3),
                info_nonzero=int((info != 0).sum()), plan=plan.info(),
-               roofline=roofline_obj("k_batched_posv (one replay)", flops, nbytes, ms, 1, peak))
-    del plan, A, B, A0, B0
+               roofline=roofline_obj("k_batched_posv (one replay)", flops, nbytes, ms, 1, peak),
+               backward=backward)
+    del plan, A, B, A0, B0, G, GB, GA
     torch.cuda.empty_cache()
     return out
 
@@ -393,6 +419,38 @@ def bench_adjoint(torch, mg, synth, n: int = 8192, nrhs: int = 64, reps: int = 5
     return dict(n=n, nrhs=nrhs, forward_ms=round(f, 3), backward_ms=round(b, 3),
                 forward_tflops=round(nominal_flops(n, nrhs) / (f / 1e3) / 1e12, 3),
                 backward_tflops=round(bflops / (b / 1e3) / 1e12, 3), info=int(info), roofline=roof)
+
+
+def bench_potrf_backward(torch, mg, synth, n: int = 8192, reps: int = 3, seed: int = 8300):
+    """Adjoint of the factorisation itself (mg_potrf_backward) at n = 8192:
+    P = Phi(L^T gL), two backward sweeps with n right-hand sides, the
+    symmetrisation.  TF/s counts n^3/3 + 2 n^3."""
+    from paper_2601_14466_amd import _lib
+    A = synth.torch_gram_spd(n, seed)
+    L, info = mg.potrf(A)
+    Lc = L.T.contiguous() if not L.T.is_contiguous() else L.T
+    Gc = synth.torch_normal((n, n), seed + 1)        # only its lower triangle is read
+    gA = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    h = mg.handle()
+    wb = ctypes.c_size_t()
+    _lib.call("mg_potrf_backward_buffer_size", h.h, n, ctypes.byref(wb))
+    work = torch.empty(max(1, wb.value), dtype=torch.uint8, device=A.device)
+    ts = []
+    for r in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _lib.call("mg_potrf_backward", h.sync_stream(), n, _p(Lc), n, _p(Gc), n, _p(gA), n, _lib.MG_GRAD_SYM,
+                  _p(work), wb.value, _p(info))
+        e1.record()
+        torch.cuda.synchronize()
+        if r >= 1:
+            ts.append(e0.elapsed_time(e1))
+    t = _median(ts)
+    fl = n ** 3 / 3 + 2.0 * n ** 3
+    out = dict(n=n, ms=round(t, 3), tflops=round(fl / (t / 1e3) / 1e12, 3), info=int(info))
+    del A, L, Lc, Gc, gA, work
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_gp(torch, mg, synth, n: int = 16384, nrhs: int = 1, reps: int = 3, seed: int = 7700):
@@ -516,6 +574,7 @@ def cpu_library_context(torch, synth, n: int = 8192, nrhs: int = 16, reps: int =
 
 
 LEGS = ("mixed_fp32", "mixed_bf16", "mixed_fp32_n65536", "small_n1024", "batched_f64", "batched_f32", "adjoint_n8192",
+        "potrf_backward_n8192",
         "fp64_n8192", "fp64_n16384", "gp_loglik_n16384", "gp_loglik_grad_n4096")
 
 
@@ -534,6 +593,8 @@ def run_extra(key, torch, mg, synth, args):
         return bench_batched(torch, mg, synth, torch.float32)
     if key == "adjoint_n8192":
         return bench_adjoint(torch, mg, synth)
+    if key == "potrf_backward_n8192":
+        return bench_potrf_backward(torch, mg, synth)
     if key in ("fp64_n8192", "fp64_n16384"):
         n = int(key.split("_n")[1])
         r = bench_fp64(torch, mg, synth, n, 16, 5, 2)

@@ -283,16 +283,49 @@ mg_status mg_posv_backward(mg_handle_t handle, int64_t n, int64_t nrhs, const do
                            int32_t *info);
 
 /*
+ * Adjoint of the Cholesky factorisation itself (for callers that use L or
+ * log det directly): given gL = df/dL for L = chol(A), the gradient of f with
+ * respect to A.  The paper places the solver inside differentiable programs
+ * ("Statement of need") without stating this adjoint; from A = L L^T,
+ * dL = L Phi(L^{-1} dA L^{-T}) with Phi = lower triangle, diagonal halved,
+ * so df = <S, dA> with S = L^{-T} Phi(L^T gL) L^{-1} (Murray 2016):
+ *   MG_GRAD_SYM   : gA = (S + S^T)/2, full n x n symmetric;
+ *   MG_GRAD_LOWER : gradient with respect to the lower-triangle entries:
+ *                   S_ij + S_ji for i > j, S_ii on the diagonal; the strict
+ *                   upper triangle of gA is not written.
+ * FP64.  L: lda x n factor from mg_potrf (lower triangle read).  gL: ldgl x n,
+ * only its lower triangle is read.  gA: ldga x n output (also used as
+ * scratch: every entry of its n x n block may be written).  work: device
+ * scratch of mg_potrf_backward_buffer_size bytes (an n x n FP64 matrix and
+ * the sweep words).  The two triangular solves it performs (n right-hand
+ * sides each) follow mg_set_solve_mode.  info: optional device int32 of the
+ * factorisation, in/out; when it is non-zero the entries of gA the mode
+ * writes are NaN; a sweep that gives up sets it to MG_INFO_SOLVE_ABORTED
+ * (with the same NaN outputs).
+ * Errors: -1 handle, -2 n < 0, -3 L, -4 lda, -5 gL, -6 ldgl, -7 gA, -8 ldga,
+ *         -9 mode, -10 work NULL, -11 work too small.
+ */
+mg_status mg_potrf_backward_buffer_size(mg_handle_t handle, int64_t n, size_t *bytes);
+mg_status mg_potrf_backward(mg_handle_t handle, int64_t n, const double *L, int64_t lda, const double *gL,
+                            int64_t ldgl, double *gA, int64_t ldga, mg_grad_mode mode, void *work,
+                            size_t work_bytes, int32_t *info);
+
+/*
  * Batched posv: many independent SPD systems of uneven order (0..512) solved
  * in one persistent launch replayed from a HIP graph.  The paper's operation
  * applied to a batch (it has no batched form).  A plan fixes the orders, the
  * number of right-hand sides (1..8) and the launch shape:
  *   - the systems are taken longest first (or in input order) from an atomic
  *     counter by a persistent grid of grid_per_cu workgroups per CU;
- *   - with autotune on (the default) the plan times the candidate launch
- *     shapes on synthetic systems of the same orders once and keeps the
- *     fastest; results are cached by (architecture, dtype, nrhs, batch, order
- *     histogram) in cache_path (NULL: no cache file);
+ *   - two kernel variants: four waves per system (one workgroup per
+ *     system, up to three per CU), or eight waves per system with each
+ *     block column's tiles and their earlier-column products spread over
+ *     the waves (shorter per-system latency, one or two per CU);
+ *   - with autotune on (the default) the plan times the candidates
+ *     (variant x workgroups per CU x queue order) on synthetic systems of
+ *     the same orders once and keeps the fastest; results are cached by
+ *     (architecture, dtype, nrhs, batch, order histogram) in cache_path
+ *     (NULL: no cache file);
  *   - the graph holds a counter reset and the persistent kernel; each call
  *     copies the caller's pointer/leading-dimension arrays into the plan.
  * Plan creation allocates device memory (descriptor arrays, tuning inputs);
@@ -301,16 +334,20 @@ mg_status mg_posv_backward(mg_handle_t handle, int64_t n, int64_t nrhs, const do
 typedef struct mg_batch_plan_s *mg_batch_plan_t;
 typedef struct {
     int32_t autotune;     /* 1: time the candidates (default), 0: use the fields below */
-    int32_t grid_per_cu;  /* workgroups per CU (1..8; the autotuner tries 1 to 3); 0 = default */
+    int32_t grid_per_cu;  /* workgroups per CU (1..8; the autotuner tries 1 to 3, or 1 to 2 for variant 1); 0 = default */
     int32_t order;        /* 0 longest first, 1 input order, -1 default */
     const char *cache_path;  /* tuning cache file or NULL */
+    int32_t variant;      /* kernel: 0 four waves per system, 1 eight waves (the work of each
+                             block column spread over them), -1 default (0) */
 } mg_tune_opts;
 /* Errors: -1 handle, -2 dtype, -3 batch < 0, -4 n_host NULL or an order
  * outside [0, 512], -5 nrhs outside [1, 8], -7 plan NULL. */
 mg_status mg_batch_plan_create(mg_handle_t handle, mg_dtype dtype, int32_t batch, const int64_t *n_host,
                                int32_t nrhs, const mg_tune_opts *opts, mg_batch_plan_t *plan);
-/* Chosen launch shape and the tuned replay time (ms, -1 if not tuned).  Errors: -1 NULL plan. */
-mg_status mg_batch_plan_info(mg_batch_plan_t plan, int32_t *grid_per_cu, int32_t *order, double *tuned_ms);
+/* Chosen kernel variant, launch shape and the tuned replay time (ms, -1 if
+ * not tuned); NULL outputs are skipped.  Errors: -1 NULL plan. */
+mg_status mg_batch_plan_info(mg_batch_plan_t plan, int32_t *grid_per_cu, int32_t *order, double *tuned_ms,
+                             int32_t *variant);
 /*
  * Solve every system: A_dev[k] (device pointer, lda_dev[k] x n_k, lower
  * triangle, overwritten by L_k) and B_dev[k] (ldb_dev[k] x nrhs, overwritten
@@ -322,6 +359,29 @@ mg_status mg_batch_plan_info(mg_batch_plan_t plan, int32_t *grid_per_cu, int32_t
  */
 mg_status mg_posv_batched(mg_handle_t handle, mg_batch_plan_t plan, void *const *A_dev, const int64_t *lda_dev,
                           void *const *B_dev, const int64_t *ldb_dev, int32_t *info_dev);
+/*
+ * Adjoint of mg_posv_batched (reverse mode, every system at once; the paper
+ * has no batched form, the per-system adjoint is mg_posv_backward's): for
+ * system k, from its factor L_k (as mg_posv_batched left it in A_k), its
+ * solution X_k and the upstream gradient gX_k,
+ *   gB_k = A_k^{-1} gX_k,
+ *   MG_GRAD_SYM   : gA_k = -1/2 (gB_k X_k^T + X_k gB_k^T), full n_k x n_k;
+ *   MG_GRAD_LOWER : the gradient with respect to the lower-triangle
+ *                   entries (strict upper triangle of gA_k not written).
+ * Every argument from L_dev on is a DEVICE array of length batch (pointers,
+ * leading dimensions >= n_k, info); the orders, nrhs and dtype are the
+ * plan's.  info_dev: the forward call's per-system info; a non-zero entry
+ * gives NaN in gB_k and in the entries of gA_k the mode writes.  One
+ * persistent launch on the handle's stream (no graph, no host
+ * synchronisation, nothing allocated).
+ * Errors: -1 handle, -2 plan, -3..-12 NULL arrays (L, ldl, X, ldx, gX,
+ * ldgx, gB, ldgb, gA, ldga), -15 mode, -16 info_dev NULL.
+ */
+mg_status mg_posv_batched_backward(mg_handle_t handle, mg_batch_plan_t plan, const void *const *L_dev,
+                                   const int64_t *ldl_dev, const void *const *X_dev, const int64_t *ldx_dev,
+                                   const void *const *gX_dev, const int64_t *ldgx_dev, void *const *gB_dev,
+                                   const int64_t *ldgb_dev, void *const *gA_dev, const int64_t *ldga_dev,
+                                   mg_grad_mode mode, const int32_t *info_dev);
 /* Release a plan (NULL accepted). */
 mg_status mg_batch_plan_destroy(mg_batch_plan_t plan);
 

@@ -19,7 +19,7 @@ from . import _lib
 from ._lib import MgError, call, load, raw  # noqa: F401
 
 __all__ = [
-    "Handle", "handle", "potrf", "potrs", "posv", "posv_noalloc", "posv_mixed", "posv_backward", "PosvFunction", "BatchPlan",
+    "Handle", "handle", "potrf", "potrs", "posv", "posv_noalloc", "posv_mixed", "posv_backward", "potrf_backward", "PosvFunction", "CholeskyFunction", "BatchPlan",
     "posv_batched", "logdet", "gp_loglik", "gp_loglik_grad", "GPLogLik", "colmajor",
     "MgError", "load", "call", "raw",
 ]
@@ -344,6 +344,58 @@ def posv_backward(L, X, gX, mode: str = "sym", info=None):
     return (gBv.reshape(n) if flat else gBv), gA.T
 
 
+def potrf_backward(L, gL, info=None, mode: str = "sym"):
+    """Gradient with respect to A of f(L), L = chol(A), from gL = df/dL (only
+    its lower triangle is read): mode "sym" returns the full symmetric
+    gradient (S + S^T)/2, S = L^{-T} Phi(L^T gL) L^{-1}; "lower" the gradient
+    with respect to the lower-triangle entries (strict upper part 0).  NaN
+    when ``info`` (the factor's) is non-zero."""
+    torch = _torch()
+    _check_cuda(L, gL)
+    if L.dtype != torch.float64 or gL.dtype != torch.float64:
+        raise TypeError("potrf_backward takes FP64 L and gL")
+    n = L.shape[0]
+    h = handle()
+    Lc = colmajor(L)
+    Gc = colmajor(gL)
+    gA = torch.zeros((n, n), dtype=torch.float64, device=L.device)   # column-major buffer
+    wb = ctypes.c_size_t()
+    call("mg_potrf_backward_buffer_size", h.h, n, ctypes.byref(wb))
+    work = torch.empty(max(1, wb.value), dtype=torch.uint8, device=L.device)
+    m = {"sym": _lib.MG_GRAD_SYM, "lower": _lib.MG_GRAD_LOWER}[mode]
+    call("mg_potrf_backward", h.h, n, _ptr(Lc), max(1, n), _ptr(Gc), max(1, n), _ptr(gA), max(1, n), m,
+         _ptr(work), wb.value, _ptr(info) if info is not None else None)
+    return gA.T
+
+
+def _make_cholesky_function():
+    torch = _torch()
+
+    class CholeskyFunction(torch.autograd.Function):
+        """L = chol(A) (lower, zeros above) with the hand-written adjoint of
+        mg_potrf_backward.  ``CholeskyFunction.apply(A, mode)``: mode "sym"
+        (default) gives the symmetric gradient; "lower" the derivative with
+        respect to the entries the factorisation reads (for gradcheck of a
+        function of A's lower triangle).  NaN gradients when A is not
+        positive definite."""
+
+        @staticmethod
+        def forward(ctx, A, mode="sym"):
+            L, info = potrf(A)
+            L = torch.tril(L)
+            L.masked_fill_(info != 0, float("nan"))
+            ctx.save_for_backward(L, info)
+            ctx.mode = mode
+            return L
+
+        @staticmethod
+        def backward(ctx, gL):
+            L, info = ctx.saved_tensors
+            return potrf_backward(L, gL.contiguous(), info=info.clone(), mode=ctx.mode), None
+
+    return CholeskyFunction
+
+
 def _make_posv_function():
     torch = _torch()
 
@@ -416,6 +468,7 @@ class _LazyFunction:
 
 PosvFunction = _LazyFunction(_make_posv_function)
 GPLogLik = _LazyFunction(_make_gp_function)
+CholeskyFunction = _LazyFunction(_make_cholesky_function)
 
 
 class BatchPlan:
@@ -424,7 +477,7 @@ class BatchPlan:
     replayed from a HIP graph on every solve."""
 
     def __init__(self, sizes, nrhs: int = 1, dtype=None, autotune: bool = True, grid_per_cu: int = 0,
-                 order: int = -1, cache_path: str | None = None):
+                 order: int = -1, cache_path: str | None = None, variant: int = -1):
         torch = _torch()
         import numpy as np
         self.dtype = dtype or torch.float64
@@ -432,23 +485,25 @@ class BatchPlan:
         self.nrhs = int(nrhs)
         self.h = handle()
         self._cache = cache_path.encode() if cache_path else None
-        opts = _lib.TuneOpts(1 if autotune else 0, int(grid_per_cu), int(order), self._cache)
+        opts = _lib.TuneOpts(1 if autotune else 0, int(grid_per_cu), int(order), self._cache, int(variant))
         p = ctypes.c_void_p()
         call("mg_batch_plan_create", self.h.h, _dtype_code(torch.empty(0, dtype=self.dtype)), len(self.sizes),
              self.sizes.ctypes.data_as(ctypes.c_void_p), self.nrhs, ctypes.byref(opts), ctypes.byref(p))
         self.p = p
 
     def info(self):
-        g, o, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
-        call("mg_batch_plan_info", self.p, ctypes.byref(g), ctypes.byref(o), ctypes.byref(t))
-        return dict(grid_per_cu=g.value, order=o.value, tuned_ms=t.value)
+        g, o, t, v = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32()
+        call("mg_batch_plan_info", self.p, ctypes.byref(g), ctypes.byref(o), ctypes.byref(t), ctypes.byref(v))
+        return dict(variant=v.value, grid_per_cu=g.value, order=o.value, tuned_ms=t.value)
 
     def solve_raw(self, A_ptrs, lda, B_ptrs, ldb, info):
         """Device int64 tensors of pointers / leading dimensions, int32 info."""
         call("mg_posv_batched", handle().h, self.p, _ptr(A_ptrs), _ptr(lda), _ptr(B_ptrs), _ptr(ldb), _ptr(info))
 
-    def solve(self, As, Bs):
-        """Solve every A_k X_k = B_k; returns (list of X_k, int32 info tensor)."""
+    def solve(self, As, Bs, return_factors: bool = False):
+        """Solve every A_k X_k = B_k; returns (list of X_k, int32 info tensor),
+        and with ``return_factors`` also the list of factors L_k (lower
+        triangle significant) that ``backward`` takes."""
         torch = _torch()
         dev = As[0].device if len(As) else torch.device("cuda")
         Ab = [a.T.clone(memory_format=torch.contiguous_format) for a in As]
@@ -459,7 +514,32 @@ class BatchPlan:
         info = torch.zeros(len(As), dtype=torch.int32, device=dev)
         self.solve_raw(ap, ld, bp, ld, info)
         torch.cuda.current_stream().synchronize()
+        if return_factors:
+            return [x.T for x in Xb], info, [a.T for a in Ab]
         return [x.T for x in Xb], info
+
+    def backward(self, Ls, Xs, GXs, info, mode: str = "sym"):
+        """Adjoint of the batched solve (mg_posv_batched_backward): from the
+        factors L_k and solutions X_k of ``solve`` and upstream gradients
+        gX_k, returns (list of gB_k = A_k^{-1} gX_k, list of gA_k), gA_k the
+        symmetric -1/2 (gB X^T + X gB^T) ("sym") or the lower-triangle
+        gradient ("lower"; strict upper part 0).  NaN for systems whose
+        info is non-zero."""
+        torch = _torch()
+        dev = Ls[0].device if len(Ls) else torch.device("cuda")
+        Lc = [colmajor(t) for t in Ls]
+        Xc = [colmajor(x.reshape(x.shape[0], -1)) for x in Xs]
+        Gc = [colmajor(gx.reshape(gx.shape[0], -1)) for gx in GXs]
+        GB = [torch.empty_like(x) for x in Xc]
+        GA = [torch.zeros((int(t.shape[0]), int(t.shape[0])), dtype=t.dtype, device=dev) for t in Ls]
+        P = lambda ts: torch.tensor([t.data_ptr() for t in ts], dtype=torch.int64, device=dev)
+        ld = torch.tensor([max(1, int(t.shape[0])) for t in Ls], dtype=torch.int64, device=dev)
+        m = {"sym": _lib.MG_GRAD_SYM, "lower": _lib.MG_GRAD_LOWER}[mode]
+        ptrs = [P(Lc), P(Xc), P(Gc), P(GB), P(GA)]
+        call("mg_posv_batched_backward", handle().h, self.p, _ptr(ptrs[0]), _ptr(ld), _ptr(ptrs[1]), _ptr(ld),
+             _ptr(ptrs[2]), _ptr(ld), _ptr(ptrs[3]), _ptr(ld), _ptr(ptrs[4]), _ptr(ld), m, _ptr(info))
+        torch.cuda.current_stream().synchronize()
+        return [g.T for g in GB], [g.T for g in GA]
 
     def __del__(self):
         try:

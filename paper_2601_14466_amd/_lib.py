@@ -61,9 +61,13 @@ SIGNATURES = {
     "mg_posv_mixed_buffer_size": (i32, [vp, i32, i64, i64, i32, ctypes.POINTER(sz)]),
     "mg_posv_mixed": (i32, [vp, i32, i64, i64, vp, i64, vp, i64, vp, i64, vp, vp, sz, vp, vp]),
     "mg_posv_backward": (i32, [vp, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]),
+    "mg_potrf_backward_buffer_size": (i32, [vp, i64, ctypes.POINTER(sz)]),
+    "mg_potrf_backward": (i32, [vp, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]),
     "mg_batch_plan_create": (i32, [vp, i32, i32, vp, i32, vp, ctypes.POINTER(vp)]),
-    "mg_batch_plan_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
+    "mg_batch_plan_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(dbl),
+                                 ctypes.POINTER(i32)]),
     "mg_posv_batched": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+    "mg_posv_batched_backward": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp]),
     "mg_batch_plan_destroy": (i32, [vp]),
     "mg_logdet": (i32, [vp, i32, i64, vp, i64, vp, vp]),
     "mg_gp_loglik_buffer_size": (i32, [vp, i64, i64, ctypes.POINTER(sz)]),
@@ -89,7 +93,7 @@ class IrResult(ctypes.Structure):
 
 class TuneOpts(ctypes.Structure):
     _fields_ = [("autotune", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("cache_path", ctypes.c_char_p)]
+                ("cache_path", ctypes.c_char_p), ("variant", ctypes.c_int32)]
 
 
 _lib = None

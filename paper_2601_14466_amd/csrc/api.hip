@@ -310,6 +310,33 @@ mg_status mg_posv_backward(mg_handle_t h, int64_t n, int64_t nrhs, const double*
     return posv_backward_impl(h, n, nrhs, L, lda, X, ldx, gX, ldgx, gB, ldgb, gA, ldga, (int)mode, work, info);
 }
 
+mg_status mg_potrf_backward_buffer_size(mg_handle_t h, int64_t n, size_t* bytes) {
+    if (!h) return -1;
+    if (n < 0) return -2;
+    if (!bytes) return -3;
+    *bytes = potrf_backward_work_bytes(n);
+    return MG_OK;
+}
+
+mg_status mg_potrf_backward(mg_handle_t h, int64_t n, const double* L, int64_t lda, const double* GL, int64_t ldgl,
+                            double* GA, int64_t ldga, mg_grad_mode mode, void* work, size_t work_bytes,
+                            int32_t* info) {
+    if (!h) return -1;
+    if (n < 0) return -2;
+    const int64_t ld1 = std::max<int64_t>(1, n);
+    if (!L && n > 0) return -3;
+    if (lda < ld1) return -4;
+    if (!GL && n > 0) return -5;
+    if (ldgl < ld1) return -6;
+    if (!GA && n > 0) return -7;
+    if (ldga < ld1) return -8;
+    if (mode != MG_GRAD_SYM && mode != MG_GRAD_LOWER) return -9;
+    const size_t need = potrf_backward_work_bytes(n);
+    if (need > 0 && !work) return -10;
+    if (work_bytes < need) return -11;
+    return potrf_backward_impl(h, n, L, lda, GL, ldgl, GA, ldga, (int)mode, work, info);
+}
+
 mg_status mg_logdet(mg_handle_t h, mg_dtype dt, int64_t n, const void* L, int64_t lda, double* out,
                     const int32_t* info) {
     if (!h) return -1;

@@ -62,11 +62,19 @@ template <typename T>
 mg_status potrs_impl(mg_handle_t h, int64_t n, int64_t nrhs, const T* L, int64_t lda, T* B,
                      int64_t ldb, T* ywork, int32_t* info);
 size_t potrs_work_bytes(int64_t n, int64_t nrhs, int es);
+// Backward sweep alone: Out = L^{-T} In (In, Out distinct); words: sweep_words_bytes(nrhs) bytes.
+size_t sweep_words_bytes(int64_t nrhs);
+template <typename T>
+mg_status trsm_lt_impl(mg_handle_t h, int64_t n, int64_t nrhs, const T* L, int64_t lda, const T* In, int64_t ldi,
+                       T* Out, int64_t ldo, void* words, int32_t* info);
 size_t mixed_work_bytes(int64_t n, int64_t nrhs, int fallback, int lo);
 inline size_t bf16_panel_bytes(int64_t n) { return 3 * (size_t)n * 512 * 2; }
 mg_status posv_backward_impl(mg_handle_t h, int64_t n, int64_t nrhs, const double* L, int64_t lda,
                              const double* X, int64_t ldx, const double* GX, int64_t ldgx, double* GB,
                              int64_t ldgb, double* GA, int64_t ldga, int mode, void* work, int32_t* info);
+size_t potrf_backward_work_bytes(int64_t n);
+mg_status potrf_backward_impl(mg_handle_t h, int64_t n, const double* L, int64_t lda, const double* GL,
+                              int64_t ldgl, double* GA, int64_t ldga, int mode, void* work, int32_t* info);
 mg_status posv_mixed_impl(mg_handle_t h, int lo, int64_t n, int64_t nrhs, const double* A, int64_t lda,
                           const double* B, int64_t ldb, double* X, int64_t ldx, const mg_ir_opts* o, void* work,
                           mg_ir_result* res, int32_t* info);

@@ -455,6 +455,39 @@ mg_status potrs_impl(mg_handle_t h, int64_t n, int64_t nrhs, const T* L, int64_t
                     (nd * (nd + 1) + 4.0 * nd * (double)nrhs) * sizeof(T), st);
 }
 
+// Out = L^{-T} In alone (the backward sweep), In and Out distinct, nrhs
+// columns in passes of 16; sy: the pass words (sweep_words_bytes(nrhs)).
+// The sweep is followed by the give-up check (Out NaN and info =
+// MG_INFO_SOLVE_ABORTED when a wait gave up); skipped when *info != 0.
+size_t sweep_words_bytes(int64_t nrhs) { return align_up((size_t)sweep_passes(nrhs) * 16, 256); }
+
+template <typename T>
+mg_status trsm_lt_impl(mg_handle_t h, int64_t n, int64_t nrhs, const T* L, int64_t lda, const T* In, int64_t ldi,
+                       T* Out, int64_t ldo, void* words, int32_t* info) {
+    if (n == 0 || nrhs == 0) return MG_OK;
+    hipStream_t st = h->stream;
+    SweepSync* sy = (SweepSync*)words;
+    const int lim = h->spin_limit < 0 ? SWEEP_SPIN_LIMIT : h->spin_limit;
+    const int64_t np = sweep_passes(nrhs);
+    const dim3 grid((unsigned)cdiv(n, JB), (unsigned)np);
+    const unsigned gfill = (unsigned)std::min<int64_t>(std::max<int64_t>(1, cdiv(n * nrhs, 256)), 2048);
+    hipLaunchKernelGGL((k_sweep_init<T>), dim3(gfill), dim3(256), 0, st, Out, ldo, n, nrhs, sy, info);
+    MG_LAUNCH_CHECK();
+    if (h->solve_mode == MG_SOLVE_SUBSTITUTION)
+        hipLaunchKernelGGL((k_sweep<T, 1, false, false>), grid, dim3(256), 0, st, L, lda, n, nrhs, In, ldi, Out, ldo,
+                           sy, info, lim);
+    else
+        hipLaunchKernelGGL((k_sweep<T, 1, false, true>), grid, dim3(256), 0, st, L, lda, n, nrhs, In, ldi, Out, ldo,
+                           sy, info, lim);
+    MG_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_sweep_check<T>), dim3(1), dim3(256), 0, st, Out, ldo, n, nrhs, (const SweepSync*)sy,
+                       (int)np, info);
+    MG_LAUNCH_CHECK();
+    return MG_OK;
+}
+template mg_status trsm_lt_impl<double>(mg_handle_t, int64_t, int64_t, const double*, int64_t, const double*, int64_t,
+                                        double*, int64_t, void*, int32_t*);
+
 template mg_status potrs_impl<double>(mg_handle_t, int64_t, int64_t, const double*, int64_t, double*, int64_t,
                                       double*, int32_t*);
 template mg_status potrs_impl<float>(mg_handle_t, int64_t, int64_t, const float*, int64_t, float*, int64_t,

@@ -1,5 +1,6 @@
 """GPU parity of the batched uneven posv (one persistent, graph-replayed
-launch per call) against the oracle, system by system, through the C ABI.
+launch per call) against the oracle, system by system, through the C ABI,
+for both kernel variants (four or eight waves per system).
 
 Bars: FP64 eta <= 1e-12 per system; FP32 eta <= n_i * 2^-24 on the rounded
 data; integer-exact systems bitwise; a failing system reports its own info,
@@ -32,9 +33,10 @@ def _dev(list_np, dtype=torch.float64):
 SIZES = [1, 2, 7, 16, 17, 31, 64, 65, 100, 128, 255, 256, 257, 300, 400, 511, 512]
 
 
-def test_mixed_sizes_fp64(mg, orc):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_mixed_sizes_fp64(mg, orc, variant):
     As, xs, bs = synth.batch_systems(SIZES, seed=5)
-    plan = mg.BatchPlan(SIZES, nrhs=1, autotune=False)
+    plan = mg.BatchPlan(SIZES, nrhs=1, autotune=False, variant=variant)
     Xs, info = plan.solve(_dev(As), _dev(bs))
     assert int(info.abs().sum()) == 0
     for A, X, b in zip(As, Xs, bs):
@@ -42,7 +44,8 @@ def test_mixed_sizes_fp64(mg, orc):
         assert eta[0] <= 1e-12, (A.shape, eta)
 
 
-def test_integer_systems_bitwise_and_injected_failure(mg, orc):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_integer_systems_bitwise_and_injected_failure(mg, orc, variant):
     sizes = [33, 150, 300, 512, 90]
     As, xs, bs = [], [], []
     for k, n in enumerate(sizes):
@@ -54,7 +57,7 @@ def test_integer_systems_bitwise_and_injected_failure(mg, orc):
     bad = 3
     As[bad] = As[bad].copy()
     As[bad][200, 200] = -1e6            # leading minor 201 not positive definite
-    plan = mg.BatchPlan(sizes, nrhs=1, autotune=False)
+    plan = mg.BatchPlan(sizes, nrhs=1, autotune=False, variant=variant)
     Xs, info = plan.solve(_dev(As), _dev(bs))
     info = info.cpu().numpy()
     assert info[bad] == 201
@@ -65,12 +68,13 @@ def test_integer_systems_bitwise_and_injected_failure(mg, orc):
             assert np.array_equal(Xs[k].cpu().numpy(), xs[k])
 
 
-def test_fp32(mg, orc):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_fp32(mg, orc, variant):
     sizes = [20, 100, 256, 333, 512]
     As, xs, bs = synth.batch_systems(sizes, seed=9)
     As = [a.astype(np.float32).astype(np.float64) for a in As]
     bs = [b.astype(np.float32).astype(np.float64) for b in bs]
-    plan = mg.BatchPlan(sizes, nrhs=1, dtype=torch.float32, autotune=False)
+    plan = mg.BatchPlan(sizes, nrhs=1, dtype=torch.float32, autotune=False, variant=variant)
     Xs, info = plan.solve(_dev(As, torch.float32), _dev(bs, torch.float32))
     assert int(info.abs().sum()) == 0
     for A, X, b in zip(As, Xs, bs):
@@ -78,13 +82,14 @@ def test_fp32(mg, orc):
         assert eta[0] <= A.shape[0] * 2.0 ** -24, eta
 
 
-def test_permutation_invariance_and_replay(mg):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_permutation_invariance_and_replay(mg, variant):
     sizes = list(synth.batch_sizes(64, 3))
     As, xs, bs = synth.batch_systems(sizes, seed=4)
-    plan = mg.BatchPlan(sizes, nrhs=1, autotune=False)
+    plan = mg.BatchPlan(sizes, nrhs=1, autotune=False, variant=variant)
     X1, _ = plan.solve(_dev(As), _dev(bs))
     perm = synth.rng(5).permutation(len(sizes))
-    plan2 = mg.BatchPlan([sizes[k] for k in perm], nrhs=1, autotune=False)
+    plan2 = mg.BatchPlan([sizes[k] for k in perm], nrhs=1, autotune=False, variant=variant)
     X2, _ = plan2.solve(_dev([As[k] for k in perm]), _dev([bs[k] for k in perm]))
     for j, k in enumerate(perm):
         assert torch.equal(X2[j], X1[k])
@@ -94,10 +99,11 @@ def test_permutation_invariance_and_replay(mg):
         assert torch.equal(a, b)
 
 
-def test_multiple_rhs(mg, orc):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_multiple_rhs(mg, orc, variant):
     sizes = [40, 200, 512]
     As, xs, bs = synth.batch_systems(sizes, seed=12, nrhs=5)
-    plan = mg.BatchPlan(sizes, nrhs=5, autotune=False)
+    plan = mg.BatchPlan(sizes, nrhs=5, autotune=False, variant=variant)
     Xs, info = plan.solve(_dev(As), _dev(bs))
     assert int(info.abs().sum()) == 0
     for A, X, b in zip(As, Xs, bs):
@@ -110,6 +116,7 @@ def test_autotune_and_cache(mg, orc, tmp_path):
     plan = mg.BatchPlan(sizes, nrhs=1, autotune=True, cache_path=cache)
     inf = plan.info()
     assert inf["grid_per_cu"] in (1, 2, 3) and inf["order"] in (0, 1) and inf["tuned_ms"] > 0
+    assert inf["variant"] in (0, 1)
     assert os.path.exists(cache)
     plan2 = mg.BatchPlan(sizes, nrhs=1, autotune=True, cache_path=cache)
     assert plan2.info() == inf            # served from the cache
@@ -135,3 +142,38 @@ def test_full_config3(mg, orc, dtype):
         eta = orc.backward_error(A, X.double().cpu().numpy(), b)[0]
         bar = 1e-12 if dtype == torch.float64 else A.shape[0] * 2.0 ** -24
         assert eta <= bar, (A.shape, eta)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batched_backward_matches_oracle(mg, orc, dtype):
+    """Adjoint of the batched solve, system by system against the oracle's
+    posv_backward on the same factor and solution: gB and gA (both modes)
+    to 1e-12 relative (FP64) or n 2^-24 kappa-scaled (FP32); a failing
+    system gets NaN and leaves the others alone."""
+    sizes = [1, 16, 17, 100, 257, 512, 300]
+    As, xs, bs = synth.batch_systems(sizes, seed=31, nrhs=3)
+    bad = 4
+    As[bad] = As[bad].copy()
+    As[bad][100, 100] = -1e6
+    if dtype == torch.float32:
+        As = [a.astype(np.float32).astype(np.float64) for a in As]
+        bs = [b.astype(np.float32).astype(np.float64) for b in bs]
+    plan = mg.BatchPlan(sizes, nrhs=3, dtype=dtype, autotune=False)
+    Xs, info, Ls = plan.solve(_dev(As, dtype), _dev(bs, dtype), return_factors=True)
+    assert int(info[bad]) == 101
+    W = [synth.normal((n, 3), 40 + k) for k, n in enumerate(sizes)]
+    for mode, om in (("sym", 0), ("lower", 1)):
+        gBs, gAs = plan.backward(Ls, Xs, _dev(W, dtype), info, mode=mode)
+        for k, n in enumerate(sizes):
+            gb, ga = gBs[k].double().cpu().numpy(), gAs[k].double().cpu().numpy()
+            if k == bad:
+                assert np.isnan(gb).all() and np.isnan(ga[np.tril_indices(n)]).all()
+                continue
+            L = np.tril(Ls[k].double().cpu().numpy())
+            gB, gA = orc.posv_backward(L, Xs[k].double().cpu().numpy(), W[k], mode=om)
+            if mode == "lower":
+                assert np.all(ga[np.triu_indices(n, 1)] == 0)
+            tol = 1e-12 if dtype == torch.float64 else 64 * n * 2.0 ** -24 * np.linalg.cond(L) ** 2
+            for got, want in ((gb, gB), (ga, gA)):
+                err = np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300)
+                assert err <= tol, (mode, k, n, err)
