@@ -235,9 +235,13 @@ __global__ __launch_bounds__(256, 2) void k_sweep(const T* __restrict__ L, int64
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) acc[rt] = acc2[rt] = V4<T>{0, 0, 0, 0};
         // Software pipeline over the dependency blocks: the L values (per
-        // lane, one per k-step) and the solution values of block d + 1 are
-        // requested before block d is multiplied.
-        T lc[JB / 4], ln[JB / 4], xc[XPT], xn[XPT];
+        // lane, one per k-step) stream through a ring of LR blocks, requested
+        // LR - 1 blocks ahead (a workgroup's own stream of L is what limits a
+        // sweep: one block of prefetch kept it at a fifth of HBM bandwidth);
+        // the solution values of block d + 1 are requested before block d is
+        // multiplied.
+        constexpr int LR = 4;
+        T lr[LR][JB / 4], xc[XPT], xn[XPT];
         auto load_l = [&](T* dst, int d) {
             const int j = FWD ? d : nblk - 1 - d;
             const int64_t c0 = (int64_t)j * JB;
@@ -258,15 +262,17 @@ __global__ __launch_bounds__(256, 2) void k_sweep(const T* __restrict__ L, int64
                 dst[k] = (c < jbj && rc0 + q < nrhs) ? load_coherent(&Out[idx(c0 + c, rc0 + q, ldo)]) : (T)0;
             }
         };
-        if (ndep > 0) {
-            load_l(lc, 0);
-            load_x(xc, 0);
-        }
-        for (int d = 0; d < ndep; ++d) {
-            if (d + 1 < ndep) {
-                load_l(ln, d + 1);
-                load_x(xn, d + 1);
-            }
+#pragma unroll
+        for (int s = 0; s < LR - 1; ++s)
+            if (s < ndep) load_l(lr[s], s);
+        if (ndep > 0) load_x(xc, 0);
+        for (int d0 = 0; d0 < ndep; d0 += LR)
+#pragma unroll
+        for (int sl = 0; sl < LR; ++sl) {
+            const int d = d0 + sl;
+            if (d >= ndep) break;  // uniform
+            if (d + LR - 1 < ndep) load_l(lr[(sl + LR - 1) % LR], d + LR - 1);
+            if (d + 1 < ndep) load_x(xn, d + 1);
             // block d's solution into LDS, reloaded until every value is
             // written (the barrier that checks this also publishes the LDS)
             T* xs = Xs[d & 1];
@@ -310,12 +316,10 @@ __global__ __launch_bounds__(256, 2) void k_sweep(const T* __restrict__ L, int64
                 const int c = 4 * ks + g;
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt) {
-                    if (ks & 1) acc2[rt] = mma_xzt(acc2[rt], lc[ks], xs[c * XP + 16 * rt + i]);
-                    else acc[rt] = mma_xzt(acc[rt], lc[ks], xs[c * XP + 16 * rt + i]);
+                    if (ks & 1) acc2[rt] = mma_xzt(acc2[rt], lr[sl][ks], xs[c * XP + 16 * rt + i]);
+                    else acc[rt] = mma_xzt(acc[rt], lr[sl][ks], xs[c * XP + 16 * rt + i]);
                 }
             }
-#pragma unroll
-            for (int ks = 0; ks < JB / 4; ++ks) lc[ks] = ln[ks];
 #pragma unroll
             for (int k = 0; k < XPT; ++k) xc[k] = xn[k];
         }
