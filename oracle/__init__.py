@@ -30,6 +30,9 @@ optionally with log det):
 * ``posv_ir``   -- low-precision factor plus FP64 iterative refinement;
                    falls back to FP64 when it stalls.
 * ``posv_backward`` -- gB = A^{-1} gX, gA = -1/2 (gB X^T + X gB^T).
+* ``getrf`` / ``getrs`` / ``lu_solve`` -- the paper's general solve: P A = L U
+                   by partial pivoting (LAPACK ipiv convention), then the
+                   swaps, L y = P b and U x = y.
 * ``potrf_backward`` -- gradient with respect to A of f(chol(A)) from
                    gL = df/dL: sym(L^{-T} Phi(L^T gL) L^{-1}), Phi the lower
                    triangle with the diagonal halved (Murray 2016; the paper
@@ -105,6 +108,12 @@ def _load():
     lib.or_posv_backward.restype = None
     lib.or_potrf_backward.argtypes = [_i64, _dp, _i64, _dp, _i64, _dp, _i64, ctypes.c_int]
     lib.or_potrf_backward.restype = None
+    lib.or_getrf.argtypes = [_i64, _dp, _i64, ctypes.POINTER(ctypes.c_int32)]
+    lib.or_getrf.restype = _i64
+    lib.or_getrs.argtypes = [_i64, _i64, _dp, _i64, ctypes.POINTER(ctypes.c_int32), _dp, _i64]
+    lib.or_getrs.restype = None
+    lib.or_residual_gen.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64, _dp]
+    lib.or_residual_gen.restype = ctypes.c_double
     lib.or_num_threads.argtypes = []
     lib.or_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -258,6 +267,50 @@ def posv_backward(L, X, GX, mode: int = 0):
     lib.or_posv_backward(n, nrhs, _ptr(Lf), _ld(Lf), _ptr(Xf), _ld(Xf), _ptr(Gf), _ld(Gf),
                          _ptr(GB), _ld(GB), _ptr(GA), _ld(GA), int(mode))
     return (GB.ravel() if flat else GB), GA
+
+
+def getrf(A):
+    """Return (LU, ipiv, info): P A = L U by partial pivoting; LU holds the
+    unit lower L below the diagonal and U on and above it; ipiv[k] is the
+    1-based row swapped with row k (LAPACK convention)."""
+    lib = _load()
+    W = _f64(A).copy(order="F")
+    n = W.shape[0]
+    ipiv = np.zeros(max(1, n), dtype=np.int32)
+    info = lib.or_getrf(n, _ptr(W), _ld(W), ipiv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return W, ipiv[:n], int(info)
+
+
+def getrs(LU, ipiv, B):
+    """X with A X = B from getrf's LU and ipiv."""
+    lib = _load()
+    LUf = _f64(LU)
+    B2, flat = _as2d(B)
+    X = _f64(B2).copy(order="F")
+    n, nrhs = X.shape
+    piv = np.ascontiguousarray(np.asarray(ipiv, dtype=np.int32))
+    lib.or_getrs(n, nrhs, _ptr(LUf), _ld(LUf), piv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(X), _ld(X))
+    return X.ravel() if flat else X
+
+
+def lu_solve(A, B):
+    """Return (X, info) for a general A X = B (getrf then getrs)."""
+    LU, ipiv, info = getrf(A)
+    return getrs(LU, ipiv, B), info
+
+
+def backward_error_gen(A, X, B) -> np.ndarray:
+    """Per-column normwise backward error of a general system (extended
+    precision residual, |A|inf the largest row sum)."""
+    lib = _load()
+    Af = _f64(A)
+    X2, _ = _as2d(X)
+    B2, _ = _as2d(B)
+    Xf, Bf = _f64(X2), _f64(B2)
+    n, nrhs = Xf.shape
+    eta = np.zeros(nrhs, dtype=np.float64)
+    lib.or_residual_gen(n, nrhs, _ptr(Af), _ld(Af), _ptr(Xf), _ld(Xf), _ptr(Bf), _ld(Bf), _ptr(eta))
+    return eta
 
 
 def potrf_backward(L, GL, mode: int = 0):

@@ -41,6 +41,14 @@
  *   or_posv_backward: adjoint of X = A^{-1} B:  gB = A^{-1} gX and
  *                gA = -1/2 (gB X^T + X gB^T) (symmetric convention), or the
  *                gradient with respect to the lower-triangle parameters.
+ *   or_getrf / or_getrs: the paper's general solve (lu_solve): P A = L U by
+ *                Gaussian elimination with partial pivoting (column by
+ *                column: the row with the largest |entry| on or below the
+ *                diagonal, the first one on ties, is swapped into place;
+ *                L unit lower, U upper, stored over A; ipiv[k] = 1-based row
+ *                swapped with row k); info = first k whose pivot is exactly
+ *                zero (elimination goes on past it, as LAPACK's xGETRF).
+ *                getrs applies the swaps to B, then L y = P b, U x = y.
  *   or_potrf_backward: adjoint of L = chol(A) (the paper is silent; the
  *                result is Murray, "Differentiation of the Cholesky
  *                decomposition", 2016).  From A = L L^T,
@@ -592,6 +600,105 @@ void or_potrf_backward(int64_t n, const double *L, int64_t lda, const double *GL
             AT(GA, ldga, i, j) = v;
         }
     free(P);
+}
+
+int64_t or_getrf(int64_t n, double *A, int64_t lda, int32_t *ipiv)
+{
+    int64_t info = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t p = k;
+        double best = fabs(AT(A, lda, k, k));
+        for (int64_t i = k + 1; i < n; ++i)
+            if (fabs(AT(A, lda, i, k)) > best) {
+                best = fabs(AT(A, lda, i, k));
+                p = i;
+            }
+        ipiv[k] = (int32_t)(p + 1);
+        if (p != k)
+            for (int64_t j = 0; j < n; ++j) {
+                double t = AT(A, lda, k, j);
+                AT(A, lda, k, j) = AT(A, lda, p, j);
+                AT(A, lda, p, j) = t;
+            }
+        double piv = AT(A, lda, k, k);
+        if (piv == 0.0) {
+            if (info == 0)
+                info = k + 1;
+            continue;
+        }
+        for (int64_t i = k + 1; i < n; ++i)
+            AT(A, lda, i, k) = AT(A, lda, i, k) / piv;
+#pragma omp parallel for schedule(static) if ((n - k) * (n - k) > 65536)
+        for (int64_t j = k + 1; j < n; ++j) {
+            double ukj = AT(A, lda, k, j);
+            for (int64_t i = k + 1; i < n; ++i)
+                AT(A, lda, i, j) = AT(A, lda, i, j) - AT(A, lda, i, k) * ukj;
+        }
+    }
+    return info;
+}
+
+void or_getrs(int64_t n, int64_t nrhs, const double *LU, int64_t lda, const int32_t *ipiv,
+              double *B, int64_t ldb)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrhs; ++r) {
+        double *b = &AT(B, ldb, 0, r);
+        for (int64_t k = 0; k < n; ++k) {
+            int64_t p = ipiv[k] - 1;
+            if (p != k) {
+                double t = b[k];
+                b[k] = b[p];
+                b[p] = t;
+            }
+        }
+        for (int64_t i = 0; i < n; ++i) { /* L y = P b, L unit lower */
+            double v = b[i];
+            for (int64_t k = 0; k < i; ++k)
+                v = v - AT(LU, lda, i, k) * b[k];
+            b[i] = v;
+        }
+        for (int64_t i = n - 1; i >= 0; --i) { /* U x = y */
+            double v = b[i];
+            for (int64_t k = i + 1; k < n; ++k)
+                v = v - AT(LU, lda, i, k) * b[k];
+            b[i] = v / AT(LU, lda, i, i);
+        }
+    }
+}
+
+/* residual of a general (non-symmetric) system in extended precision:
+ * eta_j = |b_j - A x_j|inf / (|A|inf |x_j|inf + |b_j|inf), |A|inf the
+ * largest row sum of |A| */
+double or_residual_gen(int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                       const double *X, int64_t ldx, const double *B, int64_t ldb, double *eta)
+{
+    long double anorm = 0.0L;
+    for (int64_t i = 0; i < n; ++i) {
+        long double s = 0.0L;
+        for (int64_t j = 0; j < n; ++j)
+            s += fabsl((long double)AT(A, lda, i, j));
+        if (s > anorm)
+            anorm = s;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrhs; ++r) {
+        long double rmax = 0.0L, xmax = 0.0L, bmax = 0.0L;
+        for (int64_t i = 0; i < n; ++i) {
+            long double s = (long double)AT(B, ldb, i, r);
+            for (int64_t j = 0; j < n; ++j)
+                s -= (long double)AT(A, lda, i, j) * (long double)AT(X, ldx, j, r);
+            if (fabsl(s) > rmax)
+                rmax = fabsl(s);
+            if (fabsl((long double)AT(X, ldx, i, r)) > xmax)
+                xmax = fabsl((long double)AT(X, ldx, i, r));
+            if (fabsl((long double)AT(B, ldb, i, r)) > bmax)
+                bmax = fabsl((long double)AT(B, ldb, i, r));
+        }
+        long double den = anorm * xmax + bmax;
+        eta[r] = (double)(den > 0.0L ? rmax / den : 0.0L);
+    }
+    return (double)anorm;
 }
 
 int or_num_threads(void)

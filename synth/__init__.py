@@ -156,6 +156,31 @@ def integer_exact(n: int, seed: int, diag_choices=(1, 2, 4), offmax: int = 3):
     return L0.astype(np.float64), A.astype(np.float64)
 
 
+def lu_exact(n: int, seed: int):
+    """(perm, L0, U0, A) with A = P0^T L0 U0 for a general-solve pin: L0 unit
+    lower with entries in {-1/2, -1/4, 0, 1/4, 1/2}, U0 upper with integer
+    entries in [-3, 3] and a diagonal in {+-2, +-4, +-8}, P0 a random row
+    permutation (row i of L0 U0 is row perm[i] of A).  Every partial sum of
+    the elimination is a multiple of 1/4 far below 2^53 and every pivot a
+    power of two, and |L0| < 1 below the diagonal makes each pivot a strict
+    column maximum, so partial pivoting reproduces P0, L0 and U0 exactly."""
+    g = rng(seed)
+    L0 = np.tril(g.choice(np.array([-0.5, -0.25, 0.0, 0.25, 0.5]), size=(n, n)), -1) + np.eye(n)
+    U0 = np.triu(g.integers(-3, 4, size=(n, n)).astype(np.float64), 1)
+    U0[np.diag_indices(n)] = g.choice(np.array([-8.0, -4.0, -2.0, 2.0, 4.0, 8.0]), size=n)
+    perm = g.permutation(n)
+    M = L0 @ U0                       # exact: dyadic values of small magnitude
+    A = np.empty_like(M)
+    A[perm] = M
+    return perm, L0, U0, A
+
+
+def general_matrix(n: int, seed: int) -> np.ndarray:
+    """Dense general test matrix: i.i.d. N(0, 1) entries (well conditioned
+    with high probability at the sizes used), seeded."""
+    return rng(seed).standard_normal((n, n))
+
+
 def integer_vector(shape, seed: int, vmax: int = 3) -> np.ndarray:
     return rng(seed).integers(-vmax, vmax + 1, size=shape).astype(np.float64)
 

@@ -361,6 +361,100 @@ def test_planted_mistakes_are_caught():
             assert not np.array_equal(chol(A, v), L0)
 
 
+# ------------------------------------------------------ general solve (lu_solve)
+# The paper's general solve: P A = L U by partial pivoting, then the two
+# triangular solves ("Software design", lu_solve bullet).
+def _perm_from_ipiv(ipiv):
+    p = np.arange(len(ipiv))
+    for k, r in enumerate(ipiv):
+        p[[k, r - 1]] = p[[r - 1, k]]
+    return p
+
+
+def test_getrf_hand_worked_2x2(orc):
+    """A = [[1, 2], [4, 4]]: |4| > |1| so the rows swap (ipiv = [2, 2]);
+    l = 1/4, U = [[4, 4], [0, 2 - 4/4]] = [[4, 4], [0, 1]]."""
+    LU, ipiv, info = orc.getrf(np.array([[1.0, 2.0], [4.0, 4.0]]))
+    assert info == 0 and list(ipiv) == [2, 2]
+    assert np.array_equal(LU, np.array([[4.0, 4.0], [0.25, 1.0]]))
+    # x1 + 2 x2 = 5, 4 x1 + 4 x2 = 12  =>  x = (1, 2)
+    assert np.array_equal(orc.getrs(LU, ipiv, np.array([5.0, 12.0])), np.array([1.0, 2.0]))
+
+
+@pytest.mark.parametrize("n,seed", [(1, 1), (3, 2), (17, 3), (64, 4), (150, 5)])
+def test_getrf_dyadic_family_exact(orc, n, seed):
+    perm, L0, U0, A = synth.lu_exact(n, seed)
+    LU, ipiv, info = orc.getrf(A)
+    assert info == 0
+    assert np.array_equal(np.tril(LU, -1) + np.eye(n), L0)
+    assert np.array_equal(np.triu(LU), U0)
+    assert np.array_equal(_perm_from_ipiv(ipiv), perm)       # row k of P A is row perm[k] of A
+    xt = synth.integer_vector((n, 3), seed)
+    assert np.array_equal(orc.getrs(LU, ipiv, A @ xt), xt)
+
+
+def test_getrf_reconstruction_and_backward_error(orc):
+    n = 120
+    A = synth.general_matrix(n, 7)
+    LU, ipiv, info = orc.getrf(A)
+    L = np.tril(LU, -1) + np.eye(n)
+    U = np.triu(LU)
+    p = _perm_from_ipiv(ipiv)
+    assert np.linalg.norm(A[p] - L @ U) / np.linalg.norm(A) <= 8 * n * EPS
+    assert np.all(np.abs(np.tril(LU, -1)) <= 1.0)               # partial pivoting: |l| <= 1
+    xt = synth.normal((n, 4), 8)
+    B = A @ xt
+    X = orc.getrs(LU, ipiv, B)
+    assert np.all(orc.backward_error_gen(A, X, B) <= 4 * n * EPS)
+
+
+def test_getrf_matches_lapack_pivots(orc):
+    """Library cross-check: LAPACK dgetrf (scipy) picks the same pivots."""
+    from scipy.linalg import lu_factor
+    n = 80
+    A = synth.general_matrix(n, 9)
+    LU, ipiv, info = orc.getrf(A)
+    lu, piv = lu_factor(A)
+    assert np.array_equal(ipiv, piv + 1)
+    assert np.allclose(LU, lu, rtol=0, atol=1e-12 * np.abs(lu).max())
+
+
+def test_getrf_singular_info(orc):
+    """A zero pivot (here an all-zero column 3) is reported as info = 3 and
+    elimination continues (LAPACK semantics)."""
+    A = synth.general_matrix(6, 10)
+    A[:, 2] = 0.0
+    LU, ipiv, info = orc.getrf(A)
+    assert info == 3
+    assert np.all(np.isfinite(LU))
+
+
+def test_getrf_planted_mistakes_are_caught(orc):
+    """No pivoting, pivoting on the signed maximum, or an update that skips
+    the first column's multiplier each break a pin above (on a throw-away
+    numpy copy, never the oracle)."""
+    def lu(A, variant):
+        A = A.copy()
+        n = A.shape[0]
+        perm = np.arange(n)
+        for k in range(n):
+            col = A[k:, k]
+            p = k if variant == "no_pivot" else k + int(np.argmax(col if variant == "signed" else np.abs(col)))
+            A[[k, p]] = A[[p, k]]
+            perm[[k, p]] = perm[[p, k]]
+            A[k + 1:, k] /= A[k, k]
+            if not (variant == "skip" and k == 0):
+                A[k + 1:, k + 1:] -= np.outer(A[k + 1:, k], A[k, k + 1:])
+        return A, perm
+    perm, L0, U0, A = synth.lu_exact(30, 11)
+    ok, p_ok = lu(A, "ok")
+    assert np.array_equal(np.triu(ok), U0) and np.array_equal(p_ok, perm)
+    for v in ("no_pivot", "signed", "skip"):
+        with np.errstate(all="ignore"):
+            bad, p_bad = lu(A, v)
+        assert not (np.array_equal(np.triu(bad), U0) and np.array_equal(p_bad, perm)), v
+
+
 # ------------------------------------------------------ Cholesky adjoint
 # Gradient with respect to A of f(L), L = chol(A), given gL = df/dL (Murray
 # 2016; the paper is silent).  Pins: central differences of the oracle's own
