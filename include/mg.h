@@ -50,7 +50,8 @@ typedef struct mg_handle_s *mg_handle_t;
 #define MG_ERR_INTERNAL 3     /* inconsistent internal state */
 #define MG_ERR_ABORTED 4      /* a synchronising call saw a triangular sweep give up waiting */
 
-#define MG_INFO_SOLVE_ABORTED (-1) /* device info: a sweep's bounded wait gave up */
+#define MG_INFO_SOLVE_ABORTED (-1) /* device info: a sweep's (or the LU panel's) bounded wait gave up */
+#define MG_INFO_BAD_PIVOT (-2)     /* device info: mg_getrs met an ipiv entry outside 1..n */
 
 typedef enum { MG_F64 = 0, MG_F32 = 1 } mg_dtype;
 
@@ -91,7 +92,9 @@ mg_status mg_set_lookahead(mg_handle_t handle, int32_t enable);
  * call): -1 restores the built-in limit (2^22); 0 makes every block that
  * depends on another give up at once without waiting, which drives the
  * give-up path (info = MG_INFO_SOLVE_ABORTED, NaN solution) from the host for
- * tests; positive values set the limit.
+ * tests; positive values set the limit.  The same value bounds the polls of
+ * mg_getrf's panel grid barrier (built-in limit 2^24; 0: every barrier of a
+ * panel of more than 256 rows gives up without waiting).
  * Errors: -1 NULL handle, -2 limit outside [-1, 2^30]. */
 mg_status mg_set_sweep_spin_limit(mg_handle_t handle, int64_t limit);
 
@@ -457,6 +460,66 @@ mg_status mg_gp_loglik_grad(mg_handle_t handle, int64_t n, int64_t nrhs, const d
                             int32_t *info);
 
 /*
+ * General solve (paper: "Software design", the lu_solve bullet: A x = b for a
+ * general A through an LU factorisation with partial pivoting), FP64.
+ *
+ * getrf: P A = L U in place, LAPACK xGETRF semantics.  L is unit lower (its
+ * strict lower triangle stored over A's), U upper (stored over A's upper
+ * triangle, diagonal included).  Pivot of column k: the row with the largest
+ * |entry| on or below the diagonal, the first such row on ties (an entry that
+ * is NaN never wins; a NaN diagonal entry stays the pivot).
+ *   n      order, n >= 0.
+ *   A      device, lda x n column-major, overwritten by L and U.
+ *   ipiv   device int32[n]: row k was interchanged with row ipiv[k] (1-based,
+ *          ipiv[k] >= k + 1), in order k = 0..n-1.
+ *   work   device scratch of mg_getrf_buffer_size bytes (no initialisation;
+ *          not shared by two calls in flight).
+ *   info   device int32, written: 0, or k > 0 when U(k,k) (1-based) is exactly
+ *          zero -- the factorisation still completes, as LAPACK's; or
+ *          MG_INFO_SOLVE_ABORTED when a panel's bounded grid-barrier wait gave
+ *          up (A is then all NaN; mg_set_sweep_spin_limit sets the bound, 0
+ *          forces the give-up at the first wait of a panel with more than 256
+ *          rows).
+ * Limits (MG_ERR_UNSUPPORTED, nothing enqueued): n > 65536 for the default
+ * 256-CU device, or (n + 128 lda) * 8 >= 2^31.
+ * Errors: -1 handle, -2 n < 0, -3 A NULL, -4 lda < max(1,n), -5 ipiv NULL,
+ *         -6 work NULL, -7 work too small, -8 info NULL.
+ */
+mg_status mg_getrf_buffer_size(mg_handle_t handle, int64_t n, size_t *bytes);
+mg_status mg_getrf(mg_handle_t handle, int64_t n, double *A, int64_t lda, int32_t *ipiv, void *work,
+                   size_t work_bytes, int32_t *info);
+
+/*
+ * getrs: X = A^{-1} B from mg_getrf's L, U and ipiv: the interchanges applied
+ * to B, then L Y = P B and U X = Y by the persistent triangular sweeps of
+ * mg_potrs (mg_set_solve_mode applies).
+ *   LU     device, lda x n, mg_getrf's output (read only).
+ *   ipiv   device int32[n], mg_getrf's output; an entry outside 1..n is
+ *          ignored and reported (info = MG_INFO_BAD_PIVOT, B all NaN).
+ *   B      device, ldb x nrhs, overwritten with X.
+ *   work   device scratch of mg_getrs_buffer_size bytes.
+ *   info   optional device int32, in/out (NULL = absent): when non-zero on
+ *          entry (a singular U from mg_getrf), B is left unmodified; set to
+ *          MG_INFO_SOLVE_ABORTED when a sweep gives up (B all NaN).
+ * Errors: -1 handle, -2 n < 0, -3 nrhs < 0, -4 LU NULL, -5 lda, -6 ipiv NULL,
+ *         -7 B NULL, -8 ldb < max(1,n), -9 work NULL, -10 work too small.
+ */
+mg_status mg_getrs_buffer_size(mg_handle_t handle, int64_t n, int64_t nrhs, size_t *bytes);
+mg_status mg_getrs(mg_handle_t handle, int64_t n, int64_t nrhs, const double *LU, int64_t lda,
+                   const int32_t *ipiv, double *B, int64_t ldb, void *work, size_t work_bytes, int32_t *info);
+
+/*
+ * gesv: getrf then getrs, no host synchronisation.  A is overwritten by L and
+ * U, ipiv written, B by X unless info > 0 (U singular: B left unmodified).
+ * Workspace: mg_gesv_buffer_size bytes (the larger of the two).
+ * Errors: -1 handle, -2 n, -3 nrhs, -4 A, -5 lda, -6 ipiv, -7 B, -8 ldb,
+ *         -9 work NULL, -10 work too small, -11 info NULL.
+ */
+mg_status mg_gesv_buffer_size(mg_handle_t handle, int64_t n, int64_t nrhs, size_t *bytes);
+mg_status mg_gesv(mg_handle_t handle, int64_t n, int64_t nrhs, double *A, int64_t lda, int32_t *ipiv,
+                  double *B, int64_t ldb, void *work, size_t work_bytes, int32_t *info);
+
+/*
  * Profiling.  When enabled, every launch of the kernel kinds below is
  * bracketed by a pair of HIP events on the handle's stream, and the
  * algorithmic work of each launch is accumulated.
@@ -472,6 +535,10 @@ mg_status mg_gp_loglik_grad(mg_handle_t handle, int64_t n, int64_t nrhs, const d
  *   MG_PROF_TRAILING_NARROW -- trailing updates of rank 64 or 128 (inside a
  *                        two-level block column, and the rank-64/128 block
  *                        sizes); flops as MG_PROF_TRAILING
+ *   MG_PROF_LU_PANEL  -- mg_getrf's pivoted panel factorisation (m x 64);
+ *                        flops = m b^2 - b^3/3
+ *   MG_PROF_LU_UPDATE -- mg_getrf's trailing update A22 -= L21 U12 (m x m,
+ *                        rank 64); flops = 2 * 64 * m^2
  * mg_profile_query synchronises on the last recorded event, returns the
  * summed event time (ms), the number of launches and the summed flops and
  * algorithmic bytes, and resets the counter when reset != 0.
@@ -487,7 +554,9 @@ mg_status mg_gp_loglik_grad(mg_handle_t handle, int64_t n, int64_t nrhs, const d
 #define MG_PROF_ADJOINT 4
 #define MG_PROF_BATCHED 5
 #define MG_PROF_TRAILING_NARROW 6
-#define MG_PROF_KINDS 7
+#define MG_PROF_LU_PANEL 7
+#define MG_PROF_LU_UPDATE 8
+#define MG_PROF_KINDS 9
 /* Errors: -1 NULL handle. */
 mg_status mg_set_profiling(mg_handle_t handle, int32_t enable);
 /* Errors: -1 NULL handle, -2 a bit at or above MG_PROF_KINDS. */

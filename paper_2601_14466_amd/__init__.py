@@ -20,6 +20,7 @@ from ._lib import MgError, call, load, raw  # noqa: F401
 
 __all__ = [
     "Handle", "handle", "potrf", "potrs", "posv", "posv_noalloc", "posv_mixed", "posv_backward", "potrf_backward", "PosvFunction", "CholeskyFunction", "BatchPlan",
+    "getrf", "getrs", "gesv", "lu_solve",
     "posv_batched", "logdet", "gp_loglik", "gp_loglik_grad", "GPLogLik", "colmajor",
     "MgError", "load", "call", "raw",
 ]
@@ -366,6 +367,89 @@ def potrf_backward(L, gL, info=None, mode: str = "sym"):
     call("mg_potrf_backward", h.h, n, _ptr(Lc), max(1, n), _ptr(Gc), max(1, n), _ptr(gA), max(1, n), m,
          _ptr(work), wb.value, _ptr(info) if info is not None else None)
     return gA.T
+
+
+def _bytes_work(name, h, device, *dims):
+    torch = _torch()
+    nbytes = ctypes.c_size_t()
+    call(name, h.h, *dims, ctypes.byref(nbytes))
+    return torch.empty(max(1, nbytes.value), dtype=torch.uint8, device=device), nbytes.value
+
+
+def _check_f64(*ts):
+    torch = _torch()
+    if any(t.dtype != torch.float64 for t in ts):
+        raise TypeError("the general solve takes FP64 tensors")
+
+
+def getrf(A):
+    """LU factorisation with partial pivoting, P A = L U (FP64): returns
+    (LU, ipiv, info).  LU holds L's strict lower triangle (unit diagonal
+    implied) and U; ipiv is an int32 device tensor of 1-based interchanges
+    (row k swapped with row ipiv[k] - 1, in order); info is a 0-dim int32
+    device tensor (0, or k when U[k-1, k-1] is exactly zero; the
+    factorisation still completes)."""
+    torch = _torch()
+    _check_cuda(A)
+    _check_f64(A)
+    n = A.shape[0]
+    h = handle()
+    buf = A.T.clone(memory_format=torch.contiguous_format)
+    ipiv = torch.zeros(max(1, n), dtype=torch.int32, device=A.device)[:n]
+    info = torch.zeros((), dtype=torch.int32, device=A.device)
+    work, wb = _bytes_work("mg_getrf_buffer_size", h, A.device, n)
+    call("mg_getrf", h.h, n, _ptr(buf), max(1, n), _ptr(ipiv), _ptr(work), wb, _ptr(info))
+    return buf.T, ipiv, info
+
+
+def getrs(LU, ipiv, B, info=None):
+    """X = A^{-1} B from getrf's (LU, ipiv).  ``info`` (getrf's, optional):
+    when non-zero, X is B unchanged; a sweep that gives up sets it to
+    MG_INFO_SOLVE_ABORTED (X NaN), an ipiv entry outside 1..n to
+    MG_INFO_BAD_PIVOT (X NaN)."""
+    torch = _torch()
+    _check_cuda(LU, B)
+    _check_f64(LU, B)
+    flat = B.dim() == 1
+    n = LU.shape[0]
+    nrhs = 1 if flat else B.shape[1]
+    h = handle()
+    LUc = colmajor(LU)
+    Xc = (B.reshape(n, 1) if flat else B).T.clone(memory_format=torch.contiguous_format)
+    ip = ipiv.to(torch.int32).contiguous()
+    work, wb = _bytes_work("mg_getrs_buffer_size", h, LU.device, n, nrhs)
+    call("mg_getrs", h.h, n, nrhs, _ptr(LUc), max(1, n), _ptr(ip), _ptr(Xc), max(1, n), _ptr(work), wb,
+         _ptr(info) if info is not None else None)
+    X = Xc.T
+    return X.reshape(n) if flat else X
+
+
+def gesv(A, B):
+    """Solve A X = B for a general A (FP64) by getrf + getrs in one call
+    (mg_gesv).  Returns (X, LU, ipiv, info); on info > 0 X is B unchanged."""
+    torch = _torch()
+    _check_cuda(A, B)
+    _check_f64(A, B)
+    flat = B.dim() == 1
+    n = A.shape[0]
+    nrhs = 1 if flat else B.shape[1]
+    h = handle()
+    Ac = A.T.clone(memory_format=torch.contiguous_format)
+    Xc = (B.reshape(n, 1) if flat else B).T.clone(memory_format=torch.contiguous_format)
+    ipiv = torch.zeros(max(1, n), dtype=torch.int32, device=A.device)[:n]
+    info = torch.zeros((), dtype=torch.int32, device=A.device)
+    work, wb = _bytes_work("mg_gesv_buffer_size", h, A.device, n, nrhs)
+    call("mg_gesv", h.h, n, nrhs, _ptr(Ac), max(1, n), _ptr(ipiv), _ptr(Xc), max(1, n), _ptr(work), wb,
+         _ptr(info))
+    X = Xc.T
+    return (X.reshape(n) if flat else X), Ac.T, ipiv, info
+
+
+def lu_solve(A, B):
+    """The paper's lu_solve: X with A X = B for a general A (FP64).
+    Returns (X, info)."""
+    X, _, _, info = gesv(A, B)
+    return X, info
 
 
 def _make_cholesky_function():

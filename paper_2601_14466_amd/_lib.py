@@ -20,6 +20,7 @@ MG_ERR_ABORTED = 4
 MG_ERR_SCRATCH_LIMIT = 5
 MG_NOALLOC_SCRATCH_BYTES = 32 << 20
 MG_INFO_SOLVE_ABORTED = -1
+MG_INFO_BAD_PIVOT = -2
 MG_F64 = 0
 MG_F32 = 1
 MG_PREC_F32 = 1
@@ -31,6 +32,8 @@ MG_PROF_SOLVE = 3
 MG_PROF_ADJOINT = 4
 MG_PROF_BATCHED = 5
 MG_PROF_TRAILING_NARROW = 6
+MG_PROF_LU_PANEL = 7
+MG_PROF_LU_UPDATE = 8
 MG_GRAD_SYM = 0
 MG_GRAD_LOWER = 1
 MG_SOLVE_INVERSE = 0
@@ -63,6 +66,12 @@ SIGNATURES = {
     "mg_posv_backward": (i32, [vp, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]),
     "mg_potrf_backward_buffer_size": (i32, [vp, i64, ctypes.POINTER(sz)]),
     "mg_potrf_backward": (i32, [vp, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]),
+    "mg_getrf_buffer_size": (i32, [vp, i64, ctypes.POINTER(sz)]),
+    "mg_getrf": (i32, [vp, i64, vp, i64, vp, vp, sz, vp]),
+    "mg_getrs_buffer_size": (i32, [vp, i64, i64, ctypes.POINTER(sz)]),
+    "mg_getrs": (i32, [vp, i64, i64, vp, i64, vp, vp, i64, vp, sz, vp]),
+    "mg_gesv_buffer_size": (i32, [vp, i64, i64, ctypes.POINTER(sz)]),
+    "mg_gesv": (i32, [vp, i64, i64, vp, i64, vp, vp, i64, vp, sz, vp]),
     "mg_batch_plan_create": (i32, [vp, i32, i32, vp, i32, vp, ctypes.POINTER(vp)]),
     "mg_batch_plan_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(dbl),
                                  ctypes.POINTER(i32)]),

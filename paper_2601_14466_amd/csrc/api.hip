@@ -337,6 +337,84 @@ mg_status mg_potrf_backward(mg_handle_t h, int64_t n, const double* L, int64_t l
     return potrf_backward_impl(h, n, L, lda, GL, ldgl, GA, ldga, (int)mode, work, info);
 }
 
+// ------------------------------------------------------------ general solve
+
+mg_status mg_getrf_buffer_size(mg_handle_t h, int64_t n, size_t* bytes) {
+    if (!h) return -1;
+    if (n < 0) return -2;
+    if (!bytes) return -3;
+    *bytes = getrf_work_bytes(n);
+    return MG_OK;
+}
+
+mg_status mg_getrf(mg_handle_t h, int64_t n, double* A, int64_t lda, int32_t* ipiv, void* work, size_t work_bytes,
+                   int32_t* info) {
+    if (!h) return -1;
+    if (n < 0) return -2;
+    if (!A && n > 0) return -3;
+    if (lda < std::max<int64_t>(1, n)) return -4;
+    if (!ipiv && n > 0) return -5;
+    const size_t need = getrf_work_bytes(n);
+    if (need > 0 && !work) return -6;
+    if (work_bytes < need) return -7;
+    if (!info) return -8;
+    return getrf_impl(h, n, A, lda, ipiv, work, info);
+}
+
+mg_status mg_getrs_buffer_size(mg_handle_t h, int64_t n, int64_t nrhs, size_t* bytes) {
+    if (!h) return -1;
+    if (n < 0) return -2;
+    if (nrhs < 0) return -3;
+    if (!bytes) return -4;
+    *bytes = getrs_work_bytes(n, nrhs);
+    return MG_OK;
+}
+
+mg_status mg_getrs(mg_handle_t h, int64_t n, int64_t nrhs, const double* LU, int64_t lda, const int32_t* ipiv,
+                   double* B, int64_t ldb, void* work, size_t work_bytes, int32_t* info) {
+    if (!h) return -1;
+    if (n < 0) return -2;
+    if (nrhs < 0) return -3;
+    if (!LU && n > 0) return -4;
+    if (lda < std::max<int64_t>(1, n)) return -5;
+    if (!ipiv && n > 0) return -6;
+    if (!B && n > 0 && nrhs > 0) return -7;
+    if (ldb < std::max<int64_t>(1, n)) return -8;
+    const size_t need = getrs_work_bytes(n, nrhs);
+    if (need > 0 && !work) return -9;
+    if (work_bytes < need) return -10;
+    if (n > INT32_MAX - 1) return MG_ERR_UNSUPPORTED;
+    return getrs_impl(h, n, nrhs, LU, lda, ipiv, B, ldb, work, info);
+}
+
+mg_status mg_gesv_buffer_size(mg_handle_t h, int64_t n, int64_t nrhs, size_t* bytes) {
+    if (!h) return -1;
+    if (n < 0) return -2;
+    if (nrhs < 0) return -3;
+    if (!bytes) return -4;
+    *bytes = std::max(getrf_work_bytes(n), getrs_work_bytes(n, nrhs));
+    return MG_OK;
+}
+
+mg_status mg_gesv(mg_handle_t h, int64_t n, int64_t nrhs, double* A, int64_t lda, int32_t* ipiv, double* B,
+                  int64_t ldb, void* work, size_t work_bytes, int32_t* info) {
+    if (!h) return -1;
+    if (n < 0) return -2;
+    if (nrhs < 0) return -3;
+    if (!A && n > 0) return -4;
+    if (lda < std::max<int64_t>(1, n)) return -5;
+    if (!ipiv && n > 0) return -6;
+    if (!B && n > 0 && nrhs > 0) return -7;
+    if (ldb < std::max<int64_t>(1, n)) return -8;
+    const size_t need = std::max(getrf_work_bytes(n), getrs_work_bytes(n, nrhs));
+    if (need > 0 && !work) return -9;
+    if (work_bytes < need) return -10;
+    if (!info) return -11;
+    mg_status rc;
+    if ((rc = getrf_impl(h, n, A, lda, ipiv, work, info))) return rc;
+    return getrs_impl(h, n, nrhs, A, lda, ipiv, B, ldb, work, info);
+}
+
 mg_status mg_logdet(mg_handle_t h, mg_dtype dt, int64_t n, const void* L, int64_t lda, double* out,
                     const int32_t* info) {
     if (!h) return -1;

@@ -79,6 +79,18 @@ mg_status posv_mixed_impl(mg_handle_t h, int lo, int64_t n, int64_t nrhs, const 
                           const double* B, int64_t ldb, double* X, int64_t ldx, const mg_ir_opts* o, void* work,
                           mg_ir_result* res, int32_t* info);
 
+// General solve (LU with partial pivoting), FP64.
+size_t getrf_work_bytes(int64_t n);
+mg_status getrf_impl(mg_handle_t h, int64_t n, double* A, int64_t lda, int32_t* ipiv, void* work, int32_t* info);
+size_t getrs_work_bytes(int64_t n, int64_t nrhs);
+mg_status getrs_impl(mg_handle_t h, int64_t n, int64_t nrhs, const double* LU, int64_t lda, const int32_t* ipiv,
+                     double* B, int64_t ldb, void* work, int32_t* info);
+// The two sweeps of an LU solve (forward with the unit lower factor, B's rows
+// read through rperm; backward with the upper factor); words: 2 x
+// sweep_words_bytes(nrhs) bytes.
+mg_status lu_sweeps(mg_handle_t h, int64_t n, int64_t nrhs, const double* LU, int64_t lda, const int32_t* rperm,
+                    double* B, int64_t ldb, double* Y, void* words, int32_t* info);
+
 mg_status set_info_zero(hipStream_t s, int32_t* info);
 // Create (or re-create after a mode change) the look-ahead streams and events.
 mg_status ensure_streams(mg_handle_t h);

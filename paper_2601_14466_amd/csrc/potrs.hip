@@ -87,11 +87,25 @@ __global__ __launch_bounds__(256) void k_sweep_init(T* Out, int64_t ld, int64_t 
         Out[idx(e % n, e / n, ld)] = sentinel((T*)nullptr);
 }
 
+// The lower-triangular operator a sweep applies, entry (r, c) with r >= c:
+// KIND 0, the Cholesky factor L (the lower triangle of the array); KIND 1,
+// the unit lower factor of an LU factorisation (strict lower triangle of the
+// array, 1 on the diagonal); KIND 2, U^T for the upper factor U of an LU
+// factorisation (the upper triangle of the array read transposed), so that
+// the backward sweep, which applies the operator's transpose, solves U x = y.
+template <typename T, int KIND>
+__device__ __forceinline__ T lop(const T* L, int64_t lda, int64_t r, int64_t c) {
+    if constexpr (KIND == 2) return L[idx(c, r, lda)];
+    if constexpr (KIND == 1)
+        if (r == c) return (T)1;
+    return L[idx(r, c, lda)];
+}
+
 // L_jj (jb x jb lower, identity-padded to 64 x 64) into Ls[r*LDP + c] scaled
 // by its pivots: by column (Ls(r,c) = L(r,c)/L(c,c)) when by_row is false,
 // by row (Ls(r,c) = L(r,c)/L(r,r)) when it is true; the diagonal of Ls is 0
 // and piv holds L(c,c).  All 256 threads take part.
-template <typename T, bool by_row>
+template <typename T, bool by_row, int KIND>
 __device__ __forceinline__ void stage_diag(T* Ls, T* piv, const T* L, int64_t lda, int64_t j0, int jb) {
     const int tid = threadIdx.x;
     T v[JB * JB / 256];
@@ -99,7 +113,7 @@ __device__ __forceinline__ void stage_diag(T* Ls, T* piv, const T* L, int64_t ld
     for (int q = 0; q < JB * JB / 256; ++q) {
         const int e = tid + 256 * q;
         const int rr = e & (JB - 1), cc = e >> 6;
-        v[q] = (rr < jb && cc < jb && rr >= cc) ? L[idx(j0 + rr, j0 + cc, lda)] : (T)(rr == cc ? 1 : 0);
+        v[q] = (rr < jb && cc < jb && rr >= cc) ? lop<T, KIND>(L, lda, j0 + rr, j0 + cc) : (T)(rr == cc ? 1 : 0);
         if (rr == cc) piv[rr] = v[q];
     }
     __syncthreads();
@@ -120,14 +134,14 @@ __device__ __forceinline__ void stage_diag(T* Ls, T* piv, const T* L, int64_t ld
 // (the same entry for every lane).  The wave reads all of Ls before it writes
 // Z over it (LDS operations of one wave complete in program order).  All 256
 // threads take part in the staging.
-template <typename T>
+template <typename T, int KIND>
 __device__ __forceinline__ void stage_inverse(T* Ls, T* rpiv, const T* L, int64_t lda, int64_t j0, int jb) {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int q = 0; q < JB * JB / 256; ++q) {
         const int e = tid + 256 * q;
         const int rr = e & (JB - 1), cc = e >> 6;
-        const T v = (rr < jb && cc < jb && rr >= cc) ? L[idx(j0 + rr, j0 + cc, lda)] : (T)(rr == cc ? 1 : 0);
+        const T v = (rr < jb && cc < jb && rr >= cc) ? lop<T, KIND>(L, lda, j0 + rr, j0 + cc) : (T)(rr == cc ? 1 : 0);
         Ls[cc * LDP + rr] = v;
         if (rr == cc) rpiv[rr] = (T)1 / v;
     }
@@ -171,11 +185,14 @@ __device__ __forceinline__ void store_coherent(T* p, T v) {
 // dependency without waiting, which exercises the give-up path).
 // INV: the diagonal block is applied as its inverse (formed when the
 // workgroup starts, off the chain of dependencies) by MFMA products;
-// otherwise by substitution.
-template <typename T, int RT, bool FWD, bool INV>
+// otherwise by substitution.  KIND selects the triangular operator (lop).
+// rperm (forward sweep; may be null): row i of In is taken from row
+// rperm[i], the row interchanges of an LU factorisation applied on the fly.
+template <typename T, int RT, bool FWD, bool INV, int KIND = 0>
 __global__ __launch_bounds__(256, 2) void k_sweep(const T* __restrict__ L, int64_t lda, int64_t n, int64_t nrhs,
                                                const T* __restrict__ In, int64_t ldi, T* Out, int64_t ldo,
-                                               SweepSync* sy, const int32_t* info, int spin_limit) {
+                                               SweepSync* sy, const int32_t* info, int spin_limit,
+                                               const int32_t* __restrict__ rperm) {
     constexpr int NR = 16 * RT, XP = NR + 1, QW = NR / 4;
     __shared__ T Ls[JB * LDP];
     __shared__ T piv[JB];
@@ -194,8 +211,8 @@ __global__ __launch_bounds__(256, 2) void k_sweep(const T* __restrict__ L, int64
     const int bi = FWD ? t : nblk - 1 - t;
     const int64_t r0 = (int64_t)bi * JB;
     const int jb = (int)(n - r0 < JB ? n - r0 : JB);
-    if constexpr (INV) stage_inverse<T>(Ls, piv, L, lda, r0, jb);
-    else stage_diag<T, !FWD>(Ls, piv, L, lda, r0, jb);
+    if constexpr (INV) stage_inverse<T, KIND>(Ls, piv, L, lda, r0, jb);
+    else stage_diag<T, !FWD, KIND>(Ls, piv, L, lda, r0, jb);
     // MFMA phase: wave w owns rows 16 w .. 16 w + 15 of the block
     const int64_t rwc = (16 * w + i < jb) ? r0 + 16 * w + i : r0;  // clamped for loads
     // blocks this one depends on: j = 0 .. bi - 1 (forward) or j = nblk - 1
@@ -214,18 +231,20 @@ __global__ __launch_bounds__(256, 2) void k_sweep(const T* __restrict__ L, int64
     T vin[INV ? 4 * RT : QW];
     if constexpr (INV) {
         const bool rok = 16 * w + i < jb;
+        const int64_t rin = (rperm && rok) ? rperm[r0 + 16 * w + i] : r0 + 16 * w + i;
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t q = rc0 + 16 * rt + tcol<T>(g, r);
-                vin[4 * rt + r] = (rok && q < nrhs) ? In[idx(r0 + 16 * w + i, q, ldi)] : (T)0;
+                vin[4 * rt + r] = (rok && q < nrhs) ? In[idx(rin, q, ldi)] : (T)0;
             }
     } else {
+        const int64_t rin = (rperm && lane < jb) ? rperm[r0 + lane] : r0 + lane;
 #pragma unroll
         for (int u = 0; u < QW; ++u) {
             const int q = w + 4 * u;
-            vin[u] = (lane < jb && rc0 + q < nrhs) ? In[idx(r0 + lane, rc0 + q, ldi)] : (T)0;
+            vin[u] = (lane < jb && rc0 + q < nrhs) ? In[idx(rin, rc0 + q, ldi)] : (T)0;
         }
     }
     {
@@ -249,7 +268,10 @@ __global__ __launch_bounds__(256, 2) void k_sweep(const T* __restrict__ L, int64
 #pragma unroll
             for (int ks = 0; ks < JB / 4; ++ks) {
                 const int c = 4 * ks + g;
-                dst[ks] = (c < jbj) ? (FWD ? L[idx(rwc, c0 + c, lda)] : L[idx(c0 + c, rwc, lda)]) : (T)0;
+                // forward: operator row rwc; backward: operator column rwc
+                // (KIND 2 stores the operator transposed: both read along a row)
+                dst[ks] = (c < jbj) ? ((FWD || KIND == 2) ? L[idx(rwc, c0 + c, lda)] : L[idx(c0 + c, rwc, lda)])
+                                    : (T)0;
             }
         };
         auto load_x = [&](T* dst, int d) {
@@ -428,13 +450,13 @@ static mg_status sweep(hipStream_t st, int64_t n, int64_t nrhs, const T* L, int6
     hipLaunchKernelGGL((k_sweep_init<T>), dim3(gfill), dim3(256), 0, st, Y, n, n, nrhs, sy, info);
     MG_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_sweep<T, 1, true, INV>), grid, dim3(256), 0, st, L, lda, n, nrhs, (const T*)B, ldb, Y, n, sy,
-                       info, spin_limit);
+                       info, spin_limit, (const int32_t*)nullptr);
     MG_LAUNCH_CHECK();
     // B has been read; it now receives X
     hipLaunchKernelGGL((k_sweep_init<T>), dim3(gfill), dim3(256), 0, st, B, ldb, n, nrhs, sy + np, info);
     MG_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_sweep<T, 1, false, INV>), grid, dim3(256), 0, st, L, lda, n, nrhs, (const T*)Y, n, B, ldb,
-                       sy + np, info, spin_limit);
+                       sy + np, info, spin_limit, (const int32_t*)nullptr);
     MG_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_sweep_check<T>), dim3(1), dim3(256), 0, st, B, ldb, n, nrhs, (const SweepSync*)sy,
                        (int)(2 * np), info);
@@ -479,16 +501,54 @@ mg_status trsm_lt_impl(mg_handle_t h, int64_t n, int64_t nrhs, const T* L, int64
     MG_LAUNCH_CHECK();
     if (h->solve_mode == MG_SOLVE_SUBSTITUTION)
         hipLaunchKernelGGL((k_sweep<T, 1, false, false>), grid, dim3(256), 0, st, L, lda, n, nrhs, In, ldi, Out, ldo,
-                           sy, info, lim);
+                           sy, info, lim, (const int32_t*)nullptr);
     else
         hipLaunchKernelGGL((k_sweep<T, 1, false, true>), grid, dim3(256), 0, st, L, lda, n, nrhs, In, ldi, Out, ldo,
-                           sy, info, lim);
+                           sy, info, lim, (const int32_t*)nullptr);
     MG_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_sweep_check<T>), dim3(1), dim3(256), 0, st, Out, ldo, n, nrhs, (const SweepSync*)sy,
                        (int)np, info);
     MG_LAUNCH_CHECK();
     return MG_OK;
 }
+// The two sweeps of an LU solve: Y = L^{-1} (P B) with L the unit lower
+// factor and row i of P B read from row rperm[i] of B, then B = U^{-1} Y,
+// followed by the give-up check.  sy: two pass-word sets
+// (2 * sweep_words_bytes(nrhs) bytes).  Skipped when *info != 0.
+mg_status lu_sweeps(mg_handle_t h, int64_t n, int64_t nrhs, const double* LU, int64_t lda, const int32_t* rperm,
+                    double* B, int64_t ldb, double* Y, void* words, int32_t* info) {
+    if (n == 0 || nrhs == 0) return MG_OK;
+    hipStream_t st = h->stream;
+    const int64_t np = sweep_passes(nrhs);
+    SweepSync* sy = (SweepSync*)words;
+    const int lim = h->spin_limit < 0 ? SWEEP_SPIN_LIMIT : h->spin_limit;
+    const dim3 grid((unsigned)cdiv(n, JB), (unsigned)np);
+    const unsigned gfill = (unsigned)std::min<int64_t>(std::max<int64_t>(1, cdiv(n * nrhs, 256)), 2048);
+    const bool sub = h->solve_mode == MG_SOLVE_SUBSTITUTION;
+    hipLaunchKernelGGL((k_sweep_init<double>), dim3(gfill), dim3(256), 0, st, Y, n, n, nrhs, sy, info);
+    MG_LAUNCH_CHECK();
+    if (sub)
+        hipLaunchKernelGGL((k_sweep<double, 1, true, false, 1>), grid, dim3(256), 0, st, LU, lda, n, nrhs,
+                           (const double*)B, ldb, Y, n, sy, info, lim, rperm);
+    else
+        hipLaunchKernelGGL((k_sweep<double, 1, true, true, 1>), grid, dim3(256), 0, st, LU, lda, n, nrhs,
+                           (const double*)B, ldb, Y, n, sy, info, lim, rperm);
+    MG_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_sweep_init<double>), dim3(gfill), dim3(256), 0, st, B, ldb, n, nrhs, sy + np, info);
+    MG_LAUNCH_CHECK();
+    if (sub)
+        hipLaunchKernelGGL((k_sweep<double, 1, false, false, 2>), grid, dim3(256), 0, st, LU, lda, n, nrhs,
+                           (const double*)Y, n, B, ldb, sy + np, info, lim, (const int32_t*)nullptr);
+    else
+        hipLaunchKernelGGL((k_sweep<double, 1, false, true, 2>), grid, dim3(256), 0, st, LU, lda, n, nrhs,
+                           (const double*)Y, n, B, ldb, sy + np, info, lim, (const int32_t*)nullptr);
+    MG_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_sweep_check<double>), dim3(1), dim3(256), 0, st, B, ldb, n, nrhs, (const SweepSync*)sy,
+                       (int)(2 * np), info);
+    MG_LAUNCH_CHECK();
+    return MG_OK;
+}
+
 template mg_status trsm_lt_impl<double>(mg_handle_t, int64_t, int64_t, const double*, int64_t, const double*, int64_t,
                                         double*, int64_t, void*, int32_t*);
 

@@ -69,6 +69,12 @@ def test_null_handle_is_argument_one(lib):
     assert L.raw("mg_gp_loglik_buffer_size", None, n, 1, ctypes.byref(sz)) == -1
     assert L.raw("mg_gp_loglik", None, n, 1, vp(8), n, vp(8), n, None, n, vp(8), n, vp(8), vp(8), 64,
                  vp(8)) == -1
+    assert L.raw("mg_getrf_buffer_size", None, n, ctypes.byref(sz)) == -1
+    assert L.raw("mg_getrf", None, n, vp(8), n, vp(8), vp(8), 64, vp(8)) == -1
+    assert L.raw("mg_getrs_buffer_size", None, n, 1, ctypes.byref(sz)) == -1
+    assert L.raw("mg_getrs", None, n, 1, vp(8), n, vp(8), vp(8), n, vp(8), 64, None) == -1
+    assert L.raw("mg_gesv_buffer_size", None, n, 1, ctypes.byref(sz)) == -1
+    assert L.raw("mg_gesv", None, n, 1, vp(8), n, vp(8), vp(8), n, vp(8), 64, vp(8)) == -1
     d, i = ctypes.c_double(), ctypes.c_int64()
     assert L.raw("mg_profile_query", None, 0, ctypes.byref(d), ctypes.byref(i), ctypes.byref(d),
                  ctypes.byref(d), 0) == -1
