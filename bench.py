@@ -573,9 +573,90 @@ def cpu_library_context(torch, synth, n: int = 8192, nrhs: int = 16, reps: int =
                 info=int(inf1) or int(inf2))
 
 
+def lu_flops(n: int, nrhs: int) -> float:
+    """Nominal flops of getrf (LAWN 41: 2n^3/3 - n^2/2 + 5n/6) plus getrs (2 n^2 nrhs)."""
+    return 2.0 * n ** 3 / 3 - n ** 2 / 2 + 5.0 * n / 6 + 2.0 * n * n * nrhs
+
+
+def bench_lu(torch, mg, synth, n: int, nrhs: int = 16, reps: int = 3, seed: int = 7100):
+    """The general solve (mg_gesv: pivoted LU + the two sweeps), FP64, on a
+    Gaussian A (entries N(0,1)) and B = A X_true; each rep factors its own
+    pre-staged copy.  Only the trailing-update kind is bracketed by events in
+    the timed reps; the per-kind breakdown comes from one extra rep."""
+    from paper_2601_14466_amd import _lib
+    dev = torch.device("cuda", 0)
+    log(f"[bench] lu: generating n={n} nrhs={nrhs}")
+    A0 = synth.torch_normal((n, n), seed + n)
+    Xt = synth.torch_normal((n, nrhs), seed + 1 + n)
+    B0 = A0 @ Xt
+    A0c = A0.T.contiguous()                    # column-major A
+    B0c = B0.T.contiguous()
+    h = mg.handle()
+    wb = ctypes.c_size_t()
+    _lib.call("mg_gesv_buffer_size", h.h, n, nrhs, ctypes.byref(wb))
+    work = torch.empty(max(1, wb.value), dtype=torch.uint8, device=dev)
+    free, _ = torch.cuda.mem_get_info()
+    ncopy = max(1, min(reps + 1, int(0.7 * free // (A0c.numel() * 8 + B0c.numel() * 8))))
+    As = [A0c.clone() for _ in range(ncopy)]
+    Bs = [B0c.clone() for _ in range(ncopy)]
+    ipiv = torch.zeros(n, dtype=torch.int32, device=dev)
+    infos = torch.zeros(ncopy, dtype=torch.int32, device=dev)
+
+    def run(j):
+        _lib.call("mg_gesv", h.sync_stream(), n, nrhs, ctypes.c_void_p(As[j].data_ptr()), n,
+                  ctypes.c_void_p(ipiv.data_ptr()), ctypes.c_void_p(Bs[j].data_ptr()), n,
+                  ctypes.c_void_p(work.data_ptr()), wb.value, ctypes.c_void_p(infos[j:j + 1].data_ptr()))
+
+    def restage():
+        for j in range(ncopy):
+            As[j].copy_(A0c)
+            Bs[j].copy_(B0c)
+        torch.cuda.synchronize()
+
+    run(0)                                     # warm-up
+    restage()
+    h.set_profiling(True, kinds=[_lib.MG_PROF_LU_UPDATE])
+    h.profile(_lib.MG_PROF_LU_UPDATE, reset=True)
+    ts = []
+    for i in range(reps):
+        j = i % ncopy
+        if i >= ncopy:
+            As[j].copy_(A0c)
+            Bs[j].copy_(B0c)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run(j)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    up = h.profile(_lib.MG_PROF_LU_UPDATE, reset=True)
+    info = int(infos.max())
+    X = Bs[(reps - 1) % ncopy].T
+    R = B0 - A0 @ X
+    anorm = float(A0.abs().sum(1).max())
+    eta = (R.abs().amax(0) / (anorm * X.abs().amax(0) + B0.abs().amax(0))).max().item()
+    # per-kind breakdown, one more rep with the panel and solve kinds bracketed too
+    restage()
+    kinds = [_lib.MG_PROF_LU_PANEL, _lib.MG_PROF_LU_UPDATE, _lib.MG_PROF_SOLVE]
+    h.set_profiling(True, kinds=kinds)
+    for k in kinds:
+        h.profile(k, reset=True)
+    run(0)
+    torch.cuda.synchronize()
+    kms = {name: round(h.profile(k, reset=True)["ms"], 3) for name, k in zip(("panel", "update", "solve"), kinds)}
+    h.set_profiling(False)
+    ms = _median(ts)
+    del As, Bs
+    return dict(n=n, nrhs=nrhs, ms=round(ms, 3), runs_ms=[round(t, 3) for t in ts],
+                tflops=round(lu_flops(n, nrhs) / (ms / 1e3) / 1e12, 3), eta_fp64_device=eta, info=info,
+                kernel_ms=kms,
+                roofline=(roofline_obj("k_gemm_sub (LU trailing update, rank 64)", up["flops"], up["bytes"],
+                                       up["ms"], up["launches"], FP64_PEAK_TFLOPS) if up["launches"] else None))
+
+
 LEGS = ("mixed_fp32", "mixed_bf16", "mixed_fp32_n65536", "small_n1024", "batched_f64", "batched_f32", "adjoint_n8192",
         "potrf_backward_n8192",
-        "fp64_n8192", "fp64_n16384", "gp_loglik_n16384", "gp_loglik_grad_n4096")
+        "fp64_n8192", "fp64_n16384", "gp_loglik_n16384", "gp_loglik_grad_n4096", "lu_n8192", "lu_n32768")
 
 
 def run_extra(key, torch, mg, synth, args):
@@ -608,6 +689,8 @@ def run_extra(key, torch, mg, synth, args):
         return bench_gp(torch, mg, synth)
     if key == "gp_loglik_grad_n4096":
         return bench_gp_grad(torch, mg, synth)
+    if key in ("lu_n8192", "lu_n32768"):
+        return bench_lu(torch, mg, synth, int(key.split("_n")[1]))
     raise ValueError(key)
 
 
