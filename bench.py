@@ -650,7 +650,7 @@ def bench_lu(torch, mg, synth, n: int, nrhs: int = 16, reps: int = 3, seed: int 
     return dict(n=n, nrhs=nrhs, ms=round(ms, 3), runs_ms=[round(t, 3) for t in ts],
                 tflops=round(lu_flops(n, nrhs) / (ms / 1e3) / 1e12, 3), eta_fp64_device=eta, info=info,
                 kernel_ms=kms,
-                roofline=(roofline_obj("k_gemm_sub (LU trailing update, rank 64)", up["flops"], up["bytes"],
+                roofline=(roofline_obj("k_gemm_sub<true> (LU trailing update, rank 256/512)", up["flops"], up["bytes"],
                                        up["ms"], up["launches"], FP64_PEAK_TFLOPS) if up["launches"] else None))
 
 

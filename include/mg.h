@@ -480,8 +480,13 @@ mg_status mg_gp_loglik_grad(mg_handle_t handle, int64_t n, int64_t nrhs, const d
  *          up (A is then all NaN; mg_set_sweep_spin_limit sets the bound, 0
  *          forces the give-up at the first wait of a panel with more than 256
  *          rows).
+ * Blocking: 64-wide pivoted panels inside outer block columns of 256 or 512
+ * (the rank of the trailing update: 512 from n = 16384, else 256;
+ * mg_set_block_size(h, 256 or 512) selects one, other values leave the
+ * default).  The result does not depend on it up to rounding; pivots and
+ * info are those of column-by-column elimination.
  * Limits (MG_ERR_UNSUPPORTED, nothing enqueued): n > 65536 for the default
- * 256-CU device, or (n + 128 lda) * 8 >= 2^31.
+ * 256-CU device, or (n + 576 lda) * 8 >= 2^31.
  * Errors: -1 handle, -2 n < 0, -3 A NULL, -4 lda < max(1,n), -5 ipiv NULL,
  *         -6 work NULL, -7 work too small, -8 info NULL.
  */
@@ -538,7 +543,9 @@ mg_status mg_gesv(mg_handle_t handle, int64_t n, int64_t nrhs, double *A, int64_
  *   MG_PROF_LU_PANEL  -- mg_getrf's pivoted panel factorisation (m x 64);
  *                        flops = m b^2 - b^3/3
  *   MG_PROF_LU_UPDATE -- mg_getrf's trailing update A22 -= L21 U12 (m x m,
- *                        rank 64); flops = 2 * 64 * m^2
+ *                        rank 256); flops = 2 * 256 * m^2 (its rank-64
+ *                        updates inside a 256-wide block column count as
+ *                        MG_PROF_TRAILING_NARROW)
  * mg_profile_query synchronises on the last recorded event, returns the
  * summed event time (ms), the number of launches and the summed flops and
  * algorithmic bytes, and resets the counter when reset != 0.

@@ -3,29 +3,39 @@
 // factorisation): P A = L U by Gaussian elimination with partial pivoting,
 // then the row interchanges and the two triangular solves.  FP64.
 //
-// Blocked right-looking factorisation over block columns of LU_NB = 64:
-//   1. k_getf2_panel: the panel (rows k0..n-1, columns k0..k0+63) with
-//      partial pivoting, a cooperative launch of G workgroups that each keep
-//      256 consecutive rows of the panel in LDS, one row per thread.  For
-//      every column j each workgroup publishes its largest |entry| (the first
-//      row on ties) with that row's values, and the owner of row j publishes
-//      row j, to a double-buffered slot array; the workgroups meet at one
-//      grid barrier and all pick the same winner: the owners of rows j and p
-//      exchange them, and every row below j is scaled by the pivot and
-//      updated with the pivot row (a local rank-1 update).  Pivot choice and
-//      the order of each entry's updates are those of column-by-column
+// Two-level blocked right-looking factorisation: outer block columns of
+// nb2 = 256 or 512 (512 from n = 16384; the handle's block size selects
+// either), each factored as inner panels of LU_NB = 64.
+//   1. k_getf2_panel: the inner panel (rows k0..n-1, 64 columns) with partial
+//      pivoting, a cooperative launch of G workgroups that each keep 256
+//      consecutive rows of the panel in LDS, one row per thread.  For every
+//      column j each workgroup publishes its largest |entry| (the first row
+//      on ties; reduced by DPP moves and the gfx950 row swaps) with that
+//      row's values, and the owner of row j publishes row j, into write-once
+//      slots (one per column and workgroup, reset to a sentinel before the
+//      panel); every workgroup polls the G headers until all are written,
+//      picks the same winner, fetches its row, and the owners of rows j and
+//      p exchange them before the local rank-1 update.  Pivot choice and the
+//      order of each entry's updates are those of column-by-column
 //      elimination.
 //   2. k_lu_swap_cols: the panel's interchanges applied to the columns left
-//      of it.
-//   3. k_lu_row_block: per 64 columns right of the panel, the interchanges
-//      (the block row's rows and every row they touch go through LDS), then
-//      U12 = L11^{-1} A12 by forward substitution with the unit lower L11
-//      (one lane per column), stored over A12 and transposed into a
-//      workspace, the operand layout of the update.
-//   4. k_gemm_sub: A22 -= L21 U12 on the FP64 matrix pipe (128 x 128 output
-//      tiles of four 64 x 64 wave quarters, operands streamed from memory
-//      straight into registers through a ring of four k-steps, as the
-//      Cholesky trailing update but over the whole tile grid).
+//      of it and to those right of the outer block column (which no update
+//      of this outer block has reached yet, so moving their rows keeps them
+//      consistent).
+//   3. k_lu_row_block (with interchanges): the rest of the outer block row,
+//      U12 = L11^{-1} A12 by forward substitution with the panel's unit lower
+//      L11 (one lane per column), then k_gemm_sub<false>: the rank-64 update
+//      of the rest of the outer block column, so the next inner panel sees
+//      every earlier one.
+//   4. After the inner panels, the outer block row right of the outer
+//      block: U12 = L11^{-1} A12 with the nb2 x nb2 unit lower L11, by 64-row
+//      blocks (k_lu_row_block without interchanges, then a rank-64
+//      k_gemm_sub<false> of the rows below inside the outer block).
+//   5. k_gemm_sub<true>: A22 -= L21 U12 of rank nb2 on the FP64 matrix pipe
+//      over the trailing matrix (128 x 128 output tiles of four 64 x 64 wave
+//      quarters in bands of 8 tile rows, operands streamed from memory
+//      straight into registers through a ring of four k-steps, C folded into
+//      the k-loop).
 // info: the first k (1-based) whose pivot is exactly zero; elimination goes
 // on past it (that column is not scaled), as LAPACK's xGETRF.
 //
@@ -42,26 +52,38 @@
 
 namespace mg {
 
-constexpr int LU_NB = 64;                    // block column width
-constexpr int LU_ROWS = 256;                 // panel rows per workgroup (one per thread)
-constexpr int LU_HDR = 2;                    // slot header: |value|, row
-constexpr int LU_SLOT = LU_HDR + LU_NB;      // doubles per slot
-constexpr int LU_LIST = 2 * LU_NB;           // rows one block of 64 interchanges can touch
+constexpr int LU_NB = 64;                       // inner panel width
+constexpr int LU_NB2 = 512;                     // widest outer block (rank of the trailing update)
+constexpr int LU_ROWS = 256;                    // panel rows per workgroup (one per thread)
+constexpr int LU_HDR = 2;                       // slot header: |value|, row
+constexpr int LU_SLOT = LU_HDR + LU_NB;         // doubles per slot
+constexpr int LU_LIST = 2 * LU_NB;              // rows one block of 64 interchanges can touch
 constexpr int LU_LIST_WORDS = 1 + 2 * LU_LIST;  // count, destination rows, source rows
-constexpr int LU_SPIN_LIMIT = 1 << 24;       // default polls before a barrier wait gives up
+constexpr int LU_SPIN_LIMIT = 1 << 22;          // default polls before a wait gives up
 
 struct LuSync {
-    unsigned count;  // grid-barrier arrivals since the start of the factorisation
-    int err;         // set when a barrier wait gave up
-    int bad;         // the solve: an interchange outside 1..n was ignored
-    int pad;
+    int err;  // set when a panel wait gave up
+    int bad;  // the solve: an interchange outside 1..n was ignored
+    int pad[2];
 };
 
+// Panel slots are write-once per panel: reset to a signalling NaN (never
+// produced by arithmetic; published values are canonicalised so that an
+// input NaN cannot carry this payload), written with device-coherent stores
+// and polled with device-coherent loads until no value is the sentinel.
+__device__ __forceinline__ double lu_sentinel() { return __builtin_bit_cast(double, 0x7ff4d1e5a1f00d01ull); }
+__device__ __forceinline__ bool lu_is_sentinel(double v) {
+    return __builtin_bit_cast(unsigned long long, v) == 0x7ff4d1e5a1f00d01ull;
+}
+__device__ __forceinline__ double lu_canon(double v) { return v == v ? v : (double)NAN; }
 __device__ __forceinline__ double ld_dev(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ int ld_dev(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // (v, r) pairs: larger v wins, the smaller r on ties.  v < 0 marks "no candidate".
@@ -71,121 +93,177 @@ __device__ __forceinline__ void argmax_merge(double& v, int& r, double ov, int o
         r = orr;
     }
 }
-__device__ __forceinline__ void wave_argmax(double& v, int& r) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(v, off, 64);
-        const int orr = __shfl_xor(r, off, 64);
-        argmax_merge(v, r, ov, orr);
+
+// A double moved across lanes by a DPP pattern (both halves; every lane
+// reads a valid lane for the patterns used here).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+// max(v over the pairs of rows of 16 lanes that a permlane swap exchanges)
+template <bool B32>
+__device__ __forceinline__ double swap_max_f64(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+    const auto l = B32 ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
+                       : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = B32 ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
+                       : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const double d0 = __builtin_bit_cast(double, ((unsigned long long)h[0] << 32) | l[0]);
+    const double d1 = __builtin_bit_cast(double, ((unsigned long long)h[1] << 32) | l[1]);
+    return fmax(d0, d1);
+}
+// Largest v of the wave (no NaN among the values): quad, half-row and row
+// steps by DPP, then the two gfx950 row swaps.
+__device__ __forceinline__ double wave_max_f64(double v) {
+    v = fmax(v, dpp_f64<0xB1>(v));   // quad_perm [1,0,3,2]
+    v = fmax(v, dpp_f64<0x4E>(v));   // quad_perm [2,3,0,1]
+    v = fmax(v, dpp_f64<0x141>(v));  // row_half_mirror
+    v = fmax(v, dpp_f64<0x140>(v));  // row_mirror
+    v = swap_max_f64<false>(v);
+    return swap_max_f64<true>(v);
+}
+// Workgroup argmax of (v, r) over 256 threads (v >= 0 candidates, -1 none):
+// each wave takes its largest v and, among the lanes holding it, the first
+// lane's r (callers number r in lane order, so that is the smallest r); the
+// four wave results meet in LDS.  Every thread returns the same pair.
+__device__ __forceinline__ void block_argmax(double v, int r, double* rv, int* rr, double& ov, int& orr) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const double m = wave_max_f64(v);
+    const unsigned long long hit = __ballot(v == m);
+    const int first = __ffsll((long long)hit) - 1;
+    const int rw = __builtin_amdgcn_readlane(r, first);
+    if (lane == 0) {
+        rv[w] = m;
+        rr[w] = m >= 0.0 ? rw : INT_MAX;
     }
+    __syncthreads();
+    ov = rv[0];
+    orr = rr[0];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) argmax_merge(ov, orr, rv[q], rr[q]);
 }
 
 __global__ void k_lu_reset(LuSync* sy) {
-    if (threadIdx.x == 0) *sy = LuSync{0u, 0, 0, 0};
+    if (threadIdx.x == 0) *sy = LuSync{0, 0, {0, 0}};
 }
 
-// Panel factorisation (cooperative launch of G = ceil(m / 256) workgroups).
-// base: barrier arrivals of earlier panels of this factorisation.
-// slots: 2 x (G + 1) x LU_SLOT doubles (slot G: row j).
+__global__ __launch_bounds__(256) void k_lu_fill_sentinel(double* p, int64_t cnt) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256)
+        p[e] = lu_sentinel();
+}
+
+// Panel factorisation (cooperative launch of G = ceil(m / 256) workgroups,
+// thread t of workgroup q holding panel row 256 q + t in LDS).
+// cur: this panel's slots, LU_NB x gs entries of LU_SLOT doubles (entry
+// (j, q): workgroup q's candidate for column j; entry (j, gs - 1): row j);
+// nxt: the next panel's slots, whose entries this launch resets (workgroup q
+// those of workgroup q, workgroup 0 also the row-j entries).
 __global__ __launch_bounds__(256, 1) void k_getf2_panel(double* __restrict__ A, int64_t lda, int64_t n, int64_t k0,
-                                                        int nbw, double* slots, LuSync* sy, unsigned base,
+                                                        int nbw, double* cur, double* nxt, int gs, LuSync* sy,
                                                         int32_t* __restrict__ ipiv, int32_t* __restrict__ info,
                                                         int spin_limit) {
     __shared__ double P[LU_ROWS][LU_NB + 1];
-    __shared__ double urow[LU_NB], jrow[LU_NB];
+    __shared__ double urow[LU_NB], jrow[LU_NB], wrow[LU_NB];
     __shared__ double red_v[2][4];
     __shared__ int red_r[2][4];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, G = gridDim.x, wg = blockIdx.x;
+    const int tid = threadIdx.x, G = gridDim.x, wg = blockIdx.x;
+    const int jslot = gs - 1;
     const int64_t m = n - k0;
     const int64_t row0 = (int64_t)wg * LU_ROWS;  // first panel row (relative to k0) of this workgroup
     const int R = (int)(m - row0 < LU_ROWS ? m - row0 : LU_ROWS);
+    for (int e = tid; e < LU_NB * LU_SLOT; e += 256) {
+        const int j = e / LU_SLOT, x = e - j * LU_SLOT;
+        nxt[((size_t)j * gs + wg) * LU_SLOT + x] = lu_sentinel();
+        if (wg == 0) nxt[((size_t)j * gs + jslot) * LU_SLOT + x] = lu_sentinel();
+    }
     for (int c = 0; c < nbw; ++c)
         if (tid < R) P[tid][c] = A[idx(k0 + row0 + tid, k0 + c, lda)];
     __syncthreads();
-    bool gave_up = false;
+    // a spin limit of 0 (host setting) gives up every wait of a panel with
+    // more than one workgroup, without waiting
+    bool gave_up = spin_limit == 0 && G > 1;
+    if (gave_up && tid == 0) atomicExch(&sy->err, 1);
     for (int j = 0; j < nbw; ++j) {
-        double* sl = slots + (size_t)(j & 1) * (G + 1) * LU_SLOT;
+        double* E = cur + (size_t)j * gs * LU_SLOT;  // column j's entries
         // ---- this workgroup's candidate: rows >= j, NaN entries never win
         double v = -1.0;
-        int r = INT_MAX;
         if (tid < R && row0 + tid >= j) {
             const double a = fabs(P[tid][j]);
-            if (a == a) {
-                v = a;
-                r = tid;
-            }
+            if (a == a) v = a;
         }
-        wave_argmax(v, r);
-        if (lane == 0) {
-            red_v[0][w] = v;
-            red_r[0][w] = r;
-        }
-        __syncthreads();
-        v = red_v[0][0];
-        r = red_r[0][0];
-#pragma unroll
-        for (int q = 1; q < 4; ++q) argmax_merge(v, r, red_v[0][q], red_r[0][q]);
+        double bv;
+        int br;
+        block_argmax(v, tid, red_v[0], red_r[0], bv, br);
         // ---- publish it, and row j by its owner
-        double* me = sl + (size_t)wg * LU_SLOT;
-        if (tid == 0) {
-            me[0] = v;
-            me[1] = v >= 0.0 ? (double)(row0 + r) : -1.0;
-        }
-        if (v >= 0.0 && tid < nbw) me[LU_HDR + tid] = P[r][tid];
+        double* me = E + (size_t)wg * LU_SLOT;
         const bool ownj = j >= row0 && j < row0 + R;
-        if (ownj && tid < nbw) sl[(size_t)G * LU_SLOT + LU_HDR + tid] = P[j - row0][tid];
-        // ---- grid barrier: every thread's stores are made visible at device
-        // scope, then one arrival per workgroup; the wait is bounded (a flag
-        // set by any workgroup that gave up ends every other wait)
-        __threadfence();
-        __syncthreads();
+        if (bv >= 0.0 && tid < nbw) st_dev(&me[LU_HDR + tid], lu_canon(P[br][tid]));
+        if (ownj && tid < nbw) st_dev(&E[(size_t)jslot * LU_SLOT + LU_HDR + tid], lu_canon(P[j - row0][tid]));
         if (tid == 0) {
-            atomicAdd(&sy->count, 1u);
-            const unsigned target = base + (unsigned)(j + 1) * (unsigned)G;
-            for (int spins = 0;; ++spins) {
-                if (spin_limit == 0 && G > 1) {  // forced give-up (host setting)
-                    atomicExch(&sy->err, 1);
-                    break;
-                }
-                if (__hip_atomic_load(&sy->count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
-                if (gave_up || spins > spin_limit || ld_dev(&sy->err) != 0) {
-                    atomicExch(&sy->err, 1);
-                    gave_up = true;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
+            st_dev(&me[0], bv);
+            st_dev(&me[1], bv >= 0.0 ? (double)(row0 + br) : -1.0);
         }
-        __syncthreads();
-        __threadfence();
-        // ---- the winner over all workgroups (every workgroup alike): headers
-        // from the slots; row j's values meanwhile
+        // ---- every workgroup's header (a thread each), polled until written
         double hv = -1.0;
         int hr = INT_MAX;
-        if (tid < G) {
-            const double a = ld_dev(&sl[(size_t)tid * LU_SLOT]);
-            const double rr = ld_dev(&sl[(size_t)tid * LU_SLOT + 1]);
-            if (a >= 0.0 && rr >= (double)j && rr < (double)m) {
-                hv = a;
-                hr = (int)rr;
+        for (int spins = 0;; ++spins) {
+            bool ok = true;
+            hv = -1.0;
+            hr = INT_MAX;
+            if (tid < G) {
+                const double a = ld_dev(&E[(size_t)tid * LU_SLOT]);
+                const double rr = ld_dev(&E[(size_t)tid * LU_SLOT + 1]);
+                ok = !lu_is_sentinel(a) && !lu_is_sentinel(rr);
+                if (a >= 0.0 && rr >= (double)j && rr < (double)m) {
+                    hv = a;
+                    hr = (int)rr;
+                }
             }
+            if (__syncthreads_and(ok) || gave_up) break;
+            if ((spins & 31) == 31) {
+                const int e = (tid == 0) ? ld_dev(&sy->err) : 0;
+                if (__syncthreads_or(spins > spin_limit || e != 0)) {
+                    gave_up = true;
+                    if (tid == 0) atomicExch(&sy->err, 1);
+                    break;
+                }
+            }
+            __builtin_amdgcn_s_sleep(1);
         }
-        if (tid < nbw) jrow[tid] = ld_dev(&sl[(size_t)G * LU_SLOT + LU_HDR + tid]);
-        wave_argmax(hv, hr);
-        if (lane == 0) {
-            red_v[1][w] = hv;
-            red_r[1][w] = hr;
+        // ---- the winner (every workgroup alike; workgroup q's rows follow q)
+        double gv;
+        int gr;
+        block_argmax(hv, hr, red_v[1], red_r[1], gv, gr);
+        const int pw = gv >= 0.0 ? gr / LU_ROWS : 0;  // workgroup whose slot holds the candidate row
+        // ---- row j and the candidate row, polled until written
+        for (int spins = 0;; ++spins) {
+            bool ok = true;
+            if (tid < nbw) {
+                const double jr = ld_dev(&E[(size_t)jslot * LU_SLOT + LU_HDR + tid]);
+                const double wr = gv >= 0.0 ? ld_dev(&E[(size_t)pw * LU_SLOT + LU_HDR + tid]) : 0.0;
+                ok = !lu_is_sentinel(jr) && !lu_is_sentinel(wr);
+                jrow[tid] = jr;
+                wrow[tid] = wr;
+            }
+            if (__syncthreads_and(ok) || gave_up) break;
+            if ((spins & 31) == 31) {
+                const int e = (tid == 0) ? ld_dev(&sy->err) : 0;
+                if (__syncthreads_or(spins > spin_limit || e != 0)) {
+                    gave_up = true;
+                    if (tid == 0) atomicExch(&sy->err, 1);
+                    break;
+                }
+            }
+            __builtin_amdgcn_s_sleep(1);
         }
-        __syncthreads();
-        hv = red_v[1][0];
-        hr = red_r[1][0];
-#pragma unroll
-        for (int q = 1; q < 4; ++q) argmax_merge(hv, hr, red_v[1][q], red_r[1][q]);
         // a NaN diagonal entry stays the pivot (a sequential scan starting
-        // from it never replaces it); so does row j when nothing else qualifies
-        const int64_t p = (hv < 0.0 || jrow[j] != jrow[j]) ? (int64_t)j : (int64_t)hr;
-        const int pw = (int)(p / LU_ROWS);  // workgroup whose slot holds row p
-        if (tid < nbw) urow[tid] = (p == j) ? jrow[tid] : ld_dev(&sl[(size_t)pw * LU_SLOT + LU_HDR + tid]);
+        // from it never replaces it); so does row j when nothing qualifies
+        const int64_t p = (gv < 0.0 || jrow[j] != jrow[j]) ? (int64_t)j : (int64_t)gr;
+        if (tid < nbw) urow[tid] = (p == j) ? jrow[tid] : wrow[tid];
         __syncthreads();
         const double piv = urow[j];
         if (wg == 0 && tid == 0) {
@@ -201,6 +279,7 @@ __global__ __launch_bounds__(256, 1) void k_getf2_panel(double* __restrict__ A, 
         if (piv != 0.0 && tid < R && row0 + tid > j) {
             const double l = P[tid][j] / piv;
             P[tid][j] = l;
+#pragma unroll 8
             for (int c = j + 1; c < nbw; ++c) P[tid][c] = P[tid][c] - l * urow[c];
         }
         __syncthreads();
@@ -265,11 +344,12 @@ __device__ int lu_swap_list(const int32_t* __restrict__ ipiv, int64_t n, int64_t
     return cw + cnt;
 }
 
-// Interchanges of the panel at k0 (nbw of them) applied to columns
-// [0, ncols): 64 columns per workgroup, every touched value read into LDS
-// before any is written.
+// Interchanges of the panel at k0 (nbw of them) applied to the columns
+// [0, nleft) and [cr0, n): 64 columns per workgroup, every touched value read
+// into LDS before any is written.
 __global__ __launch_bounds__(256) void k_lu_swap_cols(double* __restrict__ A, int64_t lda, int64_t n, int64_t k0,
-                                                      int nbw, int64_t ncols, const int32_t* __restrict__ ipiv) {
+                                                      int nbw, int64_t nleft, int64_t cr0,
+                                                      const int32_t* __restrict__ ipiv) {
     __shared__ double V[LU_LIST][65];
     __shared__ int sdst[LU_LIST], ssrc[LU_LIST];
     __shared__ int s_cnt;
@@ -281,57 +361,67 @@ __global__ __launch_bounds__(256) void k_lu_swap_cols(double* __restrict__ A, in
     }
     __syncthreads();
     const int cnt = s_cnt;
+    const int64_t ncols = nleft + (n - cr0);
     const int64_t cb = (int64_t)blockIdx.x * 64;
     const int cw = (int)(ncols - cb < 64 ? ncols - cb : 64);
+    auto col = [&](int c) { return cb + c < nleft ? cb + c : cb + c - nleft + cr0; };
     for (int e = tid; e < LU_LIST * 64; e += 256) {
         const int t = e & (LU_LIST - 1), c = e >> 7;
-        if (t < cnt && c < cw && sdst[t] != ssrc[t]) V[t][c] = A[idx(ssrc[t], cb + c, lda)];
+        if (t < cnt && c < cw && sdst[t] != ssrc[t]) V[t][c] = A[idx(ssrc[t], col(c), lda)];
     }
     __syncthreads();
     for (int e = tid; e < LU_LIST * 64; e += 256) {
         const int t = e & (LU_LIST - 1), c = e >> 7;
-        if (t < cnt && c < cw && sdst[t] != ssrc[t]) A[idx(sdst[t], cb + c, lda)] = V[t][c];
+        if (t < cnt && c < cw && sdst[t] != ssrc[t]) A[idx(sdst[t], col(c), lda)] = V[t][c];
     }
 }
 
-// Block row right of a full-width panel at k0 (64 interchanges), 64 columns
-// per workgroup starting at column k0 + 64 + 64 * blockIdx.x: the panel's
-// interchanges, then U12 = L11^{-1} A12 (L11 = the panel's unit lower
-// 64 x 64 block) by forward substitution, one lane per column of wave 0,
-// stored over A12 and as U12^T into Ut (column j - (k0 + 64) of U12 is row
-// j - (k0 + 64) of Ut; leading dimension ldu).
+// Block row of a full-width panel at k0 (rows k0..k0+63) over the columns
+// [c0, c0 + ncols), 64 per workgroup: with SWAPS, the panel's interchanges
+// first (the block row's rows and every row they touch go through LDS; the
+// touched rows below the block row are written back); then
+// U12 = L11^{-1} A12 (L11 = the panel's unit lower 64 x 64 block) by forward
+// substitution, one lane per column of wave 0, stored over A12.
 __global__ __launch_bounds__(256) void k_lu_row_block(double* __restrict__ A, int64_t lda, int64_t n, int64_t k0,
-                                                      const int32_t* __restrict__ ipiv, double* __restrict__ Ut,
-                                                      int64_t ldu) {
+                                                      int64_t c0, int64_t ncols, int swaps,
+                                                      const int32_t* __restrict__ ipiv) {
     constexpr int nbw = LU_NB;
     __shared__ double V[LU_LIST][65];
     __shared__ double Lt[LU_NB][LU_NB + 1];  // Lt[c][r] = L11(r, c), r > c
     __shared__ int sdst[LU_LIST], ssrc[LU_LIST];
     __shared__ int s_cnt;
     const int tid = threadIdx.x;
-    if (tid < 64) {
+    if (swaps && tid < 64) {
         bool bad;
         const int cnt = lu_swap_list(ipiv, n, k0, nbw, sdst, ssrc, bad);
         if (tid == 0) s_cnt = cnt;
     }
-    const int64_t cb = k0 + nbw + (int64_t)blockIdx.x * 64;
-    const int cw = (int)(n - cb < 64 ? n - cb : 64);
+    const int64_t cb = c0 + (int64_t)blockIdx.x * 64;
+    const int cw = (int)(c0 + ncols - cb < 64 ? c0 + ncols - cb : 64);
     for (int e = tid; e < LU_NB * LU_NB; e += 256) {
         const int r = e & 63, c = e >> 6;
         if (r > c) Lt[c][r] = A[idx(k0 + r, k0 + c, lda)];
     }
     __syncthreads();
-    const int cnt = s_cnt;
-    // every touched row's values (the block row's own rows included) into V
-    for (int e = tid; e < LU_LIST * 64; e += 256) {
-        const int t = e & (LU_LIST - 1), c = e >> 7;
-        if (t < cnt && c < cw) V[t][c] = A[idx(ssrc[t], cb + c, lda)];
-    }
-    __syncthreads();
-    // rows below the block row that received another row's values
-    for (int e = tid; e < LU_LIST * 64; e += 256) {
-        const int t = e & (LU_LIST - 1), c = e >> 7;
-        if (t >= nbw && t < cnt && c < cw && sdst[t] != ssrc[t]) A[idx(sdst[t], cb + c, lda)] = V[t][c];
+    if (swaps) {
+        const int cnt = s_cnt;
+        // every touched row's values (the block row's own rows included) into V
+        for (int e = tid; e < LU_LIST * 64; e += 256) {
+            const int t = e & (LU_LIST - 1), c = e >> 7;
+            if (t < cnt && c < cw) V[t][c] = A[idx(ssrc[t], cb + c, lda)];
+        }
+        __syncthreads();
+        // rows below the block row that received another row's values
+        for (int e = tid; e < LU_LIST * 64; e += 256) {
+            const int t = e & (LU_LIST - 1), c = e >> 7;
+            if (t >= nbw && t < cnt && c < cw && sdst[t] != ssrc[t]) A[idx(sdst[t], cb + c, lda)] = V[t][c];
+        }
+    } else {
+        for (int e = tid; e < LU_NB * 64; e += 256) {
+            const int r = e & 63, c = e >> 6;
+            if (c < cw) V[r][c] = A[idx(k0 + r, cb + c, lda)];
+        }
+        __syncthreads();
     }
     // V[0..64) holds the interchanged block row; substitution down each column
     if (tid < 64) {
@@ -346,11 +436,6 @@ __global__ __launch_bounds__(256) void k_lu_row_block(double* __restrict__ A, in
         }
 #pragma unroll
         for (int r = 0; r < LU_NB; ++r) V[r][tid] = b[r];
-        if (tid < cw) {
-            const int64_t jc = cb + tid - (k0 + LU_NB);
-#pragma unroll
-            for (int r = 0; r < LU_NB; ++r) Ut[idx(jc, r, ldu)] = b[r];
-        }
     }
     __syncthreads();
     for (int e = tid; e < LU_NB * 64; e += 256) {
@@ -359,20 +444,32 @@ __global__ __launch_bounds__(256) void k_lu_row_block(double* __restrict__ A, in
     }
 }
 
-// C (m x nn, ldc) -= X (m x kdim, ldx) Zt^T with Zt nn x kdim (ldz): 128 x 128
-// output tiles over the whole grid, tiles taken column by column with
-// consecutive runs per XCD; each wave computes a 64 x 64 quarter, C loaded
-// up front (the k-loop is short), operands through a ring of four k-steps.
-// The host keeps every byte offset below 2^31 and kdim a multiple of 16.
+// C (m x nn, ldc) -= X Z with X m x kdim (column-major, ldx) and Z kdim x nn
+// (column-major, ldz: the block row U12 as it lies in A).  128 x 128 output
+// tiles, each XCD taking a contiguous run of tiles numbered in bands of 8
+// tile rows, column by column inside a band (the workgroups an XCD holds at
+// once cover an 8 x 8 patch and share its operand blocks in L2); each wave
+// computes a 64 x 64 quarter.  Operands stream straight into registers
+// through a ring of four k-steps: lane (i, g) of k-step s reads X row
+// 16 b + i, column 4 s + g, and Z column 16 b + i, row 4 s + g (32 contiguous
+// bytes of a column per 4 lanes).  FOLD (rank 256): C is folded into the
+// k-loop one 16 x 16 piece at a time; otherwise (rank 64) C is loaded up
+// front.  The accumulators hold X Z - C and are negated as they are stored.
+// The host keeps every byte offset below 2^31 and kdim a multiple of 16
+// (of 256 with FOLD).
+template <bool FOLD>
 __global__ __launch_bounds__(256, 2) void k_gemm_sub(double* __restrict__ C, int64_t ldc, const double* __restrict__ X,
-                                                     int64_t ldx, const double* __restrict__ Zt, int64_t ldz, int64_t m,
+                                                     int64_t ldx, const double* __restrict__ Z, int64_t ldz, int64_t m,
                                                      int64_t nn, int kdim) {
     constexpr int ES = 8, RG = 4;
     const int64_t TI = (m + 127) / 128, TJ = (nn + 127) / 128, ntiles = TI * TJ;
     const int64_t per = gridDim.x / 8;
     const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (t >= ntiles) return;
-    const int64_t I = t % TI, J = t / TI;
+    const int64_t band = t / (8 * TJ), rem = t - band * 8 * TJ;
+    const int64_t bh = TI - band * 8 < 8 ? TI - band * 8 : 8;
+    const int64_t I = __builtin_amdgcn_readfirstlane((int)(band * 8 + rem % bh));
+    const int64_t J = __builtin_amdgcn_readfirstlane((int)(rem / bh));
     const int tid = threadIdx.x, l = tid & 63, i = l & 15, g = l >> 4;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = w >> 1, wc = w & 1;
@@ -389,23 +486,25 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sub(double* __restrict__ C, int
         const int rr = min(16 * bi + i, rmax), cc = min(16 * bj + tcol<double>(g, r), cmax);
         return (rr + cc * lc) * ES;
     };
-    // accumulators hold X Zt^T - C (negated as they are stored)
+    auto c_load = [&](int bi, int bj, int r) -> double {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(crs, c_off(bi, bj, r), 0, 0));
+    };
     f64x4 acc[4][4];
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                acc[bi][bj][r] =
-                    -__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(crs, c_off(bi, bj, r), 0, 0));
-    const __amdgpu_buffer_rsrc_t xrs = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, 0x7fffffff, 0x00020000);
-    const __amdgpu_buffer_rsrc_t zrs = __builtin_amdgcn_make_buffer_rsrc((void*)Zt, (short)0, 0x7fffffff, 0x00020000);
+            for (int r = 0; r < 4; ++r) acc[bi][bj][r] = FOLD ? 0.0 : -c_load(bi, bj, r);
+    const __amdgpu_buffer_rsrc_t xrs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(X + sr0), (short)0, 0x7fffffff, 0x00020000);
+    const __amdgpu_buffer_rsrc_t zrs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(Z + idx(0, sc0, ldz)), (short)0, 0x7fffffff, 0x00020000);
     int xo[4], zo[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        xo[b] = ((int)sr0 + min(16 * b + i, rmax) + g * lx) * ES;
-        zo[b] = ((int)sc0 + min(16 * b + i, cmax) + g * lz) * ES;
+        xo[b] = (min(16 * b + i, rmax) + g * lx) * ES;
+        zo[b] = (min(16 * b + i, cmax) * lz + g) * ES;
     }
     const int nks = kdim / 4;
     double xq[RG][4], zq[RG][4];
@@ -415,13 +514,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sub(double* __restrict__ C, int
         for (int b = 0; b < 4; ++b) {
             xq[slot][b] =
                 __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(xrs, xo[b], kk * 4 * lx * ES, 0));
-            zq[slot][b] =
-                __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(zrs, zo[b], kk * 4 * lz * ES, 0));
+            zq[slot][b] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(zrs, zo[b], kk * 4 * ES, 0));
         }
     };
 #pragma unroll
     for (int p = 0; p < RG - 1; ++p) fetch(p, p);
-    for (int ks = 0; ks < nks; ks += RG) {
+    auto body = [&](int ks) {
 #pragma unroll
         for (int s = 0; s < RG; ++s) {
             fetch((s + RG - 1) % RG, ks + s + RG - 1);
@@ -430,6 +528,20 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sub(double* __restrict__ C, int
 #pragma unroll
                 for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mma_xzt(acc[bi][bj], xq[s][bi], zq[s][bj]);
         }
+    };
+    if constexpr (FOLD) {
+        const int per_q = nks / (16 * RG);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            f64x4 cv;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cv[r] = c_load(q >> 2, q & 3, r);
+            for (int u = 0; u < per_q; ++u) body((q * per_q + u) * RG);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[q >> 2][q & 3][r] -= cv[r];
+        }
+    } else {
+        for (int ks = 0; ks < nks; ks += RG) body(ks);
     }
     typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
 #pragma unroll
@@ -443,7 +555,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sub(double* __restrict__ C, int
                                                           c_off(bi, bj, r), 0, 0);
 }
 
-// After the factorisation: a panel barrier that gave up turns A into quiet
+// After the factorisation: a panel wait that gave up turns A into quiet
 // NaNs and info into MG_INFO_SOLVE_ABORTED.
 __global__ __launch_bounds__(256) void k_lu_check(double* A, int64_t lda, int64_t n, const LuSync* sy, int32_t* info) {
     if (ld_dev(&sy->err) == 0) return;
@@ -508,63 +620,118 @@ __global__ __launch_bounds__(256) void k_lu_solve_check(double* B, int64_t ldb, 
 
 static int panel_groups(int64_t m) { return (int)cdiv(m, LU_ROWS); }
 
+// Workspace: two slot sets (LU_NB x (G + 1) entries each, G the first
+// panel's workgroups) and the sync words.
+static size_t slot_set_doubles(int64_t n) { return (size_t)LU_NB * (panel_groups(n) + 1) * LU_SLOT; }
+
 size_t getrf_work_bytes(int64_t n) {
     if (n == 0) return 0;
-    const int gmax = panel_groups(n);
-    return align_up((size_t)2 * (gmax + 1) * LU_SLOT * 8, 256) + 256 + align_up((size_t)n * LU_NB * 8, 256);
+    return align_up(2 * slot_set_doubles(n) * 8, 256) + 256;
+}
+
+template <bool FOLD>
+static mg_status gemm_sub(hipStream_t st, double* C, int64_t ldc, const double* X, int64_t ldx, const double* Z,
+                          int64_t ldz, int64_t m, int64_t nn, int kdim) {
+    if (m <= 0 || nn <= 0) return MG_OK;
+    const int64_t tiles = cdiv(m, 128) * cdiv(nn, 128);
+    hipLaunchKernelGGL((k_gemm_sub<FOLD>), dim3((unsigned)(8 * cdiv(tiles, 8))), dim3(256), 0, st, C, ldc, X, ldx, Z,
+                       ldz, m, nn, kdim);
+    MG_LAUNCH_CHECK();
+    return MG_OK;
 }
 
 mg_status getrf_impl(mg_handle_t h, int64_t n, double* A, int64_t lda, int32_t* ipiv, void* work, int32_t* info) {
     hipStream_t st = h->stream;
     mg_status rc = set_info_zero(st, info);
     if (rc != MG_OK || n == 0) return rc;
-    // 32-bit buffer offsets of the update's operands and C quarters
-    if (((n + (int64_t)(LU_NB + 64) * lda) * 8 >= ((int64_t)1 << 31) - 65536) ||
-        ((int64_t)n * LU_NB * 8 >= ((int64_t)1 << 31) - 65536))
-        return MG_ERR_UNSUPPORTED;
+    // 32-bit buffer offsets of the update's operands (X: up to 512 columns from its
+    // base row; Z and C: 64 columns from a wave's base column)
+    if ((n + (int64_t)(LU_NB2 + 64) * lda) * 8 >= ((int64_t)1 << 31) - 65536) return MG_ERR_UNSUPPORTED;
+    const int64_t nb2 = (h->nb == 256 || h->nb == 512) ? h->nb : (n >= 16384 ? 512 : 256);
     if (panel_groups(n) > h->cu_count) return MG_ERR_UNSUPPORTED;  // co-residency of the cooperative panel
-    char* base = (char*)work;
-    double* slots = (double*)base;
-    LuSync* sy = (LuSync*)(base + align_up((size_t)2 * (panel_groups(n) + 1) * LU_SLOT * 8, 256));
-    double* Ut = (double*)((char*)sy + 256);
+    const int gs = panel_groups(n) + 1;
+    double* sets[2] = {(double*)work, (double*)work + slot_set_doubles(n)};
+    LuSync* sy = (LuSync*)((char*)work + align_up(2 * slot_set_doubles(n) * 8, 256));
     int lim = h->spin_limit < 0 ? LU_SPIN_LIMIT : h->spin_limit;
     hipLaunchKernelGGL(k_lu_reset, dim3(1), dim3(64), 0, st, sy);
     MG_LAUNCH_CHECK();
-    unsigned arrivals = 0;
-    for (int64_t k0 = 0; k0 < n; k0 += LU_NB) {
-        int nbw = (int)std::min<int64_t>(LU_NB, n - k0);
-        const int64_t m = n - k0;
-        const int G = panel_groups(m);
-        if ((rc = prof_begin(h, MG_PROF_LU_PANEL, st))) return rc;
-        void* args[] = {(void*)&A,  (void*)&lda,      (void*)&n,    (void*)&k0,   (void*)&nbw, (void*)&slots,
-                        (void*)&sy, (void*)&arrivals, (void*)&ipiv, (void*)&info, (void*)&lim};
-        MG_HIP(hipLaunchCooperativeKernel((const void*)k_getf2_panel, dim3(G), dim3(256), args, 0, st));
-        const double md = (double)m, bd = (double)nbw;
-        if ((rc = prof_end(h, MG_PROF_LU_PANEL, md * bd * bd - bd * bd * bd / 3.0, 2.0 * md * bd * 8.0, st)))
-            return rc;
-        arrivals += (unsigned)G * (unsigned)nbw;
-        if (k0 > 0) {
-            hipLaunchKernelGGL(k_lu_swap_cols, dim3((unsigned)cdiv(k0, 64)), dim3(256), 0, st, A, lda, n, k0, nbw, k0,
-                               (const int32_t*)ipiv);
+    const int64_t nfill = (int64_t)(2 * slot_set_doubles(n));
+    hipLaunchKernelGGL(k_lu_fill_sentinel, dim3((unsigned)std::min<int64_t>(cdiv(nfill, 256), 1024)), dim3(256), 0,
+                       st, sets[0], nfill);
+    MG_LAUNCH_CHECK();
+    int set = 0;
+    for (int64_t K0 = 0; K0 < n; K0 += nb2) {
+        const int64_t W = std::min<int64_t>(nb2, n - K0);  // < nb2 only for the last outer block
+        const int64_t kend = K0 + W;
+        // the outer block column, inner panel by inner panel; the columns
+        // right of it only take the interchanges (no update of this outer
+        // block has reached them yet, so moving their rows is consistent)
+        for (int64_t k0 = K0; k0 < kend; k0 += LU_NB) {
+            int nbw = (int)std::min<int64_t>(LU_NB, kend - k0);
+            const int64_t m = n - k0;
+            const int G = panel_groups(m);
+            if ((rc = prof_begin(h, MG_PROF_LU_PANEL, st))) return rc;
+            double* cur = sets[set];
+            double* nxt = sets[set ^ 1];
+            int gsv = gs;
+            void* args[] = {(void*)&A,   (void*)&lda, (void*)&n,  (void*)&k0,   (void*)&nbw,  (void*)&cur,
+                            (void*)&nxt, (void*)&gsv, (void*)&sy, (void*)&ipiv, (void*)&info, (void*)&lim};
+            MG_HIP(hipLaunchCooperativeKernel((const void*)k_getf2_panel, dim3(G), dim3(256), args, 0, st));
+            const double md = (double)m, bd = (double)nbw;
+            if ((rc = prof_end(h, MG_PROF_LU_PANEL, md * bd * bd - bd * bd * bd / 3.0, 2.0 * md * bd * 8.0, st)))
+                return rc;
+            set ^= 1;
+            const int64_t nsw = k0 + (n - kend);
+            if (nsw > 0) {
+                hipLaunchKernelGGL(k_lu_swap_cols, dim3((unsigned)cdiv(nsw, 64)), dim3(256), 0, st, A, lda, n, k0, nbw,
+                                   k0, kend, (const int32_t*)ipiv);
+                MG_LAUNCH_CHECK();
+            }
+            const int64_t k1 = k0 + nbw;
+            if (k1 >= kend) continue;  // nbw == LU_NB below
+            hipLaunchKernelGGL(k_lu_row_block, dim3((unsigned)cdiv(kend - k1, 64)), dim3(256), 0, st, A, lda, n, k0,
+                               k1, kend - k1, 1, (const int32_t*)ipiv);
             MG_LAUNCH_CHECK();
-        }
-        const int64_t nr = n - k0 - nbw;
-        if (nr > 0) {
-            // nr > 0 implies a full-width panel (nbw == LU_NB)
-            hipLaunchKernelGGL(k_lu_row_block, dim3((unsigned)cdiv(nr, 64)), dim3(256), 0, st, A, lda, n, k0,
-                               (const int32_t*)ipiv, Ut, nr);
-            MG_LAUNCH_CHECK();
-            const int64_t tiles = cdiv(nr, 128) * cdiv(nr, 128);
-            if ((rc = prof_begin(h, MG_PROF_LU_UPDATE, st))) return rc;
-            hipLaunchKernelGGL(k_gemm_sub, dim3((unsigned)(8 * cdiv(tiles, 8))), dim3(256), 0, st,
-                               A + idx(k0 + nbw, k0 + nbw, lda), lda, (const double*)(A + idx(k0 + nbw, k0, lda)), lda,
-                               (const double*)Ut, nr, nr, nr, LU_NB);
-            MG_LAUNCH_CHECK();
-            const double nd = (double)nr;
-            if ((rc = prof_end(h, MG_PROF_LU_UPDATE, 2.0 * nd * nd * LU_NB, (2.0 * nd * nd + 2.0 * nd * LU_NB) * 8.0,
-                               st)))
+            // rank-64 update of the rest of the outer block column
+            if ((rc = prof_begin(h, MG_PROF_TRAILING_NARROW, st))) return rc;
+            if ((rc = gemm_sub<false>(st, A + idx(k1, k1, lda), lda, A + idx(k1, k0, lda), lda, A + idx(k0, k1, lda),
+                                      lda, n - k1, kend - k1, LU_NB)))
+                return rc;
+            const double a1 = (double)(n - k1) * (double)(kend - k1);
+            if ((rc = prof_end(h, MG_PROF_TRAILING_NARROW, 2.0 * LU_NB * a1,
+                               (2.0 * a1 + LU_NB * (double)(n - k1 + kend - k1)) * 8.0, st)))
                 return rc;
         }
+        const int64_t mr = n - kend;
+        if (mr <= 0) continue;
+        // the outer block row right of it: U12 = L11^{-1} A12 with the
+        // nb2 x nb2 unit lower L11, by 64-row blocks (substitution, then a
+        // rank-64 update of the block rows below inside the outer block)
+        for (int64_t k0 = K0; k0 < kend; k0 += LU_NB) {
+            hipLaunchKernelGGL(k_lu_row_block, dim3((unsigned)cdiv(mr, 64)), dim3(256), 0, st, A, lda, n, k0, kend, mr,
+                               0, (const int32_t*)ipiv);
+            MG_LAUNCH_CHECK();
+            const int64_t k1 = k0 + LU_NB;
+            if (k1 < kend) {
+                if ((rc = prof_begin(h, MG_PROF_TRAILING_NARROW, st))) return rc;
+                if ((rc = gemm_sub<false>(st, A + idx(k1, kend, lda), lda, A + idx(k1, k0, lda), lda,
+                                          A + idx(k0, kend, lda), lda, kend - k1, mr, LU_NB)))
+                    return rc;
+                const double a2 = (double)(kend - k1) * (double)mr;
+                if ((rc = prof_end(h, MG_PROF_TRAILING_NARROW, 2.0 * LU_NB * a2,
+                                   (2.0 * a2 + LU_NB * (double)(kend - k1 + mr)) * 8.0, st)))
+                    return rc;
+            }
+        }
+        // rank-nb2 update of the trailing matrix
+        if ((rc = prof_begin(h, MG_PROF_LU_UPDATE, st))) return rc;
+        if ((rc = gemm_sub<true>(st, A + idx(kend, kend, lda), lda, A + idx(kend, K0, lda), lda,
+                                 A + idx(K0, kend, lda), lda, mr, mr, (int)W)))
+            return rc;
+        const double md = (double)mr;
+        if ((rc = prof_end(h, MG_PROF_LU_UPDATE, 2.0 * (double)W * md * md, (2.0 * md * md + 2.0 * (double)W * md) * 8.0,
+                           st)))
+            return rc;
     }
     hipLaunchKernelGGL(k_lu_check, dim3((unsigned)std::min<int64_t>(cdiv(n * n, 256), 1024)), dim3(256), 0, st, A,
                        lda, n, (const LuSync*)sy, info);

@@ -78,6 +78,35 @@ def test_getrs_matches_oracle(mg, orc, n, nrhs):
     assert np.all(orc.backward_error_gen(A, X, B) <= 1e-14)
 
 
+@pytest.fixture
+def outer_width(mg):
+    """Select the factorisation's outer block width (256 or 512) for a test."""
+    h = mg.handle()
+    yield h.set_block_size
+    h.set_block_size(0)
+
+
+@pytest.mark.parametrize("nb2", [256, 512])
+@pytest.mark.parametrize("n", [513, 1100])
+def test_outer_block_widths(mg, orc, substitution, outer_width, n, nb2):
+    """Both outer widths, ragged orders spanning several outer blocks: the
+    dyadic family bit-identical to the oracle, a Gaussian A with the
+    oracle's pivots."""
+    outer_width(nb2)
+    print(f"[lu] outer width {nb2} n={n}", flush=True)
+    _, _, _, A = synth.lu_exact(n, 900 + n)
+    LU, ipiv, info = mg.getrf(_dev(A))
+    LUo, ipo, _ = orc.getrf(A)
+    assert int(info) == 0
+    assert np.array_equal(ipiv.cpu().numpy(), ipo)
+    assert np.array_equal(LU.cpu().numpy(), LUo)
+    G = synth.general_matrix(n, 901 + n)
+    LU, ipiv, info = mg.getrf(_dev(G))
+    LUo, ipo, _ = orc.getrf(G)
+    assert np.array_equal(ipiv.cpu().numpy(), ipo)
+    assert _rel(LU.cpu().numpy(), LUo) <= 1e-12
+
+
 def test_inverse_mode_backward_error(mg, orc):
     n, nrhs = 700, 5
     A = synth.general_matrix(n, 71)
