@@ -200,14 +200,20 @@ def _p(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def bench_mixed(torch, mg, synth, n: int, nrhs: int, cond: float, precision: str, reps: int, seed: int = 9500):
+def bench_mixed(torch, mg, synth, n: int, nrhs: int, cond: float, precision: str, reps: int, seed: int = 9500,
+                gram: bool = False):
     """Mixed precision + FP64 refinement to eta <= 1e-12 on A = Q diag(lambda) Q^T
     (Haar Q, log-spaced spectrum with exact cond).  Time covers the cast, the
     low-precision factor, every refinement step and any fallback; TFLOP/s uses
-    the same nominal FP64 count as the FP64 path."""
+    the same nominal FP64 count as the FP64 path.  gram: A = G G^T/n + delta I
+    with the same cond instead (no QR in the generator; for counter runs,
+    whose profiler does not survive the vendor QR)."""
     from paper_2601_14466_amd import _lib
-    log(f"[bench] mixed {precision}: generating n={n} nrhs={nrhs} cond={cond:g} (Haar)")
-    A = synth.torch_haar_spd(n, cond, seed + n, log=lambda m: log(f"[bench] mixed {precision}: {m}"))
+    log(f"[bench] mixed {precision}: generating n={n} nrhs={nrhs} cond={cond:g} ({'Gram' if gram else 'Haar'})")
+    if gram:
+        A = synth.torch_gram_spd_cond(n, seed + n, cond)
+    else:
+        A = synth.torch_haar_spd(n, cond, seed + n, log=lambda m: log(f"[bench] mixed {precision}: {m}"))
     Xt = synth.torch_normal((n, nrhs), seed + 1 + n)   # A symmetric: row-major bytes == column-major
     Bc = synth.torch_matmul_rows(A, Xt).T.contiguous()
     Xc = torch.empty_like(Bc)
@@ -661,9 +667,9 @@ LEGS = ("mixed_fp32", "mixed_bf16", "mixed_fp32_n65536", "small_n1024", "batched
 
 def run_extra(key, torch, mg, synth, args):
     if key == "mixed_fp32":
-        return bench_mixed(torch, mg, synth, args.n, 8, 1e4, "fp32", 3)
+        return bench_mixed(torch, mg, synth, args.n, 8, 1e4, "fp32", 3, gram=args.mixed_input == "gram")
     if key == "mixed_bf16":
-        return bench_mixed(torch, mg, synth, args.n, 8, 1e2, "bf16", 3)
+        return bench_mixed(torch, mg, synth, args.n, 8, 1e2, "bf16", 3, gram=args.mixed_input == "gram")
     if key == "mixed_fp32_n65536":
         return bench_mixed(torch, mg, synth, 65536, 8, 1e4, "fp32", 1)
     if key == "small_n1024":
@@ -705,6 +711,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision, batched, adjoint and n=1024 measurements")
+    ap.add_argument("--mixed-input", choices=("haar", "gram"), default="haar",
+                    help="input of the n = 32768 mixed legs (gram: no QR in the generator, for counter runs)")
     ap.add_argument("--only", choices=LEGS, default=None,
                     help="run one extra measurement alone (no headline leg, no CPU baseline), e.g. for profiling")
     args = ap.parse_args()
