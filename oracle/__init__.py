@@ -33,6 +33,11 @@ optionally with log det):
 * ``getrf`` / ``getrs`` / ``lu_solve`` -- the paper's general solve: P A = L U
                    by partial pivoting (LAPACK ipiv convention), then the
                    swaps, L y = P b and U x = y.
+* ``zpotrf`` / ``zpotrs`` / ``zposv`` / ``backward_error_z`` -- the complex
+                   Hermitian case (the paper lists complex64 and complex128):
+                   A = L L^H, L lower with a real positive diagonal, then
+                   L y = b, L^H x = y; backward error with the complex
+                   modulus.
 * ``potrf_backward`` -- gradient with respect to A of f(chol(A)) from
                    gL = df/dL: sym(L^{-T} Phi(L^T gL) L^{-1}), Phi the lower
                    triangle with the diagonal halved (Murray 2016; the paper
@@ -114,6 +119,12 @@ def _load():
     lib.or_getrs.restype = None
     lib.or_residual_gen.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64, _dp]
     lib.or_residual_gen.restype = ctypes.c_double
+    lib.or_zpotrf.argtypes = [_i64, _dp, _i64]
+    lib.or_zpotrf.restype = _i64
+    lib.or_zpotrs.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64]
+    lib.or_zpotrs.restype = None
+    lib.or_residual_z.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64, _dp]
+    lib.or_residual_z.restype = ctypes.c_double
     lib.or_num_threads.argtypes = []
     lib.or_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -130,6 +141,10 @@ def _ptr(a: np.ndarray, t=_dp):
 
 def _ld(a: np.ndarray) -> int:
     return max(1, a.shape[0])
+
+
+def _c128(a) -> np.ndarray:
+    return np.asfortranarray(np.asarray(a, dtype=np.complex128))
 
 
 def _as2d(b):
@@ -384,3 +399,51 @@ def gp_loglik_grad(A, Y, M=None, g=None):
     dA = 0.5 * (alpha * gv) @ alpha.T - 0.5 * gv.sum() * Ainv
     dY = -alpha * gv
     return dA, (dY.ravel() if flat else dY), (-dY.ravel() if flat else -dY), 0
+
+
+# ------------------------------------------------------------ complex Hermitian
+
+
+def zpotrf(A):
+    """Return (L, info): complex Hermitian A = L L^H, L lower with a real
+    positive diagonal (only the lower triangle of A is read; the imaginary
+    part of its diagonal is ignored).  Entries above the diagonal of the
+    returned array are those of A."""
+    lib = _load()
+    W = _c128(A).copy(order="F")
+    info = lib.or_zpotrf(W.shape[0], W.ctypes.data_as(_dp), _ld(W))
+    return W, int(info)
+
+
+def zpotrs(L, B):
+    """X with L L^H X = B from zpotrf's L."""
+    lib = _load()
+    Lf = _c128(L)
+    B2, flat = _as2d(B)
+    X = _c128(B2).copy(order="F")
+    n, nrhs = X.shape
+    lib.or_zpotrs(n, nrhs, Lf.ctypes.data_as(_dp), _ld(Lf), X.ctypes.data_as(_dp), _ld(X))
+    return X.ravel() if flat else X
+
+
+def zposv(A, B):
+    """Return (X, info) for a complex Hermitian positive-definite A X = B."""
+    L, info = zpotrf(A)
+    if info:
+        return np.array(B, dtype=np.complex128, copy=True), info
+    return zpotrs(L, B), 0
+
+
+def backward_error_z(A, X, B) -> np.ndarray:
+    """Per-column normwise backward error of A X = B, A Hermitian from its
+    lower triangle (extended precision, complex modulus)."""
+    lib = _load()
+    Af = _c128(A)
+    X2, _ = _as2d(X)
+    B2, _ = _as2d(B)
+    Xf, Bf = _c128(X2), _c128(B2)
+    n, nrhs = Xf.shape
+    eta = np.zeros(nrhs, dtype=np.float64)
+    lib.or_residual_z(n, nrhs, Af.ctypes.data_as(_dp), _ld(Af), Xf.ctypes.data_as(_dp), _ld(Xf),
+                      Bf.ctypes.data_as(_dp), _ld(Bf), _ptr(eta))
+    return eta

@@ -49,6 +49,16 @@
  *                swapped with row k); info = first k whose pivot is exactly
  *                zero (elimination goes on past it, as LAPACK's xGETRF).
  *                getrs applies the swaps to B, then L y = P b, U x = y.
+ *   or_zpotrf / or_zpotrs: the complex Hermitian case of the same solve (the
+ *                paper lists complex64 and complex128 for its routines): A =
+ *                L L^H with L lower, real positive diagonal; column j of L:
+ *                L_jj = sqrt(Re a_jj - sum_{k<j} |l_jk|^2), l_ij = (a_ij -
+ *                sum_{k<j} l_ik conj(l_jk)) / L_jj (the imaginary part of the
+ *                diagonal is not read, as LAPACK's ZPOTRF); info as or_potrf.
+ *                zpotrs: L y = b, then L^H x = y.  or_residual_z: the
+ *                per-column normwise backward error of A X = B with the full
+ *                Hermitian A rebuilt from its lower triangle, |.| the complex
+ *                modulus, in extended precision.
  *   or_potrf_backward: adjoint of L = chol(A) (the paper is silent; the
  *                result is Murray, "Differentiation of the Cholesky
  *                decomposition", 2016).  From A = L L^T,
@@ -67,6 +77,7 @@
  * Build with -ffp-contract=off so that every a - b*c is two roundings, as
  * written.
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -694,6 +705,95 @@ double or_residual_gen(int64_t n, int64_t nrhs, const double *A, int64_t lda,
                 xmax = fabsl((long double)AT(X, ldx, i, r));
             if (fabsl((long double)AT(B, ldb, i, r)) > bmax)
                 bmax = fabsl((long double)AT(B, ldb, i, r));
+        }
+        long double den = anorm * xmax + bmax;
+        eta[r] = (double)(den > 0.0L ? rmax / den : 0.0L);
+    }
+    return (double)anorm;
+}
+
+/* ---------------------------------------------------- complex Hermitian */
+int64_t or_zpotrf(int64_t n, double complex *A, int64_t lda)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        /* column j, rows j..n-1, minus sum_{k<j} L(i,k) conj(L(j,k)), k increasing */
+        int64_t m = n - j;
+#pragma omp parallel if (m * j > 65536)
+        {
+            int nt = omp_get_num_threads(), t = omp_get_thread_num();
+            int64_t i0 = j + (m * t) / nt, i1 = j + (m * (t + 1)) / nt;
+            for (int64_t k = 0; k < j; ++k) {
+                double complex cjk = conj(AT(A, lda, j, k));
+                for (int64_t i = i0; i < i1; ++i)
+                    AT(A, lda, i, j) = AT(A, lda, i, j) - AT(A, lda, i, k) * cjk;
+            }
+        }
+        /* the diagonal is real: its imaginary part is neither read nor kept */
+        double d = creal(AT(A, lda, j, j));
+        if (!(d > 0.0))
+            return j + 1;
+        d = sqrt(d);
+        AT(A, lda, j, j) = d;
+        for (int64_t i = j + 1; i < n; ++i)
+            AT(A, lda, i, j) = AT(A, lda, i, j) / d;
+    }
+    return 0;
+}
+
+void or_zpotrs(int64_t n, int64_t nrhs, const double complex *L, int64_t lda, double complex *B, int64_t ldb)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrhs; ++r) {
+        double complex *b = &AT(B, ldb, 0, r);
+        for (int64_t i = 0; i < n; ++i) { /* L y = b */
+            double complex v = b[i];
+            for (int64_t k = 0; k < i; ++k)
+                v = v - AT(L, lda, i, k) * b[k];
+            b[i] = v / creal(AT(L, lda, i, i));
+        }
+        for (int64_t i = n - 1; i >= 0; --i) { /* L^H x = y */
+            double complex v = b[i];
+            for (int64_t k = i + 1; k < n; ++k)
+                v = v - conj(AT(L, lda, k, i)) * b[k];
+            b[i] = v / creal(AT(L, lda, i, i));
+        }
+    }
+}
+
+/* entry (i, j) of the Hermitian matrix whose lower triangle is stored */
+static long double complex herm_at(const double complex *A, int64_t lda, int64_t i, int64_t j)
+{
+    if (i == j)
+        return (long double)creal(AT(A, lda, i, i));
+    if (i > j)
+        return (long double complex)AT(A, lda, i, j);
+    return conjl((long double complex)AT(A, lda, j, i));
+}
+
+double or_residual_z(int64_t n, int64_t nrhs, const double complex *A, int64_t lda,
+                     const double complex *X, int64_t ldx, const double complex *B, int64_t ldb, double *eta)
+{
+    long double anorm = 0.0L;
+    for (int64_t i = 0; i < n; ++i) {
+        long double s = 0.0L;
+        for (int64_t j = 0; j < n; ++j)
+            s += cabsl(herm_at(A, lda, i, j));
+        if (s > anorm)
+            anorm = s;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrhs; ++r) {
+        long double rmax = 0.0L, xmax = 0.0L, bmax = 0.0L;
+        for (int64_t i = 0; i < n; ++i) {
+            long double complex s = (long double complex)AT(B, ldb, i, r);
+            for (int64_t j = 0; j < n; ++j)
+                s -= herm_at(A, lda, i, j) * (long double complex)AT(X, ldx, j, r);
+            if (cabsl(s) > rmax)
+                rmax = cabsl(s);
+            if (cabsl((long double complex)AT(X, ldx, i, r)) > xmax)
+                xmax = cabsl((long double complex)AT(X, ldx, i, r));
+            if (cabsl((long double complex)AT(B, ldb, i, r)) > bmax)
+                bmax = cabsl((long double complex)AT(B, ldb, i, r));
         }
         long double den = anorm * xmax + bmax;
         eta[r] = (double)(den > 0.0L ? rmax / den : 0.0L);

@@ -181,6 +181,30 @@ def general_matrix(n: int, seed: int) -> np.ndarray:
     return rng(seed).standard_normal((n, n))
 
 
+def hermitian_pd(n: int, seed: int, shift: float = 1.0) -> np.ndarray:
+    """Complex Hermitian positive definite A = G G^H / n + shift I, G with
+    i.i.d. standard complex normal entries (real and imaginary parts
+    N(0, 1/2)), seeded; the full matrix is returned."""
+    g = rng(seed)
+    G = (g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))) / np.sqrt(2.0)
+    A = G @ G.conj().T / n + shift * np.eye(n)
+    A = (A + A.conj().T) / 2
+    A[np.diag_indices(n)] = A.diagonal().real
+    return A
+
+
+def gaussian_integer_hpd(n: int, seed: int, diag_choices=(1, 2, 4), offmax: int = 2):
+    """(L0, A) with A = L0 L0^H exact: L0 lower, Gaussian-integer entries
+    (real and imaginary parts in [-offmax, offmax]) below a real
+    power-of-two diagonal, so every product and partial sum of the complex
+    Cholesky factorisation is an exact small dyadic number and the factor
+    is L0 itself."""
+    g = rng(seed)
+    L0 = np.tril(g.integers(-offmax, offmax + 1, size=(n, n)) + 1j * g.integers(-offmax, offmax + 1, size=(n, n)), -1)
+    L0 = L0 + np.diag(g.choice(np.array(diag_choices, dtype=np.float64), size=n))
+    return L0, L0 @ L0.conj().T
+
+
 def integer_vector(shape, seed: int, vmax: int = 3) -> np.ndarray:
     return rng(seed).integers(-vmax, vmax + 1, size=shape).astype(np.float64)
 

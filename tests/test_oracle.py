@@ -455,6 +455,95 @@ def test_getrf_planted_mistakes_are_caught(orc):
         assert not (np.array_equal(np.triu(bad), U0) and np.array_equal(p_bad, perm)), v
 
 
+# ------------------------------------------------------ complex Hermitian
+# The paper lists complex64 and complex128 for its routines.  Pins: a
+# factor worked by hand, the real special case (bit-identical to the real
+# column algorithm), the Gaussian-integer family (every operation exact),
+# scipy's LAPACK ZPOTRF/ZPOTRS, info, and the parts of A that are never read.
+def test_zpotrf_hand_worked_2x2(orc):
+    """A = [[4, 2-2i], [2+2i, 6]]: L11 = 2, l21 = (2+2i)/2 = 1+i,
+    L22 = sqrt(6 - |1+i|^2) = 2; b = A [1, i]^T = [4+2+2i, 2+2i+6i]."""
+    A = np.array([[4, 2 - 2j], [2 + 2j, 6]])
+    L, info = orc.zpotrf(A)
+    assert info == 0
+    assert np.array_equal(np.tril(L), np.array([[2, 0], [1 + 1j, 2]]))
+    x = orc.zpotrs(L, np.array([6 + 2j, 2 + 8j]))
+    assert np.array_equal(x, np.array([1, 1j]))
+
+
+@pytest.mark.parametrize("n", [1, 5, 40])
+def test_zpotrf_real_case_is_real_cholesky(orc, n):
+    A = synth.gram_spd(n, 70 + n)
+    L, info = orc.zpotrf(A.astype(np.complex128))
+    Lr, info_r = orc.potrf(A)
+    assert info == info_r == 0
+    assert np.array_equal(np.tril(L).real, np.tril(Lr)) and not np.any(np.tril(L).imag)
+
+
+@pytest.mark.parametrize("n,seed", [(6, 1), (33, 2), (80, 3)])
+def test_zpotrf_gaussian_integer_family_exact(orc, n, seed):
+    L0, A = synth.gaussian_integer_hpd(n, seed)
+    L, info = orc.zpotrf(A)
+    assert info == 0 and np.array_equal(np.tril(L), L0)
+    xt = synth.integer_vector((n, 2), seed) + 1j * synth.integer_vector((n, 2), seed + 1)
+    X, info = orc.zposv(A, A @ xt)
+    assert info == 0 and np.array_equal(X, xt)
+    assert np.all(orc.backward_error_z(A, X, A @ xt) == 0.0)
+
+
+def test_zpotrf_matches_lapack(orc):
+    scipy_linalg = pytest.importorskip("scipy.linalg")
+    n = 60
+    A = synth.hermitian_pd(n, 5)
+    L, info = orc.zpotrf(A)
+    Ls = scipy_linalg.cholesky(A, lower=True)
+    assert info == 0 and np.allclose(np.tril(L), Ls, rtol=1e-13, atol=1e-14)
+    B = synth.normal((n, 3), 6) + 1j * synth.normal((n, 3), 7)
+    X = orc.zpotrs(L, B)
+    Xs = scipy_linalg.cho_solve((Ls, True), B)
+    assert np.allclose(X, Xs, rtol=1e-12, atol=1e-13)
+    assert np.all(orc.backward_error_z(A, X, B) <= 1e-15)
+
+
+def test_zpotrf_info_and_unread_parts(orc):
+    n = 12
+    A = synth.hermitian_pd(n, 8)
+    G = A.copy()
+    G[np.triu_indices(n, 1)] = np.nan + 1j * np.nan       # strict upper never read
+    G[np.diag_indices(n)] += 1j * 7.0                      # imaginary diagonal ignored
+    L, info = orc.zpotrf(G)
+    L2, _ = orc.zpotrf(A)
+    assert info == 0 and np.array_equal(np.tril(L), np.tril(L2))
+    B = A.copy()
+    B[5, 5] = -1.0
+    _, info = orc.zpotrf(B)
+    assert info == 6
+
+
+def test_zpotrf_planted_mistakes_are_caught(orc):
+    """A factor that drops the conjugate (A = L L^T) or a solve that uses L^T
+    instead of L^H each break the Gaussian-integer pin (throw-away numpy
+    code, never the oracle)."""
+    L0, A = synth.gaussian_integer_hpd(20, 4)
+    def chol(A, conj):
+        A = A.copy()
+        n = A.shape[0]
+        for j in range(n):
+            for k in range(j):
+                A[j:, j] -= A[j:, k] * (np.conj(A[j, k]) if conj else A[j, k])
+            A[j, j] = np.sqrt(A[j, j].real)
+            A[j + 1:, j] /= A[j, j]
+        return np.tril(A)
+    assert np.array_equal(chol(A, True), L0)
+    with np.errstate(all="ignore"):
+        assert not np.array_equal(chol(A, False), L0)
+    xt = synth.integer_vector(20, 9) + 1j * synth.integer_vector(20, 10)
+    b = A @ xt
+    y = np.linalg.solve(L0, b)
+    assert np.allclose(np.linalg.solve(L0.conj().T, y), xt)
+    assert not np.allclose(np.linalg.solve(L0.T, y), xt)
+
+
 # ------------------------------------------------------ Cholesky adjoint
 # Gradient with respect to A of f(L), L = chol(A), given gL = df/dL (Murray
 # 2016; the paper is silent).  Pins: central differences of the oracle's own
