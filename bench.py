@@ -660,9 +660,72 @@ def bench_lu(torch, mg, synth, n: int, nrhs: int = 16, reps: int = 3, seed: int 
                                        up["ms"], up["launches"], FP64_PEAK_TFLOPS) if up["launches"] else None))
 
 
+def bench_zposv(torch, mg, synth, n: int = 16384, nrhs: int = 16, reps: int = 3, seed: int = 7700):
+    """Complex128 Hermitian posv (mg_zposv) on A = G G^H / n + delta I (G
+    complex Gaussian, cond ~ 1e4 as the real recipe) and B = A X_true, each
+    rep on a pre-staged copy.  TFLOP/s counts the real flops of complex
+    arithmetic, 4 (n^3/3 + 2 n^2 nrhs); the path itself runs the real
+    factorisation of the 2n x 2n blocked form (twice that count)."""
+    from paper_2601_14466_amd import _lib
+    dev = torch.device("cuda", 0)
+    log(f"[bench] zposv: generating n={n} nrhs={nrhs}")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed + n)
+    G = torch.complex(torch.randn((n, n), generator=gen, device=dev, dtype=torch.float64),
+                      torch.randn((n, n), generator=gen, device=dev, dtype=torch.float64)) / (2.0 ** 0.5)
+    A0 = torch.matmul(G, G.conj().T.contiguous()) / n
+    del G
+    v = torch.complex(torch.randn((n, 1), generator=gen, device=dev, dtype=torch.float64),
+                      torch.zeros((n, 1), device=dev, dtype=torch.float64))
+    for _ in range(50):                       # power iteration for lambda_max
+        v = A0 @ v
+        v = v / torch.linalg.vector_norm(v)
+    lam = float((v.conj().T @ (A0 @ v)).real)
+    A0.diagonal().add_(synth.cond_shift(lam, 1e4))
+    Xt = torch.complex(torch.randn((n, nrhs), generator=gen, device=dev, dtype=torch.float64),
+                       torch.randn((n, nrhs), generator=gen, device=dev, dtype=torch.float64))
+    B0 = A0 @ Xt
+    A0c, B0c = A0.T.contiguous(), B0.T.contiguous()   # column-major
+    h = mg.handle()
+    wb = ctypes.c_size_t()
+    _lib.call("mg_zposv_buffer_size", h.h, _lib.MG_F64, n, nrhs, ctypes.byref(wb))
+    work = torch.empty(max(1, wb.value), dtype=torch.uint8, device=dev)
+    info = torch.zeros((), dtype=torch.int32, device=dev)
+    A, B = A0c.clone(), B0c.clone()
+
+    def run():
+        _lib.call("mg_zposv", h.sync_stream(), _lib.MG_F64, n, nrhs, ctypes.c_void_p(A.data_ptr()), n,
+                  ctypes.c_void_p(B.data_ptr()), n, ctypes.c_void_p(work.data_ptr()), wb.value,
+                  ctypes.c_void_p(info.data_ptr()))
+
+    ts = []
+    for r in range(reps + 1):
+        A.copy_(A0c)
+        B.copy_(B0c)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        if r > 0:
+            ts.append(e0.elapsed_time(e1))
+    X = B.T
+    R = B0 - A0 @ X
+    anorm = float(A0.abs().sum(1).max())
+    eta = (R.abs().amax(0) / (anorm * X.abs().amax(0) + B0.abs().amax(0))).max().item()
+    ms = _median(ts)
+    cflops = 4.0 * (n ** 3 / 3 + 2.0 * n * n * nrhs)
+    return dict(n=n, nrhs=nrhs, dtype="complex128", ms=round(ms, 3), runs_ms=[round(t, 3) for t in ts],
+                tflops=round(cflops / (ms / 1e3) / 1e12, 3),
+                real_path_tflops=round(nominal_flops(2 * n, nrhs) / (ms / 1e3) / 1e12, 3),
+                eta_fp64_device=eta, info=int(info))
+
+
 LEGS = ("mixed_fp32", "mixed_bf16", "mixed_fp32_n65536", "small_n1024", "batched_f64", "batched_f32", "adjoint_n8192",
         "potrf_backward_n8192",
-        "fp64_n8192", "fp64_n16384", "gp_loglik_n16384", "gp_loglik_grad_n4096", "lu_n8192", "lu_n32768")
+        "fp64_n8192", "fp64_n16384", "gp_loglik_n16384", "gp_loglik_grad_n4096", "lu_n8192", "lu_n32768",
+        "zposv_n16384")
 
 
 def run_extra(key, torch, mg, synth, args):
@@ -697,6 +760,8 @@ def run_extra(key, torch, mg, synth, args):
         return bench_gp_grad(torch, mg, synth)
     if key in ("lu_n8192", "lu_n32768"):
         return bench_lu(torch, mg, synth, int(key.split("_n")[1]))
+    if key == "zposv_n16384":
+        return bench_zposv(torch, mg, synth)
     raise ValueError(key)
 
 

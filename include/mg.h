@@ -460,6 +460,41 @@ mg_status mg_gp_loglik_grad(mg_handle_t handle, int64_t n, int64_t nrhs, const d
                             int32_t *info);
 
 /*
+ * Complex Hermitian positive-definite solve (the paper's routines take
+ * complex64 and complex128 as well as the real types; "Software design").
+ * Complex matrices are column-major with interleaved (real, imaginary) pairs
+ * of the dtype's real type: dtype MG_F64 is complex128, MG_F32 complex64;
+ * leading dimensions count complex elements.  Only the lower triangle of A is
+ * read, and the imaginary part of its diagonal is ignored (LAPACK ZPOTRF).
+ * The factorisation is computed as the real Cholesky factorisation of the
+ * 2n x 2n blocked form of A (each entry a as [[Re a, -Im a], [Im a, Re a]]),
+ * whose factor is the blocked form of L, on the real FP64 / FP32 path; so the
+ * solve needs mg_zposv_buffer_size bytes of workspace (the 2n x 2n real
+ * matrix, 4 n^2 real elements, plus the real solve's workspace) for all three
+ * calls, and the real path's limits apply at order 2n.
+ *   zpotrf: A = L L^H in place (lower triangle; real positive diagonal, its
+ *           imaginary part written 0; strict upper triangle untouched).
+ *           info (device int32, written): 0, or k > 0 when the leading minor
+ *           of order k is not positive definite.
+ *   zpotrs: X = A^{-1} B from zpotrf's L; B (n x nrhs) overwritten; info as
+ *           mg_potrs (optional, in/out).
+ *   zposv:  both; B left unmodified when info > 0.
+ * Errors: zposv_buffer_size: -1 handle, -2 dtype, -3 n, -4 nrhs, -5 NULL out.
+ *   zpotrf: -1 handle, -2 dtype, -3 n, -4 A NULL, -5 lda < max(1,n), -6 work
+ *           NULL, -7 work too small, -8 info NULL.
+ *   zpotrs: -1 handle, -2 dtype, -3 n, -4 nrhs, -5 L NULL, -6 lda, -7 B NULL,
+ *           -8 ldb < max(1,n), -9 work NULL, -10 work too small.
+ *   zposv:  as zpotrs with A for L, and -11 info NULL.
+ */
+mg_status mg_zposv_buffer_size(mg_handle_t handle, mg_dtype dtype, int64_t n, int64_t nrhs, size_t *bytes);
+mg_status mg_zpotrf(mg_handle_t handle, mg_dtype dtype, int64_t n, void *A, int64_t lda, void *work,
+                    size_t work_bytes, int32_t *info);
+mg_status mg_zpotrs(mg_handle_t handle, mg_dtype dtype, int64_t n, int64_t nrhs, const void *L, int64_t lda,
+                    void *B, int64_t ldb, void *work, size_t work_bytes, int32_t *info);
+mg_status mg_zposv(mg_handle_t handle, mg_dtype dtype, int64_t n, int64_t nrhs, void *A, int64_t lda, void *B,
+                   int64_t ldb, void *work, size_t work_bytes, int32_t *info);
+
+/*
  * General solve (paper: "Software design", the lu_solve bullet: A x = b for a
  * general A through an LU factorisation with partial pivoting), FP64.
  *

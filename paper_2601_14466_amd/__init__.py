@@ -20,7 +20,7 @@ from ._lib import MgError, call, load, raw  # noqa: F401
 
 __all__ = [
     "Handle", "handle", "potrf", "potrs", "posv", "posv_noalloc", "posv_mixed", "posv_backward", "potrf_backward", "PosvFunction", "CholeskyFunction", "BatchPlan",
-    "getrf", "getrs", "gesv", "lu_solve",
+    "getrf", "getrs", "gesv", "lu_solve", "zpotrf", "zpotrs", "zposv",
     "posv_batched", "logdet", "gp_loglik", "gp_loglik_grad", "GPLogLik", "colmajor",
     "MgError", "load", "call", "raw",
 ]
@@ -443,6 +443,73 @@ def gesv(A, B):
          _ptr(info))
     X = Xc.T
     return (X.reshape(n) if flat else X), Ac.T, ipiv, info
+
+
+def _zdtype(t):
+    torch = _torch()
+    if t.dtype == torch.complex128:
+        return _lib.MG_F64
+    if t.dtype == torch.complex64:
+        return _lib.MG_F32
+    raise TypeError("the complex solve takes complex128 or complex64 tensors")
+
+
+def _zwork(h, dt, n, nrhs, device):
+    return _bytes_work("mg_zposv_buffer_size", h, device, dt, n, nrhs)
+
+
+def zpotrf(A):
+    """Complex Hermitian positive-definite factor A = L L^H (complex128 or
+    complex64; lower triangle read, the diagonal's imaginary part ignored):
+    returns (L, info), L lower with a real positive diagonal (the strict upper
+    part holds A's), info a 0-dim int32 device tensor."""
+    torch = _torch()
+    _check_cuda(A)
+    dt = _zdtype(A)
+    n = A.shape[0]
+    h = handle()
+    buf = A.T.clone(memory_format=torch.contiguous_format)
+    info = torch.zeros((), dtype=torch.int32, device=A.device)
+    work, wb = _zwork(h, dt, n, 0, A.device)
+    call("mg_zpotrf", h.h, dt, n, _ptr(buf), max(1, n), _ptr(work), wb, _ptr(info))
+    return buf.T, info
+
+
+def zpotrs(L, B, info=None):
+    """X = (L L^H)^{-1} B from zpotrf's factor (same dtype as L)."""
+    torch = _torch()
+    _check_cuda(L, B)
+    dt = _zdtype(L)
+    flat = B.dim() == 1
+    n = L.shape[0]
+    nrhs = 1 if flat else B.shape[1]
+    h = handle()
+    Lc = colmajor(L)
+    Xc = (B.reshape(n, 1) if flat else B).T.clone(memory_format=torch.contiguous_format)
+    work, wb = _zwork(h, dt, n, nrhs, L.device)
+    call("mg_zpotrs", h.h, dt, n, nrhs, _ptr(Lc), max(1, n), _ptr(Xc), max(1, n), _ptr(work), wb,
+         _ptr(info) if info is not None else None)
+    X = Xc.T
+    return X.reshape(n) if flat else X
+
+
+def zposv(A, B):
+    """Solve A X = B for a complex Hermitian positive-definite A (complex128 or
+    complex64).  Returns (X, info); on info > 0 X is B unchanged."""
+    torch = _torch()
+    _check_cuda(A, B)
+    dt = _zdtype(A)
+    flat = B.dim() == 1
+    n = A.shape[0]
+    nrhs = 1 if flat else B.shape[1]
+    h = handle()
+    Ac = A.T.clone(memory_format=torch.contiguous_format)
+    Xc = (B.reshape(n, 1) if flat else B).T.clone(memory_format=torch.contiguous_format)
+    info = torch.zeros((), dtype=torch.int32, device=A.device)
+    work, wb = _zwork(h, dt, n, nrhs, A.device)
+    call("mg_zposv", h.h, dt, n, nrhs, _ptr(Ac), max(1, n), _ptr(Xc), max(1, n), _ptr(work), wb, _ptr(info))
+    X = Xc.T
+    return (X.reshape(n) if flat else X), info
 
 
 def lu_solve(A, B):

@@ -66,6 +66,10 @@ SIGNATURES = {
     "mg_posv_backward": (i32, [vp, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]),
     "mg_potrf_backward_buffer_size": (i32, [vp, i64, ctypes.POINTER(sz)]),
     "mg_potrf_backward": (i32, [vp, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]),
+    "mg_zposv_buffer_size": (i32, [vp, i32, i64, i64, ctypes.POINTER(sz)]),
+    "mg_zpotrf": (i32, [vp, i32, i64, vp, i64, vp, sz, vp]),
+    "mg_zpotrs": (i32, [vp, i32, i64, i64, vp, i64, vp, i64, vp, sz, vp]),
+    "mg_zposv": (i32, [vp, i32, i64, i64, vp, i64, vp, i64, vp, sz, vp]),
     "mg_getrf_buffer_size": (i32, [vp, i64, ctypes.POINTER(sz)]),
     "mg_getrf": (i32, [vp, i64, vp, i64, vp, vp, sz, vp]),
     "mg_getrs_buffer_size": (i32, [vp, i64, i64, ctypes.POINTER(sz)]),

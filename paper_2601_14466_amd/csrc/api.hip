@@ -337,6 +337,73 @@ mg_status mg_potrf_backward(mg_handle_t h, int64_t n, const double* L, int64_t l
     return potrf_backward_impl(h, n, L, lda, GL, ldgl, GA, ldga, (int)mode, work, info);
 }
 
+// ------------------------------------------------------- complex Hermitian
+
+mg_status mg_zposv_buffer_size(mg_handle_t h, mg_dtype dt, int64_t n, int64_t nrhs, size_t* bytes) {
+    if (!h) return -1;
+    if (!dtype_ok(dt)) return -2;
+    if (n < 0) return -3;
+    if (nrhs < 0) return -4;
+    if (!bytes) return -5;
+    *bytes = zposv_work_bytes(n, nrhs, es_of(dt));
+    return MG_OK;
+}
+
+static mg_status z_call(mg_handle_t h, mg_dtype dt, int op, int64_t n, int64_t nrhs, void* A, int64_t lda, void* B,
+                        int64_t ldb, void* work, size_t work_bytes, int32_t* info) {
+    if (dt == MG_F64)
+        return zposv_impl<double>(h, op, n, nrhs, (double*)A, lda, (double*)B, ldb, work, info);
+    return zposv_impl<float>(h, op, n, nrhs, (float*)A, lda, (float*)B, ldb, work, info);
+}
+
+mg_status mg_zpotrf(mg_handle_t h, mg_dtype dt, int64_t n, void* A, int64_t lda, void* work, size_t work_bytes,
+                    int32_t* info) {
+    if (!h) return -1;
+    if (!dtype_ok(dt)) return -2;
+    if (n < 0) return -3;
+    if (!A && n > 0) return -4;
+    if (lda < std::max<int64_t>(1, n)) return -5;
+    const size_t need = zposv_work_bytes(n, 0, es_of(dt));
+    if (need > 0 && !work) return -6;
+    if (work_bytes < need) return -7;
+    if (!info) return -8;
+    return z_call(h, dt, 0, n, 0, A, lda, nullptr, 1, work, work_bytes, info);
+}
+
+mg_status mg_zpotrs(mg_handle_t h, mg_dtype dt, int64_t n, int64_t nrhs, const void* L, int64_t lda, void* B,
+                    int64_t ldb, void* work, size_t work_bytes, int32_t* info) {
+    if (!h) return -1;
+    if (!dtype_ok(dt)) return -2;
+    if (n < 0) return -3;
+    if (nrhs < 0) return -4;
+    if (!L && n > 0) return -5;
+    if (lda < std::max<int64_t>(1, n)) return -6;
+    if (!B && n > 0 && nrhs > 0) return -7;
+    if (ldb < std::max<int64_t>(1, n)) return -8;
+    const size_t need = zposv_work_bytes(n, nrhs, es_of(dt));
+    if (need > 0 && !work) return -9;
+    if (work_bytes < need) return -10;
+    if (n == 0 || nrhs == 0) return MG_OK;
+    return z_call(h, dt, 1, n, nrhs, const_cast<void*>(L), lda, B, ldb, work, work_bytes, info);
+}
+
+mg_status mg_zposv(mg_handle_t h, mg_dtype dt, int64_t n, int64_t nrhs, void* A, int64_t lda, void* B, int64_t ldb,
+                   void* work, size_t work_bytes, int32_t* info) {
+    if (!h) return -1;
+    if (!dtype_ok(dt)) return -2;
+    if (n < 0) return -3;
+    if (nrhs < 0) return -4;
+    if (!A && n > 0) return -5;
+    if (lda < std::max<int64_t>(1, n)) return -6;
+    if (!B && n > 0 && nrhs > 0) return -7;
+    if (ldb < std::max<int64_t>(1, n)) return -8;
+    const size_t need = zposv_work_bytes(n, nrhs, es_of(dt));
+    if (need > 0 && !work) return -9;
+    if (work_bytes < need) return -10;
+    if (!info) return -11;
+    return z_call(h, dt, 2, n, nrhs, A, lda, B, ldb, work, work_bytes, info);
+}
+
 // ------------------------------------------------------------ general solve
 
 mg_status mg_getrf_buffer_size(mg_handle_t h, int64_t n, size_t* bytes) {

@@ -91,6 +91,13 @@ mg_status getrs_impl(mg_handle_t h, int64_t n, int64_t nrhs, const double* LU, i
 mg_status lu_sweeps(mg_handle_t h, int64_t n, int64_t nrhs, const double* LU, int64_t lda, const int32_t* rperm,
                     double* B, int64_t ldb, double* Y, void* words, int32_t* info);
 
+// Complex Hermitian solve through the real 2n x 2n blocked form (op 0 factor,
+// 1 solve with a given factor, 2 both); work: zposv_work_bytes.
+size_t zposv_work_bytes(int64_t n, int64_t nrhs, int es);
+template <typename T>
+mg_status zposv_impl(mg_handle_t h, int op, int64_t n, int64_t nrhs, T* A, int64_t lda, T* B, int64_t ldb, void* work,
+                     int32_t* info);
+
 mg_status set_info_zero(hipStream_t s, int32_t* info);
 // Create (or re-create after a mode change) the look-ahead streams and events.
 mg_status ensure_streams(mg_handle_t h);

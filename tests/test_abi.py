@@ -69,6 +69,10 @@ def test_null_handle_is_argument_one(lib):
     assert L.raw("mg_gp_loglik_buffer_size", None, n, 1, ctypes.byref(sz)) == -1
     assert L.raw("mg_gp_loglik", None, n, 1, vp(8), n, vp(8), n, None, n, vp(8), n, vp(8), vp(8), 64,
                  vp(8)) == -1
+    assert L.raw("mg_zposv_buffer_size", None, 0, n, 1, ctypes.byref(sz)) == -1
+    assert L.raw("mg_zpotrf", None, 0, n, vp(8), n, vp(8), 64, vp(8)) == -1
+    assert L.raw("mg_zpotrs", None, 0, n, 1, vp(8), n, vp(8), n, vp(8), 64, None) == -1
+    assert L.raw("mg_zposv", None, 0, n, 1, vp(8), n, vp(8), n, vp(8), 64, vp(8)) == -1
     assert L.raw("mg_getrf_buffer_size", None, n, ctypes.byref(sz)) == -1
     assert L.raw("mg_getrf", None, n, vp(8), n, vp(8), vp(8), 64, vp(8)) == -1
     assert L.raw("mg_getrs_buffer_size", None, n, 1, ctypes.byref(sz)) == -1
