@@ -187,9 +187,17 @@ __global__ __launch_bounds__(256, 1) void k_getf2_panel(double* __restrict__ A, 
     // more than one workgroup, without waiting
     bool gave_up = spin_limit == 0 && G > 1;
     if (gave_up && tid == 0) atomicExch(&sy->err, 1);
+    double piv_prev = 0.0;
+    // Column j's step in three parts: (1) the candidate and its header, which
+    // the other workgroups wait for, go out first; (2) then the rank-1 update
+    // of columns j + 1.. by the previous pivot row, deferred from step j - 1,
+    // overlaps that round trip, after which the candidate row and row j are
+    // complete and published; (3) the winner, the interchange, and the
+    // scaling of column j with the update of column j + 1 only (all the next
+    // candidate needs).
     for (int j = 0; j < nbw; ++j) {
         double* E = cur + (size_t)j * gs * LU_SLOT;  // column j's entries
-        // ---- this workgroup's candidate: rows >= j, NaN entries never win
+        // ---- (1) this workgroup's candidate: rows >= j, NaN entries never win
         double v = -1.0;
         if (tid < R && row0 + tid >= j) {
             const double a = fabs(P[tid][j]);
@@ -198,16 +206,23 @@ __global__ __launch_bounds__(256, 1) void k_getf2_panel(double* __restrict__ A, 
         double bv;
         int br;
         block_argmax(v, tid, red_v[0], red_r[0], bv, br);
-        // ---- publish it, and row j by its owner
         double* me = E + (size_t)wg * LU_SLOT;
         const bool ownj = j >= row0 && j < row0 + R;
-        if (bv >= 0.0 && tid < nbw) st_dev(&me[LU_HDR + tid], lu_canon(P[br][tid]));
-        if (ownj && tid < nbw) st_dev(&E[(size_t)jslot * LU_SLOT + LU_HDR + tid], lu_canon(P[j - row0][tid]));
         if (tid == 0) {
             st_dev(&me[0], bv);
             st_dev(&me[1], bv >= 0.0 ? (double)(row0 + br) : -1.0);
         }
-        // ---- every workgroup's header (a thread each), polled until written
+        // ---- (2) the deferred update a_rc -= l_r u_c, c > j, by pivot j - 1
+        // (urow and the multipliers l_r = P[r][j - 1] of step j - 1)
+        if (j > 0 && piv_prev != 0.0 && tid < R && row0 + tid > j - 1) {
+            const double l = P[tid][j - 1];
+#pragma unroll 8
+            for (int c = j + 1; c < nbw; ++c) P[tid][c] = P[tid][c] - l * urow[c];
+        }
+        __syncthreads();
+        if (bv >= 0.0 && tid < nbw) st_dev(&me[LU_HDR + tid], lu_canon(P[br][tid]));
+        if (ownj && tid < nbw) st_dev(&E[(size_t)jslot * LU_SLOT + LU_HDR + tid], lu_canon(P[j - row0][tid]));
+        // ---- (3) every workgroup's header (a thread each), polled until written
         double hv = -1.0;
         int hr = INT_MAX;
         for (int spins = 0;; ++spins) {
@@ -234,12 +249,12 @@ __global__ __launch_bounds__(256, 1) void k_getf2_panel(double* __restrict__ A, 
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        // ---- the winner (every workgroup alike; workgroup q's rows follow q)
+        // the winner (every workgroup alike; workgroup q's rows follow q)
         double gv;
         int gr;
         block_argmax(hv, hr, red_v[1], red_r[1], gv, gr);
         const int pw = gv >= 0.0 ? gr / LU_ROWS : 0;  // workgroup whose slot holds the candidate row
-        // ---- row j and the candidate row, polled until written
+        // row j and the candidate row, polled until written
         for (int spins = 0;; ++spins) {
             bool ok = true;
             if (tid < nbw) {
@@ -270,7 +285,8 @@ __global__ __launch_bounds__(256, 1) void k_getf2_panel(double* __restrict__ A, 
             ipiv[k0 + j] = (int32_t)(k0 + p + 1);
             if (piv == 0.0 && *info == 0) *info = (int32_t)(k0 + j + 1);
         }
-        // ---- interchange rows j and p (their owners), then eliminate below j
+        // interchange rows j and p (their owners), then scale column j and
+        // update column j + 1; the other columns wait for step j + 1
         if (p != j) {
             if (ownj && tid < nbw) P[j - row0][tid] = urow[tid];
             if (p >= row0 && p < row0 + R && tid < nbw) P[p - row0][tid] = jrow[tid];
@@ -279,9 +295,9 @@ __global__ __launch_bounds__(256, 1) void k_getf2_panel(double* __restrict__ A, 
         if (piv != 0.0 && tid < R && row0 + tid > j) {
             const double l = P[tid][j] / piv;
             P[tid][j] = l;
-#pragma unroll 8
-            for (int c = j + 1; c < nbw; ++c) P[tid][c] = P[tid][c] - l * urow[c];
+            if (j + 1 < nbw) P[tid][j + 1] = P[tid][j + 1] - l * urow[j + 1];
         }
+        piv_prev = piv;
         __syncthreads();
     }
     for (int c = 0; c < nbw; ++c)
@@ -381,10 +397,12 @@ __global__ __launch_bounds__(256) void k_lu_swap_cols(double* __restrict__ A, in
 // first (the block row's rows and every row they touch go through LDS; the
 // touched rows below the block row are written back); then
 // U12 = L11^{-1} A12 (L11 = the panel's unit lower 64 x 64 block) by forward
-// substitution, one lane per column of wave 0, stored over A12.
+// substitution, one lane per column of wave 0, stored over A12 and, when Ut
+// is given, transposed into Ut (row j - c0 holds column j's 64 values).
 __global__ __launch_bounds__(256) void k_lu_row_block(double* __restrict__ A, int64_t lda, int64_t n, int64_t k0,
                                                       int64_t c0, int64_t ncols, int swaps,
-                                                      const int32_t* __restrict__ ipiv) {
+                                                      const int32_t* __restrict__ ipiv, double* __restrict__ Ut,
+                                                      int64_t ldu) {
     constexpr int nbw = LU_NB;
     __shared__ double V[LU_LIST][65];
     __shared__ double Lt[LU_NB][LU_NB + 1];  // Lt[c][r] = L11(r, c), r > c
@@ -442,22 +460,32 @@ __global__ __launch_bounds__(256) void k_lu_row_block(double* __restrict__ A, in
         const int r = e & 63, c = e >> 6;
         if (c < cw) A[idx(k0 + r, cb + c, lda)] = V[r][c];
     }
+    // U12^T: column j - c0 of the block row is row j - c0 of Ut (lanes
+    // along the block row's columns, so each store is contiguous)
+    if (Ut) {
+        for (int e = tid; e < LU_NB * 64; e += 256) {
+            const int c = e & 63, r = e >> 6;
+            if (c < cw) Ut[idx(cb + c - c0, r, ldu)] = V[r][c];
+        }
+    }
 }
 
 // C (m x nn, ldc) -= X Z with X m x kdim (column-major, ldx) and Z kdim x nn
-// (column-major, ldz: the block row U12 as it lies in A).  128 x 128 output
+// (column-major, ldz: the block row U12 as it lies in A; with ZT, Z^T given
+// instead, nn x kdim column-major, read along its rows like X).  128 x 128 output
 // tiles, each XCD taking a contiguous run of tiles numbered in bands of 8
 // tile rows, column by column inside a band (the workgroups an XCD holds at
 // once cover an 8 x 8 patch and share its operand blocks in L2); each wave
 // computes a 64 x 64 quarter.  Operands stream straight into registers
 // through a ring of four k-steps: lane (i, g) of k-step s reads X row
 // 16 b + i, column 4 s + g, and Z column 16 b + i, row 4 s + g (32 contiguous
-// bytes of a column per 4 lanes).  FOLD (rank 256): C is folded into the
+// bytes of a column per 4 lanes; with ZT row 16 b + i, column 4 s + g of
+// Z^T).  FOLD (rank 256 / 512): C is folded into the
 // k-loop one 16 x 16 piece at a time; otherwise (rank 64) C is loaded up
 // front.  The accumulators hold X Z - C and are negated as they are stored.
 // The host keeps every byte offset below 2^31 and kdim a multiple of 16
 // (of 256 with FOLD).
-template <bool FOLD>
+template <bool FOLD, bool ZT>
 __global__ __launch_bounds__(256, 2) void k_gemm_sub(double* __restrict__ C, int64_t ldc, const double* __restrict__ X,
                                                      int64_t ldx, const double* __restrict__ Z, int64_t ldz, int64_t m,
                                                      int64_t nn, int kdim) {
@@ -498,13 +526,14 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sub(double* __restrict__ C, int
             for (int r = 0; r < 4; ++r) acc[bi][bj][r] = FOLD ? 0.0 : -c_load(bi, bj, r);
     const __amdgpu_buffer_rsrc_t xrs =
         __builtin_amdgcn_make_buffer_rsrc((void*)(X + sr0), (short)0, 0x7fffffff, 0x00020000);
-    const __amdgpu_buffer_rsrc_t zrs =
-        __builtin_amdgcn_make_buffer_rsrc((void*)(Z + idx(0, sc0, ldz)), (short)0, 0x7fffffff, 0x00020000);
+    // ZT: Z given transposed (nn x kdim, leading dimension ldz), read like X
+    const __amdgpu_buffer_rsrc_t zrs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(ZT ? Z + sc0 : Z + idx(0, sc0, ldz)), (short)0, 0x7fffffff, 0x00020000);
     int xo[4], zo[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         xo[b] = (min(16 * b + i, rmax) + g * lx) * ES;
-        zo[b] = (min(16 * b + i, cmax) * lz + g) * ES;
+        zo[b] = ZT ? (min(16 * b + i, cmax) + g * lz) * ES : (min(16 * b + i, cmax) * lz + g) * ES;
     }
     const int nks = kdim / 4;
     double xq[RG][4], zq[RG][4];
@@ -514,7 +543,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_sub(double* __restrict__ C, int
         for (int b = 0; b < 4; ++b) {
             xq[slot][b] =
                 __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(xrs, xo[b], kk * 4 * lx * ES, 0));
-            zq[slot][b] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(zrs, zo[b], kk * 4 * ES, 0));
+            zq[slot][b] = __builtin_bit_cast(
+                double, __builtin_amdgcn_raw_buffer_load_b64(zrs, zo[b], kk * 4 * (ZT ? lz : 1) * ES, 0));
         }
     };
 #pragma unroll
@@ -624,18 +654,20 @@ static int panel_groups(int64_t m) { return (int)cdiv(m, LU_ROWS); }
 // panel's workgroups) and the sync words.
 static size_t slot_set_doubles(int64_t n) { return (size_t)LU_NB * (panel_groups(n) + 1) * LU_SLOT; }
 
+// Workspace: the two slot sets, the sync words, and U12^T of an outer block
+// row (n x LU_NB2).
 size_t getrf_work_bytes(int64_t n) {
     if (n == 0) return 0;
-    return align_up(2 * slot_set_doubles(n) * 8, 256) + 256;
+    return align_up(2 * slot_set_doubles(n) * 8, 256) + 256 + align_up((size_t)n * LU_NB2 * 8, 256);
 }
 
-template <bool FOLD>
+template <bool FOLD, bool ZT = false>
 static mg_status gemm_sub(hipStream_t st, double* C, int64_t ldc, const double* X, int64_t ldx, const double* Z,
                           int64_t ldz, int64_t m, int64_t nn, int kdim) {
     if (m <= 0 || nn <= 0) return MG_OK;
     const int64_t tiles = cdiv(m, 128) * cdiv(nn, 128);
-    hipLaunchKernelGGL((k_gemm_sub<FOLD>), dim3((unsigned)(8 * cdiv(tiles, 8))), dim3(256), 0, st, C, ldc, X, ldx, Z,
-                       ldz, m, nn, kdim);
+    hipLaunchKernelGGL((k_gemm_sub<FOLD, ZT>), dim3((unsigned)(8 * cdiv(tiles, 8))), dim3(256), 0, st, C, ldc, X, ldx,
+                       Z, ldz, m, nn, kdim);
     MG_LAUNCH_CHECK();
     return MG_OK;
 }
@@ -652,6 +684,7 @@ mg_status getrf_impl(mg_handle_t h, int64_t n, double* A, int64_t lda, int32_t* 
     const int gs = panel_groups(n) + 1;
     double* sets[2] = {(double*)work, (double*)work + slot_set_doubles(n)};
     LuSync* sy = (LuSync*)((char*)work + align_up(2 * slot_set_doubles(n) * 8, 256));
+    double* Ut = (double*)((char*)sy + 256);
     int lim = h->spin_limit < 0 ? LU_SPIN_LIMIT : h->spin_limit;
     hipLaunchKernelGGL(k_lu_reset, dim3(1), dim3(64), 0, st, sy);
     MG_LAUNCH_CHECK();
@@ -690,7 +723,7 @@ mg_status getrf_impl(mg_handle_t h, int64_t n, double* A, int64_t lda, int32_t* 
             const int64_t k1 = k0 + nbw;
             if (k1 >= kend) continue;  // nbw == LU_NB below
             hipLaunchKernelGGL(k_lu_row_block, dim3((unsigned)cdiv(kend - k1, 64)), dim3(256), 0, st, A, lda, n, k0,
-                               k1, kend - k1, 1, (const int32_t*)ipiv);
+                               k1, kend - k1, 1, (const int32_t*)ipiv, (double*)nullptr, (int64_t)1);
             MG_LAUNCH_CHECK();
             // rank-64 update of the rest of the outer block column
             if ((rc = prof_begin(h, MG_PROF_TRAILING_NARROW, st))) return rc;
@@ -709,7 +742,7 @@ mg_status getrf_impl(mg_handle_t h, int64_t n, double* A, int64_t lda, int32_t* 
         // rank-64 update of the block rows below inside the outer block)
         for (int64_t k0 = K0; k0 < kend; k0 += LU_NB) {
             hipLaunchKernelGGL(k_lu_row_block, dim3((unsigned)cdiv(mr, 64)), dim3(256), 0, st, A, lda, n, k0, kend, mr,
-                               0, (const int32_t*)ipiv);
+                               0, (const int32_t*)ipiv, Ut + (k0 - K0) * mr, mr);
             MG_LAUNCH_CHECK();
             const int64_t k1 = k0 + LU_NB;
             if (k1 < kend) {
@@ -725,8 +758,8 @@ mg_status getrf_impl(mg_handle_t h, int64_t n, double* A, int64_t lda, int32_t* 
         }
         // rank-nb2 update of the trailing matrix
         if ((rc = prof_begin(h, MG_PROF_LU_UPDATE, st))) return rc;
-        if ((rc = gemm_sub<true>(st, A + idx(kend, kend, lda), lda, A + idx(kend, K0, lda), lda,
-                                 A + idx(K0, kend, lda), lda, mr, mr, (int)W)))
+        if ((rc = gemm_sub<true, true>(st, A + idx(kend, kend, lda), lda, A + idx(kend, K0, lda), lda,
+                                       (const double*)Ut, mr, mr, mr, (int)W)))
             return rc;
         const double md = (double)mr;
         if ((rc = prof_end(h, MG_PROF_LU_UPDATE, 2.0 * (double)W * md * md, (2.0 * md * md + 2.0 * (double)W * md) * 8.0,
