@@ -530,6 +530,158 @@ __device__ __forceinline__ f32x4 mma_xzt_bf16(f32x4 acc, bf16x8 x, bf16x8 z) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(z, x, acc, 0, 0, 0);
 }
 
+// bfloat16 trailing update with the operands staged through LDS.  The
+// register-ring form above keeps only three 32-wide k-steps in flight, so at
+// bfloat16 MFMA rates (a k-step is ~0.1 us of matrix-pipe time per wave)
+// nearly every step waits for a round trip to memory.  Here the tile's two
+// 128-row operand blocks move in chunks of 128 k: all of a chunk's loads are
+// issued at once into registers (8 x 16 bytes per thread and operand),
+// written to padded LDS rows (16 bytes of padding per row: the 16 rows a
+// quarter-wave reads sit in distinct banks), and the four waves multiply from
+// LDS while the next chunk's loads are in flight.  Two workgroups share a CU
+// (70 KB of LDS each), so one's C read and first chunk overlap the other's
+// products, and a workgroup holds its CU for one tile only, so the narrow
+// kernels of the panel chain find CUs as tiles finish.  Operand rows past the
+// block read as zero (the buffer resource ends at the panel's last row);
+// their products feed only outputs that are never stored.  Interior quarters
+// (every entry inside the block and below the diagonal) address C with one
+// per-lane offset plus uniform ones; diagonal and edge quarters take the
+// clamped, masked path of k_syrk_lower_bf16.  The MFMA sequence per output
+// tile is that kernel's, so the result is bitwise the same.
+constexpr int BFL_KC = 128;                  // k per LDS chunk
+constexpr int BFL_LD = BFL_KC * 2 + 16;      // LDS row stride in bytes
+constexpr int BFL_PC = BFL_KC / 8;           // 16-byte pieces per row of a chunk
+constexpr int BFL_U = 128 * BFL_PC / 256;    // pieces per thread and operand
+
+__global__ __launch_bounds__(256, 2) void k_syrk_lower_bf16l(float* __restrict__ Cm, const __bf16* __restrict__ Pt,
+                                                             int64_t lda, int64_t m, int kdim, int64_t j0, int64_t wj,
+                                                             const int32_t* info) {
+    __shared__ __attribute__((aligned(16))) unsigned char Xs[128 * BFL_LD];
+    __shared__ __attribute__((aligned(16))) unsigned char Zs[128 * BFL_LD];
+    if (*info != 0) return;
+    const int64_t T = (m + SY_BM - 1) / SY_BM;
+    const int64_t ntiles = slab_tiles(T, j0, wj);
+    const int64_t per = gridDim.x / 8;
+    const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (t >= ntiles) return;  // uniform across the workgroup
+    int64_t I, J;
+    trailing_tile(t, T, j0, wj, I, J);
+    constexpr int ES = 4;
+    const int tid = threadIdx.x, l = tid & 63, i = l & 15, g = l >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = w >> 1, wc = w & 1;
+    const int ld = (int)lda;
+    // chunk c: thread tid moves piece tid % BFL_PC of rows tid / BFL_PC + 16 u
+    // of both blocks; rows at or past m lie beyond the resource and read 0
+    const __amdgpu_buffer_rsrc_t prs = buf_rsrc(Pt, m * kdim * 2);
+    const int pvo = ((tid / BFL_PC) * kdim + (tid % BFL_PC) * 8) * 2;
+    const int xso = (int)(I * SY_BM) * kdim * 2, zso = (int)(J * SY_BM) * kdim * 2;
+    u32x4 sx[BFL_U], sz[BFL_U];
+    auto gload = [&](int c) {
+#pragma unroll
+        for (int u = 0; u < BFL_U; ++u) {
+            const int so = (16 * u * kdim + c * BFL_KC) * 2;
+            sx[u] = __builtin_amdgcn_raw_buffer_load_b128(prs, pvo, xso + so, 0);
+            sz[u] = __builtin_amdgcn_raw_buffer_load_b128(prs, pvo, zso + so, 0);
+        }
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int u = 0; u < BFL_U; ++u) {
+            const int row = tid / BFL_PC + 16 * u, pc = tid % BFL_PC;
+            *(u32x4*)(Xs + row * BFL_LD + pc * 16) = sx[u];
+            *(u32x4*)(Zs + row * BFL_LD + pc * 16) = sz[u];
+        }
+    };
+    gload(0);
+    const int64_t sr0 = I * SY_BM + 64 * wr, sc0 = J * SY_BM + 64 * wc;
+    // quarters above the diagonal or past the block's edge hold no output but
+    // still take part in the loads and barriers
+    const bool active = !(sr0 + 63 < sc0 || sr0 >= m || sc0 >= m);
+    const int rmax = active ? (int)(m - 1 - sr0 < 63 ? m - 1 - sr0 : 63) : 0;
+    const int cmax = active ? (int)(m - 1 - sc0 < 63 ? m - 1 - sc0 : 63) : 0;
+    const int dd = (int)(sr0 - sc0 < 64 ? sr0 - sc0 : 64);
+    const bool interior = active && rmax == 63 && cmax == 63 && dd >= 64;
+    const __amdgpu_buffer_rsrc_t crs = buf_rsrc(Cm + idx(active ? sr0 : 0, active ? sc0 : 0, lda), 0x7fffffff);
+    // C entry (16 bi + i, 16 bj + 4 g + r) of the quarter: per-lane part
+    // (i + 4 g ld), uniform parts 16 bi and (16 bj + r) ld
+    auto c_in = [&](int li, int lg, int bi, int bj, int r) {
+        const int rr = 16 * bi + li, cc = 16 * bj + tcol<float>(lg, r);
+        return rr <= rmax && cc <= cmax && rr + dd >= cc;
+    };
+    auto c_off = [&](int li, int lg, int bi, int bj, int r) {
+        const int rr = min(16 * bi + li, rmax), cc = min(16 * bj + tcol<float>(lg, r), cmax);
+        return (rr + cc * ld) * ES;
+    };
+    f32x4 acc[4][4];
+    if (interior) {
+        const int cvo = (i + 4 * g * ld) * ES;
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc[bi][bj][r] = -buf_ld((float*)nullptr, crs, cvo + 16 * bi * ES, (16 * bj + r) * ld * ES);
+    } else {
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc[bi][bj][r] = (active && c_in(i, g, bi, bj, r))
+                                         ? -buf_ld((float*)nullptr, crs, c_off(i, g, bi, bj, r), 0)
+                                         : 0.0f;
+    }
+    const int nch = kdim / BFL_KC;
+    for (int c = 0; c < nch; ++c) {
+        lstore();
+        __syncthreads();
+        if (c + 1 < nch) gload(c + 1);
+        if (active) {
+#pragma unroll
+            for (int s = 0; s < BFL_KC / 32; ++s) {
+                bf16x8 xv[4], zv[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    xv[b] = *(const bf16x8*)(Xs + (64 * wr + 16 * b + i) * BFL_LD + (32 * s + 8 * g) * 2);
+                    zv[b] = *(const bf16x8*)(Zs + (64 * wc + 16 * b + i) * BFL_LD + (32 * s + 8 * g) * 2);
+                }
+#pragma unroll
+                for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mma_xzt_bf16(acc[bi][bj], xv[bi], zv[bj]);
+            }
+        }
+        __syncthreads();
+    }
+    if (!active) return;
+    // the store's offsets are recomputed from lane indices the compiler
+    // cannot see through, so none of the load's 64 offsets stays live
+    // across the k-loop
+    int li = i, lg = g;
+    asm volatile("" : "+v"(li), "+v"(lg));
+    if (interior) {
+        const int cvo = (li + 4 * lg * ld) * ES;
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    buf_st(-acc[bi][bj][r], crs, cvo + 16 * bi * ES, (16 * bj + r) * ld * ES);
+    } else {
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (c_in(li, lg, bi, bj, r)) buf_st(-acc[bi][bj][r], crs, c_off(li, lg, bi, bj, r), 0);
+    }
+}
+
 // Row-major bfloat16 copy of the m x kb panel P (column-major, lda): thread
 // per (row, 8 columns), reading down columns (coalesced) and writing 16
 // contiguous bytes; rounding to nearest even as round_bf16.
@@ -786,8 +938,12 @@ static mg_status trailing(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int6
         // bfloat16 mode, full block column: the panel was packed by panel_block
         const int64_t ntiles = slab_tiles(T_, j0, wj);
         if ((m + (int64_t)(kb + 64) * lda) * 4 >= ((int64_t)1 << 31) - 65536) return MG_ERR_UNSUPPORTED;
-        hipLaunchKernelGGL(k_syrk_lower_bf16, dim3((unsigned)(8 * cdiv(ntiles, 8))), dim3(256), 0, st,
-                           (float*)(A + idx(e, e, lda)), Pt, lda, m, (int)kb, j0, wj, info);
+        if (kb % BFL_KC == 0 && (m + 128) * kb * 2 < ((int64_t)1 << 31))
+            hipLaunchKernelGGL(k_syrk_lower_bf16l, dim3((unsigned)(8 * cdiv(ntiles, 8))), dim3(256), 0, st,
+                               (float*)(A + idx(e, e, lda)), Pt, lda, m, (int)kb, j0, wj, info);
+        else
+            hipLaunchKernelGGL(k_syrk_lower_bf16, dim3((unsigned)(8 * cdiv(ntiles, 8))), dim3(256), 0, st,
+                               (float*)(A + idx(e, e, lda)), Pt, lda, m, (int)kb, j0, wj, info);
         MG_LAUNCH_CHECK();
     } else if ((rc = syrk_lower_launch<T>(st, A + idx(e, e, lda), A + idx(e, k0, lda), lda, m, kb, info, j0, wj,
                                           h->trail_lo == 2 ? 1 : 0))) {
