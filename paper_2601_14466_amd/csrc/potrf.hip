@@ -73,31 +73,23 @@ __device__ __forceinline__ int factor_publish(V4<C>& d, int j, C* Lsc, C* piv) {
     return 0;
 }
 
-template <typename S, int W, int SMAX>
-// (At most 256 registers per wave, VGPRs and AGPRs together: the look-ahead
-// runs this kernel while the trailing update holds two 256-register waves on
-// every SIMD, and a wave that needs more than half a SIMD's registers can
-// only start once the update drains a whole SIMD, which starved it for
-// milliseconds at a time.)
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) void k_factor_block(S* __restrict__ A, int64_t lda, int s, int64_t col0,
-                                                         int32_t* info) {
+// One wave's part of k_factor_block, with its two tile rows ra = RA and
+// rb = NTM - 1 - RA as compile-time constants: every slot test in the
+// unrolled slot loops then folds away, so the diagonal tile's slot is known
+// when it is factored (no select chain over the nine slots, no per-column
+// mask reloads).
+template <typename S, int W, int SMAX, int RA>
+__device__ __forceinline__ void factor_block_wave(S* __restrict__ A, int64_t lda, int s, int64_t col0, int32_t* info,
+                                                  double* Pc, double* Lsc, double* piv, int* fail) {
     typedef double C;
     constexpr int NTM = SMAX / 16;  // tile rows at most
-    static_assert(2 * W == NTM, "two tile rows per wave");
     constexpr int TPW = NTM + 1;    // tiles per wave
-    __shared__ C Pc[SMAX * 17];     // block column j: row r, column c at r*17 + c
-    __shared__ C Lsc[16 * 17];      // L_jj scaled by columns (0 on and above the diagonal)
-    __shared__ C piv[16];
-    __shared__ int fail;
-    if (*info != 0) return;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr int ra = RA, rb = NTM - 1 - RA;
     const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
     const int nt = (s + 15) >> 4;
-    const int ra = w, rb = NTM - 1 - w;
     const C* xa = Pc + (16 * ra + i) * 17 + g;  // LDS row bases of the two owned tile rows
     const C* xb = Pc + (16 * rb + i) * 17 + g;
     const C* zc = Pc + i * 17 + g;
-    if (threadIdx.x == 0) fail = 0;
 
     V4<C> acc[TPW];
 #pragma unroll
@@ -118,7 +110,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) voi
         V4<C> d_ = acc[0];                                                                   \
         _Pragma("unroll") for (int t = 1; t < TPW; ++t) if (t == td_) d_ = acc[t];           \
         const int f_ = factor_publish<C>(d_, (jj), Lsc, piv);                                \
-        if (f_ && l == 0) fail = f_;                                                         \
+        if (f_ && l == 0) *fail = f_;                                                         \
         _Pragma("unroll") for (int t = 0; t < TPW; ++t) if (t == td_) acc[t] = d_;           \
     } while (0)
     // acc[t] -= L(I, j) L(J, j)^T, operands from the LDS copy of column j
@@ -130,8 +122,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) voi
     for (int j = -1; j < nt; ++j) {
         if (j >= 0) {
             __syncthreads();  // L_jj published (or failure flagged)
-            if (fail) {
-                if (threadIdx.x == 0) *info = (int32_t)(col0 + fail);
+            if (*fail) {
+                if (threadIdx.x == 0) *info = (int32_t)(col0 + *fail);
                 return;
             }
             // ---- solve the owned tiles (I, j), I > j, and publish them (one
@@ -186,6 +178,32 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) voi
         } else {
             if (rb < nt) store_tile<S, C>(acc[t], A, lda, 16 * rb, 16 * (NTM - t), s, s, rb == NTM - t);
         }
+    }
+}
+
+template <typename S, int W, int SMAX>
+// (At most 256 registers per wave, VGPRs and AGPRs together: the look-ahead
+// runs this kernel while the trailing update holds two 256-register waves on
+// every SIMD, and a wave that needs more than half a SIMD's registers can
+// only start once the update drains a whole SIMD, which starved it for
+// milliseconds at a time.)
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) void k_factor_block(S* __restrict__ A, int64_t lda, int s, int64_t col0,
+                                                         int32_t* info) {
+    typedef double C;
+    constexpr int NTM = SMAX / 16;  // tile rows at most
+    static_assert(2 * W == NTM && W == 4, "four waves of two tile rows");
+    __shared__ C Pc[SMAX * 17];     // block column j: row r, column c at r*17 + c
+    __shared__ C Lsc[16 * 17];      // L_jj scaled by columns (0 on and above the diagonal)
+    __shared__ C piv[16];
+    __shared__ int fail;
+    if (*info != 0) return;
+    if (threadIdx.x == 0) fail = 0;
+    // every wave runs the same sequence of barriers in its own instance
+    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+        case 0: factor_block_wave<S, W, SMAX, 0>(A, lda, s, col0, info, Pc, Lsc, piv, &fail); break;
+        case 1: factor_block_wave<S, W, SMAX, 1>(A, lda, s, col0, info, Pc, Lsc, piv, &fail); break;
+        case 2: factor_block_wave<S, W, SMAX, 2>(A, lda, s, col0, info, Pc, Lsc, piv, &fail); break;
+        default: factor_block_wave<S, W, SMAX, 3>(A, lda, s, col0, info, Pc, Lsc, piv, &fail); break;
     }
 }
 
@@ -396,15 +414,15 @@ __device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, int vo
 template <typename S, bool FOLD, int RG, bool BF>
 __global__ __launch_bounds__(256, 2) void k_syrk_lower(S* __restrict__ Cm, const S* __restrict__ P,
                                                        int64_t lda, int64_t m, int kdim, int64_t j0, int64_t wj,
-                                                       const int32_t* info) {
+                                                       int64_t t_first, const int32_t* info) {
     if (*info != 0) return;
     const int64_t T = (m + SY_BM - 1) / SY_BM;
-    const int64_t ntiles = slab_tiles(T, j0, wj);
+    const int64_t ntiles = slab_tiles(T, j0, wj) - t_first;  // tiles t_first.. of the slab
     const int64_t per = gridDim.x / 8;
     const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (t >= ntiles) return;
     int64_t I, J;
-    trailing_tile(t, T, j0, wj, I, J);
+    trailing_tile(t + t_first, T, j0, wj, I, J);
     constexpr int ES = (int)sizeof(S);
     const int tid = threadIdx.x, l = tid & 63, i = l & 15, g = l >> 4;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -800,12 +818,15 @@ constexpr int64_t TRSM_TWO_ROWS = 12288;  // panel rows from which waves take tw
 
 template <typename S>
 static mg_status launch_trsm(hipStream_t st, int64_t nb, S* P, const S* Lkk, int64_t lda, int64_t m,
-                             const int32_t* info) {
+                             const int32_t* info, bool latency) {
     // Tall panels (the look-ahead regime, where the solve shares the chip
     // with the trailing update) take two row blocks per wave, halving the
     // wave-time the solve holds; short ones one, for the shortest latency.
+    // latency: the caller's schedule is bound by the panel chain, not by the
+    // trailing update (bfloat16 mode), so every panel takes one row block
+    // per wave.
     const dim3 block(256);
-    const bool two = m >= TRSM_TWO_ROWS;
+    const bool two = m >= TRSM_TWO_ROWS && !latency;
     const dim3 grid((unsigned)cdiv(m, two ? 128 : 64));
     if (nb == 64 && two) hipLaunchKernelGGL((k_trsm_panel<S, 64, 2>), grid, block, 0, st, P, Lkk, lda, m, info);
     else if (nb == 64) hipLaunchKernelGGL((k_trsm_panel<S, 64, 1>), grid, block, 0, st, P, Lkk, lda, m, info);
@@ -816,13 +837,18 @@ static mg_status launch_trsm(hipStream_t st, int64_t nb, S* P, const S* Lkk, int
     return MG_OK;
 }
 
+// t_first: skip the slab's first t_first tiles (in the slab's own order; for
+// a narrow slab, t_first = wj (wj + 1) / 2 leaves the tiles below its
+// diagonal triangle).
 template <typename S>
 mg_status syrk_lower_launch(hipStream_t st, S* Cm, const S* P, int64_t lda, int64_t m, int64_t kdim,
-                            const int32_t* info, int64_t j0 = 0, int64_t wj = -1, int bf16 = 0) {
+                            const int32_t* info, int64_t j0 = 0, int64_t wj = -1, int bf16 = 0,
+                            int64_t t_first = 0) {
     const int64_t T = cdiv(m, SY_BM);
     if (wj < 0) wj = T - j0;
     if (j0 >= T || wj <= 0) return MG_OK;
-    const int64_t ntiles = slab_tiles(T, j0, wj);
+    const int64_t ntiles = slab_tiles(T, j0, wj) - t_first;
+    if (ntiles <= 0 || t_first < 0) return MG_OK;
     const int64_t grid = 8 * cdiv(ntiles, 8);
     // every byte offset the kernel forms from P or from a quarter's corner
     // must fit in 31 bits
@@ -830,17 +856,23 @@ mg_status syrk_lower_launch(hipStream_t st, S* Cm, const S* P, int64_t lda, int6
         return MG_ERR_UNSUPPORTED;
 #define MG_SYRK(FOLD_, RG_, BF_)                                                                             \
     hipLaunchKernelGGL((k_syrk_lower<S, FOLD_, RG_, BF_>), dim3((unsigned)grid), dim3(256), 0, st, Cm, P, lda, m, \
-                       (int)kdim, j0, wj, info)
+                       (int)kdim, j0, wj, t_first, info)
     // rank-256/512 updates fold C into the k-loop (which needs kdim a
     // multiple of 16 ring depths); binary32 rank-512 updates use the deeper
-    // ring (not with bfloat16 rounding, which would then spill); the
-    // bfloat16 rounding of binary32 operands is a template switch
+    // ring (not with bfloat16 rounding, which would then spill), and so do
+    // binary32 updates of other ranks that are a multiple of 8 ring steps;
+    // the bfloat16 rounding of binary32 operands is a template switch
     if constexpr (sizeof(S) == 4) {
         if (kdim % 512 == 0 && !bf16) {
             MG_SYRK(true, 8, false);
         } else if (kdim % 256 == 0) {
             if (bf16) MG_SYRK(true, 4, true);
             else MG_SYRK(true, 4, false);
+        } else if (kdim % 32 == 0) {
+            // narrow slabs (the panel chain's rank-128 updates) are latency
+            // bound: the deeper ring keeps seven k-steps in flight
+            if (bf16) MG_SYRK(false, 8, true);
+            else MG_SYRK(false, 8, false);
         } else {
             if (bf16) MG_SYRK(false, 4, true);
             else MG_SYRK(false, 4, false);
@@ -854,24 +886,43 @@ mg_status syrk_lower_launch(hipStream_t st, S* Cm, const S* P, int64_t lda, int6
     return MG_OK;
 }
 
+// Factor of the diagonal block at k0 (width min(nb, n - k0)).
+template <typename T>
+static mg_status diag_step(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int64_t n, int64_t k0, int64_t nb,
+                           int32_t* info) {
+    const int64_t kb = std::min(nb, n - k0);
+    mg_status rc;
+    if ((rc = prof_begin(h, MG_PROF_DIAG, st))) return rc;
+    hipLaunchKernelGGL((k_factor_block<T, FB_MAX / 32, FB_MAX>), dim3(1), dim3(2 * FB_MAX), 0, st,
+                       A + idx(k0, k0, lda), lda, (int)kb, k0, info);
+    MG_LAUNCH_CHECK();
+    const double b = (double)kb;
+    return prof_end(h, MG_PROF_DIAG, b * b * b / 3 + b * b / 2 + b / 6, b * (b + 1) * sizeof(T), st);
+}
+
+// Panel rows [r0, r0 + m) of block column k0 (width kb) solved against its
+// factored diagonal block; rows are independent, so any split of the panel's
+// rows gives bitwise the same result.
+template <typename T>
+static mg_status panel_rows(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int64_t k0, int64_t kb, int64_t r0,
+                            int64_t m, int32_t* info) {
+    if (m <= 0) return MG_OK;
+    mg_status rc;
+    if ((rc = prof_begin(h, MG_PROF_TRSM, st))) return rc;
+    if ((rc = launch_trsm<T>(st, kb, A + idx(r0, k0, lda), A + idx(k0, k0, lda), lda, m, info, h->trail_lo == 2)))
+        return rc;
+    const double b = (double)kb;
+    return prof_end(h, MG_PROF_TRSM, (double)m * b * b, 2.0 * m * b * sizeof(T), st);
+}
+
 template <typename T>
 static mg_status panel_step(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int64_t n, int64_t k0, int64_t nb,
                            int32_t* info) {
     // factor the diagonal block at k0 and solve the panel below it
     const int64_t kb = std::min(nb, n - k0);
-    T* Akk = A + idx(k0, k0, lda);
     mg_status rc;
-    if ((rc = prof_begin(h, MG_PROF_DIAG, st))) return rc;
-    hipLaunchKernelGGL((k_factor_block<T, FB_MAX / 32, FB_MAX>), dim3(1), dim3(2 * FB_MAX), 0, st, Akk, lda, (int)kb, k0,
-                       info);
-    MG_LAUNCH_CHECK();
-    const double b = (double)kb;
-    if ((rc = prof_end(h, MG_PROF_DIAG, b * b * b / 3 + b * b / 2 + b / 6, b * (b + 1) * sizeof(T), st))) return rc;
-    const int64_t m = n - k0 - kb;
-    if (m <= 0) return MG_OK;
-    if ((rc = prof_begin(h, MG_PROF_TRSM, st))) return rc;
-    if ((rc = launch_trsm<T>(st, nb, A + idx(k0 + kb, k0, lda), Akk, lda, m, info))) return rc;
-    return prof_end(h, MG_PROF_TRSM, (double)m * b * b, 2.0 * m * b * sizeof(T), st);
+    if ((rc = diag_step<T>(h, st, A, lda, n, k0, nb, info))) return rc;
+    return panel_rows<T>(h, st, A, lda, k0, kb, k0 + kb, n - k0 - kb, info);
 }
 
 template <typename T>
@@ -894,21 +945,64 @@ static const __bf16* bf16_panel_of(mg_handle_t h, int64_t n, int64_t k0, int64_t
 }
 
 // Block column [k0, k0 + nb) factored completely (diagonal block and the
-// panel below it).  For nb <= 256 this is one panel_step; for nb = 512 the
-// column is itself factored right-looking in two halves of 256: the second
-// half's columns receive the first half's update (a 256-wide slab of the
-// trailing update) before their own panel step.  The caller then applies
-// the whole 512-wide panel to the trailing matrix in one rank-512 update,
-// which halves the passes over the trailing matrix's HBM-resident entries.
+// panel below it).  For nb <= 128 this is one panel_step; wider columns are
+// factored right-looking in sub-steps of 128: the columns after each
+// sub-step receive its update (a 128-wide slab of the trailing update)
+// before their own panel step.  The caller then applies the whole panel to
+// the trailing matrix in one rank-nb update, which divides the passes over
+// the trailing matrix's HBM-resident entries by nb / 128.
+//
+// pn (look-ahead schedule only): a second stream for the rows below the
+// block column.  The sub-steps on st then carry only what the next
+// sub-step's diagonal factor needs -- the factor, the panel rows inside the
+// block column and the slab's triangle there -- while pn solves the panel
+// rows below the block column (after the factor) and applies the slab to
+// them (after the in-block panel rows).  The tiles and rows are computed by
+// the same kernels in the same order as without pn, so the result is
+// bitwise the same; st waits for pn before the block column is used.
 template <typename T>
 static mg_status panel_block(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int64_t n, int64_t k0, int64_t nb,
-                             int32_t* info) {
+                             int32_t* info, hipStream_t pn = nullptr) {
     const int64_t nbi = std::min<int64_t>(nb, FB_MAX), end = std::min(n, k0 + nb);
     mg_status rc;
+    const bool split = pn && end < n && nb > nbi;
     for (int64_t k1 = k0; k1 < end; k1 += nbi) {
-        if ((rc = panel_step<T>(h, st, A, lda, n, k1, nbi, info))) return rc;
         const int64_t rest = end - (k1 + nbi);
-        if (rest > 0 && (rc = trailing<T>(h, st, A, lda, n, k1, nbi, info, 0, cdiv(rest, SY_BM)))) return rc;
+        if (!split) {
+            if ((rc = panel_step<T>(h, st, A, lda, n, k1, nbi, info))) return rc;
+            if (rest > 0 && (rc = trailing<T>(h, st, A, lda, n, k1, nbi, info, 0, cdiv(rest, SY_BM)))) return rc;
+            continue;
+        }
+        // (end < n and nb a multiple of 128: every sub-step is a full 128)
+        const int64_t e = k1 + nbi;
+        if ((rc = diag_step<T>(h, st, A, lda, n, k1, nbi, info))) return rc;
+        MG_HIP(hipEventRecord(h->ev_fac, st));
+        MG_HIP(hipStreamWaitEvent(pn, h->ev_fac, 0));
+        if ((rc = panel_rows<T>(h, pn, A, lda, k1, nbi, end, n - end, info))) return rc;
+        if (rest <= 0) continue;
+        if ((rc = panel_rows<T>(h, st, A, lda, k1, nbi, e, rest, info))) return rc;
+        MG_HIP(hipEventRecord(h->ev_head, st));
+        MG_HIP(hipStreamWaitEvent(pn, h->ev_head, 0));
+        const int bf = h->trail_lo == 2 ? 1 : 0;
+        const int64_t wj = cdiv(rest, SY_BM);
+        // the slab's triangle inside the block column, on st
+        if ((rc = prof_begin(h, MG_PROF_TRAILING_NARROW, st))) return rc;
+        if ((rc = syrk_lower_launch<T>(st, A + idx(e, e, lda), A + idx(e, k1, lda), lda, rest, nbi, info, 0, -1, bf)))
+            return rc;
+        const double r = (double)rest, b = (double)nbi, mr = (double)(n - end);
+        if ((rc = prof_end(h, MG_PROF_TRAILING_NARROW, b * r * (r + 1), (r * (r + 1) + r * b) * sizeof(T), st)))
+            return rc;
+        // its tiles below the block column, on pn
+        if ((rc = prof_begin(h, MG_PROF_TRAILING_NARROW, pn))) return rc;
+        if ((rc = syrk_lower_launch<T>(pn, A + idx(e, e, lda), A + idx(e, k1, lda), lda, n - e, nbi, info, 0, wj, bf,
+                                       wj * (wj + 1) / 2)))
+            return rc;
+        if ((rc = prof_end(h, MG_PROF_TRAILING_NARROW, 2.0 * b * mr * r, (2.0 * mr * r + mr * b) * sizeof(T), pn)))
+            return rc;
+    }
+    if (split) {
+        MG_HIP(hipEventRecord(h->ev_pan, pn));
+        MG_HIP(hipStreamWaitEvent(st, h->ev_pan, 0));
     }
     const __bf16* Pt = bf16_panel_of<T>(h, n, k0, nb, end - k0);
     const int64_t m = n - end;
@@ -989,6 +1083,10 @@ mg_status ensure_streams(mg_handle_t h) {
     h->side_mode = h->lookahead;
     if (h->chain) return MG_OK;
     MG_HIP(hipStreamCreateWithFlags(&h->chain, hipStreamNonBlocking));
+    MG_HIP(hipStreamCreateWithFlags(&h->pan, hipStreamNonBlocking));
+    MG_HIP(hipEventCreateWithFlags(&h->ev_fac, hipEventDisableTiming));
+    MG_HIP(hipEventCreateWithFlags(&h->ev_head, hipEventDisableTiming));
+    MG_HIP(hipEventCreateWithFlags(&h->ev_pan, hipEventDisableTiming));
     MG_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
     MG_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
     MG_HIP(hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming));
@@ -1031,7 +1129,7 @@ mg_status potrf_impl(mg_handle_t h, int64_t n, T* A, int64_t lda, int32_t* info)
     MG_HIP(hipEventRecord(h->ev_fork, st));
     MG_HIP(hipStreamWaitEvent(ch, h->ev_fork, 0));
     MG_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-    if ((rc = panel_block<T>(h, ch, A, lda, n, 0, nb, info))) return rc;
+    if ((rc = panel_block<T>(h, ch, A, lda, n, 0, nb, info, h->pan))) return rc;
     for (int64_t k = 0; k + 1 < nsteps; ++k) {
         const int64_t k0 = k * nb;
         if ((rc = trailing<T>(h, ch, A, lda, n, k0, nb, info, 0, wnext))) return rc;
@@ -1040,7 +1138,7 @@ mg_status potrf_impl(mg_handle_t h, int64_t n, T* A, int64_t lda, int32_t* info)
         if ((rc = trailing<T>(h, h->side, A, lda, n, k0, nb, info, wnext, wnext))) return rc;
         MG_HIP(hipEventRecord(h->ev_rest, h->side));         // block column k+2 has every update but panel k+1's
         if ((rc = trailing<T>(h, h->side, A, lda, n, k0, nb, info, 2 * wnext, -1))) return rc;
-        if ((rc = panel_block<T>(h, ch, A, lda, n, k0 + nb, nb, info))) return rc;
+        if ((rc = panel_block<T>(h, ch, A, lda, n, k0 + nb, nb, info, h->pan))) return rc;
         MG_HIP(hipStreamWaitEvent(ch, h->ev_rest, 0));
     }
     MG_HIP(hipEventRecord(h->ev_rest, h->side));             // the side stream's last rest_b
@@ -1053,8 +1151,8 @@ mg_status potrf_impl(mg_handle_t h, int64_t n, T* A, int64_t lda, int32_t* info)
 template mg_status potrf_impl<double>(mg_handle_t, int64_t, double*, int64_t, int32_t*);
 template mg_status potrf_impl<float>(mg_handle_t, int64_t, float*, int64_t, int32_t*);
 template mg_status syrk_lower_launch<double>(hipStream_t, double*, const double*, int64_t, int64_t, int64_t,
-                                             const int32_t*, int64_t, int64_t, int);
+                                             const int32_t*, int64_t, int64_t, int, int64_t);
 template mg_status syrk_lower_launch<float>(hipStream_t, float*, const float*, int64_t, int64_t, int64_t,
-                                            const int32_t*, int64_t, int64_t, int);
+                                            const int32_t*, int64_t, int64_t, int, int64_t);
 
 }  // namespace mg
