@@ -552,13 +552,13 @@ __device__ __forceinline__ f32x4 mma_xzt_bf16(f32x4 acc, bf16x8 x, bf16x8 z) {
 // register-ring form above keeps only three 32-wide k-steps in flight, so at
 // bfloat16 MFMA rates (a k-step is ~0.1 us of matrix-pipe time per wave)
 // nearly every step waits for a round trip to memory.  Here the tile's two
-// 128-row operand blocks move in chunks of 128 k: all of a chunk's loads are
-// issued at once into registers (8 x 16 bytes per thread and operand),
+// 128-row operand blocks move in chunks of 64 k: all of a chunk's loads are
+// issued at once into registers (4 x 16 bytes per thread and operand),
 // written to padded LDS rows (16 bytes of padding per row: the 16 rows a
 // quarter-wave reads sit in distinct banks), and the four waves multiply from
-// LDS while the next chunk's loads are in flight.  Two workgroups share a CU
-// (70 KB of LDS each), so one's C read and first chunk overlap the other's
-// products, and a workgroup holds its CU for one tile only, so the narrow
+// LDS while the next chunk's loads are in flight.  Three workgroups share a
+// CU (37 KB of LDS each), so one's C read and first chunk overlap the
+// others' products, and a workgroup holds its CU for one tile only, so the narrow
 // kernels of the panel chain find CUs as tiles finish.  Operand rows past the
 // block read as zero (the buffer resource ends at the panel's last row);
 // their products feed only outputs that are never stored.  Interior quarters
@@ -566,12 +566,13 @@ __device__ __forceinline__ f32x4 mma_xzt_bf16(f32x4 acc, bf16x8 x, bf16x8 z) {
 // per-lane offset plus uniform ones; diagonal and edge quarters take the
 // clamped, masked path of k_syrk_lower_bf16.  The MFMA sequence per output
 // tile is that kernel's, so the result is bitwise the same.
-constexpr int BFL_KC = 128;                  // k per LDS chunk
+constexpr int BFL_KC = 64;                   // k per LDS chunk
 constexpr int BFL_LD = BFL_KC * 2 + 16;      // LDS row stride in bytes
 constexpr int BFL_PC = BFL_KC / 8;           // 16-byte pieces per row of a chunk
 constexpr int BFL_U = 128 * BFL_PC / 256;    // pieces per thread and operand
+constexpr int BFL_RS = 256 / BFL_PC;         // rows between a thread's pieces
 
-__global__ __launch_bounds__(256, 2) void k_syrk_lower_bf16l(float* __restrict__ Cm, const __bf16* __restrict__ Pt,
+__global__ __launch_bounds__(256, 3) void k_syrk_lower_bf16l(float* __restrict__ Cm, const __bf16* __restrict__ Pt,
                                                              int64_t lda, int64_t m, int kdim, int64_t j0, int64_t wj,
                                                              const int32_t* info) {
     __shared__ __attribute__((aligned(16))) unsigned char Xs[128 * BFL_LD];
@@ -589,8 +590,9 @@ __global__ __launch_bounds__(256, 2) void k_syrk_lower_bf16l(float* __restrict__
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = w >> 1, wc = w & 1;
     const int ld = (int)lda;
-    // chunk c: thread tid moves piece tid % BFL_PC of rows tid / BFL_PC + 16 u
-    // of both blocks; rows at or past m lie beyond the resource and read 0
+    // chunk c: thread tid moves piece tid % BFL_PC of rows tid / BFL_PC +
+    // BFL_RS u of both blocks; rows at or past m lie beyond the resource and
+    // read 0
     const __amdgpu_buffer_rsrc_t prs = buf_rsrc(Pt, m * kdim * 2);
     const int pvo = ((tid / BFL_PC) * kdim + (tid % BFL_PC) * 8) * 2;
     const int xso = (int)(I * SY_BM) * kdim * 2, zso = (int)(J * SY_BM) * kdim * 2;
@@ -598,7 +600,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_lower_bf16l(float* __restrict__
     auto gload = [&](int c) {
 #pragma unroll
         for (int u = 0; u < BFL_U; ++u) {
-            const int so = (16 * u * kdim + c * BFL_KC) * 2;
+            const int so = (BFL_RS * u * kdim + c * BFL_KC) * 2;
             sx[u] = __builtin_amdgcn_raw_buffer_load_b128(prs, pvo, xso + so, 0);
             sz[u] = __builtin_amdgcn_raw_buffer_load_b128(prs, pvo, zso + so, 0);
         }
@@ -606,7 +608,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_lower_bf16l(float* __restrict__
     auto lstore = [&]() {
 #pragma unroll
         for (int u = 0; u < BFL_U; ++u) {
-            const int row = tid / BFL_PC + 16 * u, pc = tid % BFL_PC;
+            const int row = tid / BFL_PC + BFL_RS * u, pc = tid % BFL_PC;
             *(u32x4*)(Xs + row * BFL_LD + pc * 16) = sx[u];
             *(u32x4*)(Zs + row * BFL_LD + pc * 16) = sz[u];
         }
