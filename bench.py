@@ -255,7 +255,7 @@ def bench_mixed(torch, mg, synth, n: int, nrhs: int, cond: float, precision: str
                                 tr["launches"], FP32_PEAK_TFLOPS)
         else:
             # binary32 C read and written once, the packed bfloat16 panel read once
-            roof = roofline_obj("k_syrk_lower_bf16", tr["flops"], tr["bytes"], tr["ms"], tr["launches"],
+            roof = roofline_obj("k_syrk_lower_bf16l", tr["flops"], tr["bytes"], tr["ms"], tr["launches"],
                                 BF16_PEAK_TFLOPS)
     X = Xc.T
     B = Bc.T
