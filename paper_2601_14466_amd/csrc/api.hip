@@ -114,10 +114,6 @@ mg_status mg_destroy(mg_handle_t h) {
     if (h->ev_rest) (void)hipEventDestroy(h->ev_rest);
     if (h->side) (void)hipStreamDestroy(h->side);
     if (h->chain) (void)hipStreamDestroy(h->chain);
-    if (h->pan) (void)hipStreamDestroy(h->pan);
-    if (h->ev_fac) (void)hipEventDestroy(h->ev_fac);
-    if (h->ev_head) (void)hipEventDestroy(h->ev_head);
-    if (h->ev_pan) (void)hipEventDestroy(h->ev_pan);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     for (int k = 0; k < MG_PROF_KINDS; ++k) {
         for (hipEvent_t e : h->prof[k].start) (void)hipEventDestroy(e);

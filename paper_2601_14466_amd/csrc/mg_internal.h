@@ -32,9 +32,7 @@ struct mg_handle_s {
     // second stream and events for the look-ahead schedule (created by mg_create)
     hipStream_t side = nullptr;   // look-ahead: bulk trailing update
     hipStream_t chain = nullptr;  // look-ahead: next block column and panel chain
-    hipStream_t pan = nullptr;    // look-ahead: panel rows below a wide block column
     hipEvent_t ev_fork = nullptr, ev_panel = nullptr, ev_rest = nullptr, ev_join = nullptr;
-    hipEvent_t ev_fac = nullptr, ev_head = nullptr, ev_pan = nullptr;  // chain <-> pan hand-offs
 };
 
 namespace mg {

@@ -414,15 +414,15 @@ __device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, int vo
 template <typename S, bool FOLD, int RG, bool BF>
 __global__ __launch_bounds__(256, 2) void k_syrk_lower(S* __restrict__ Cm, const S* __restrict__ P,
                                                        int64_t lda, int64_t m, int kdim, int64_t j0, int64_t wj,
-                                                       int64_t t_first, const int32_t* info) {
+                                                       const int32_t* info) {
     if (*info != 0) return;
     const int64_t T = (m + SY_BM - 1) / SY_BM;
-    const int64_t ntiles = slab_tiles(T, j0, wj) - t_first;  // tiles t_first.. of the slab
+    const int64_t ntiles = slab_tiles(T, j0, wj);
     const int64_t per = gridDim.x / 8;
     const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (t >= ntiles) return;
     int64_t I, J;
-    trailing_tile(t + t_first, T, j0, wj, I, J);
+    trailing_tile(t, T, j0, wj, I, J);
     constexpr int ES = (int)sizeof(S);
     const int tid = threadIdx.x, l = tid & 63, i = l & 15, g = l >> 4;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -839,18 +839,13 @@ static mg_status launch_trsm(hipStream_t st, int64_t nb, S* P, const S* Lkk, int
     return MG_OK;
 }
 
-// t_first: skip the slab's first t_first tiles (in the slab's own order; for
-// a narrow slab, t_first = wj (wj + 1) / 2 leaves the tiles below its
-// diagonal triangle).
 template <typename S>
 mg_status syrk_lower_launch(hipStream_t st, S* Cm, const S* P, int64_t lda, int64_t m, int64_t kdim,
-                            const int32_t* info, int64_t j0 = 0, int64_t wj = -1, int bf16 = 0,
-                            int64_t t_first = 0) {
+                            const int32_t* info, int64_t j0 = 0, int64_t wj = -1, int bf16 = 0) {
     const int64_t T = cdiv(m, SY_BM);
     if (wj < 0) wj = T - j0;
     if (j0 >= T || wj <= 0) return MG_OK;
-    const int64_t ntiles = slab_tiles(T, j0, wj) - t_first;
-    if (ntiles <= 0 || t_first < 0) return MG_OK;
+    const int64_t ntiles = slab_tiles(T, j0, wj);
     const int64_t grid = 8 * cdiv(ntiles, 8);
     // every byte offset the kernel forms from P or from a quarter's corner
     // must fit in 31 bits
@@ -858,7 +853,7 @@ mg_status syrk_lower_launch(hipStream_t st, S* Cm, const S* P, int64_t lda, int6
         return MG_ERR_UNSUPPORTED;
 #define MG_SYRK(FOLD_, RG_, BF_)                                                                             \
     hipLaunchKernelGGL((k_syrk_lower<S, FOLD_, RG_, BF_>), dim3((unsigned)grid), dim3(256), 0, st, Cm, P, lda, m, \
-                       (int)kdim, j0, wj, t_first, info)
+                       (int)kdim, j0, wj, info)
     // rank-256/512 updates fold C into the k-loop (which needs kdim a
     // multiple of 16 ring depths); binary32 rank-512 updates use the deeper
     // ring (not with bfloat16 rounding, which would then spill), and so do
@@ -953,58 +948,15 @@ static const __bf16* bf16_panel_of(mg_handle_t h, int64_t n, int64_t k0, int64_t
 // before their own panel step.  The caller then applies the whole panel to
 // the trailing matrix in one rank-nb update, which divides the passes over
 // the trailing matrix's HBM-resident entries by nb / 128.
-//
-// pn (look-ahead schedule only): a second stream for the rows below the
-// block column.  The sub-steps on st then carry only what the next
-// sub-step's diagonal factor needs -- the factor, the panel rows inside the
-// block column and the slab's triangle there -- while pn solves the panel
-// rows below the block column (after the factor) and applies the slab to
-// them (after the in-block panel rows).  The tiles and rows are computed by
-// the same kernels in the same order as without pn, so the result is
-// bitwise the same; st waits for pn before the block column is used.
 template <typename T>
 static mg_status panel_block(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int64_t n, int64_t k0, int64_t nb,
-                             int32_t* info, hipStream_t pn = nullptr) {
+                             int32_t* info) {
     const int64_t nbi = std::min<int64_t>(nb, FB_MAX), end = std::min(n, k0 + nb);
     mg_status rc;
-    const bool split = pn && end < n && nb > nbi;
     for (int64_t k1 = k0; k1 < end; k1 += nbi) {
+        if ((rc = panel_step<T>(h, st, A, lda, n, k1, nbi, info))) return rc;
         const int64_t rest = end - (k1 + nbi);
-        if (!split) {
-            if ((rc = panel_step<T>(h, st, A, lda, n, k1, nbi, info))) return rc;
-            if (rest > 0 && (rc = trailing<T>(h, st, A, lda, n, k1, nbi, info, 0, cdiv(rest, SY_BM)))) return rc;
-            continue;
-        }
-        // (end < n and nb a multiple of 128: every sub-step is a full 128)
-        const int64_t e = k1 + nbi;
-        if ((rc = diag_step<T>(h, st, A, lda, n, k1, nbi, info))) return rc;
-        MG_HIP(hipEventRecord(h->ev_fac, st));
-        MG_HIP(hipStreamWaitEvent(pn, h->ev_fac, 0));
-        if ((rc = panel_rows<T>(h, pn, A, lda, k1, nbi, end, n - end, info))) return rc;
-        if (rest <= 0) continue;
-        if ((rc = panel_rows<T>(h, st, A, lda, k1, nbi, e, rest, info))) return rc;
-        MG_HIP(hipEventRecord(h->ev_head, st));
-        MG_HIP(hipStreamWaitEvent(pn, h->ev_head, 0));
-        const int bf = h->trail_lo == 2 ? 1 : 0;
-        const int64_t wj = cdiv(rest, SY_BM);
-        // the slab's triangle inside the block column, on st
-        if ((rc = prof_begin(h, MG_PROF_TRAILING_NARROW, st))) return rc;
-        if ((rc = syrk_lower_launch<T>(st, A + idx(e, e, lda), A + idx(e, k1, lda), lda, rest, nbi, info, 0, -1, bf)))
-            return rc;
-        const double r = (double)rest, b = (double)nbi, mr = (double)(n - end);
-        if ((rc = prof_end(h, MG_PROF_TRAILING_NARROW, b * r * (r + 1), (r * (r + 1) + r * b) * sizeof(T), st)))
-            return rc;
-        // its tiles below the block column, on pn
-        if ((rc = prof_begin(h, MG_PROF_TRAILING_NARROW, pn))) return rc;
-        if ((rc = syrk_lower_launch<T>(pn, A + idx(e, e, lda), A + idx(e, k1, lda), lda, n - e, nbi, info, 0, wj, bf,
-                                       wj * (wj + 1) / 2)))
-            return rc;
-        if ((rc = prof_end(h, MG_PROF_TRAILING_NARROW, 2.0 * b * mr * r, (2.0 * mr * r + mr * b) * sizeof(T), pn)))
-            return rc;
-    }
-    if (split) {
-        MG_HIP(hipEventRecord(h->ev_pan, pn));
-        MG_HIP(hipStreamWaitEvent(st, h->ev_pan, 0));
+        if (rest > 0 && (rc = trailing<T>(h, st, A, lda, n, k1, nbi, info, 0, cdiv(rest, SY_BM)))) return rc;
     }
     const __bf16* Pt = bf16_panel_of<T>(h, n, k0, nb, end - k0);
     const int64_t m = n - end;
@@ -1085,10 +1037,6 @@ mg_status ensure_streams(mg_handle_t h) {
     h->side_mode = h->lookahead;
     if (h->chain) return MG_OK;
     MG_HIP(hipStreamCreateWithFlags(&h->chain, hipStreamNonBlocking));
-    MG_HIP(hipStreamCreateWithFlags(&h->pan, hipStreamNonBlocking));
-    MG_HIP(hipEventCreateWithFlags(&h->ev_fac, hipEventDisableTiming));
-    MG_HIP(hipEventCreateWithFlags(&h->ev_head, hipEventDisableTiming));
-    MG_HIP(hipEventCreateWithFlags(&h->ev_pan, hipEventDisableTiming));
     MG_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
     MG_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
     MG_HIP(hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming));
@@ -1131,7 +1079,7 @@ mg_status potrf_impl(mg_handle_t h, int64_t n, T* A, int64_t lda, int32_t* info)
     MG_HIP(hipEventRecord(h->ev_fork, st));
     MG_HIP(hipStreamWaitEvent(ch, h->ev_fork, 0));
     MG_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-    if ((rc = panel_block<T>(h, ch, A, lda, n, 0, nb, info, h->pan))) return rc;
+    if ((rc = panel_block<T>(h, ch, A, lda, n, 0, nb, info))) return rc;
     for (int64_t k = 0; k + 1 < nsteps; ++k) {
         const int64_t k0 = k * nb;
         if ((rc = trailing<T>(h, ch, A, lda, n, k0, nb, info, 0, wnext))) return rc;
@@ -1140,7 +1088,7 @@ mg_status potrf_impl(mg_handle_t h, int64_t n, T* A, int64_t lda, int32_t* info)
         if ((rc = trailing<T>(h, h->side, A, lda, n, k0, nb, info, wnext, wnext))) return rc;
         MG_HIP(hipEventRecord(h->ev_rest, h->side));         // block column k+2 has every update but panel k+1's
         if ((rc = trailing<T>(h, h->side, A, lda, n, k0, nb, info, 2 * wnext, -1))) return rc;
-        if ((rc = panel_block<T>(h, ch, A, lda, n, k0 + nb, nb, info, h->pan))) return rc;
+        if ((rc = panel_block<T>(h, ch, A, lda, n, k0 + nb, nb, info))) return rc;
         MG_HIP(hipStreamWaitEvent(ch, h->ev_rest, 0));
     }
     MG_HIP(hipEventRecord(h->ev_rest, h->side));             // the side stream's last rest_b
@@ -1153,8 +1101,8 @@ mg_status potrf_impl(mg_handle_t h, int64_t n, T* A, int64_t lda, int32_t* info)
 template mg_status potrf_impl<double>(mg_handle_t, int64_t, double*, int64_t, int32_t*);
 template mg_status potrf_impl<float>(mg_handle_t, int64_t, float*, int64_t, int32_t*);
 template mg_status syrk_lower_launch<double>(hipStream_t, double*, const double*, int64_t, int64_t, int64_t,
-                                             const int32_t*, int64_t, int64_t, int, int64_t);
+                                             const int32_t*, int64_t, int64_t, int);
 template mg_status syrk_lower_launch<float>(hipStream_t, float*, const float*, int64_t, int64_t, int64_t,
-                                            const int32_t*, int64_t, int64_t, int, int64_t);
+                                            const int32_t*, int64_t, int64_t, int);
 
 }  // namespace mg
