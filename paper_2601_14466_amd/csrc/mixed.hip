@@ -26,27 +26,24 @@
 namespace mg {
 
 // ---------------------------------------------------------------- casts
-// W = fl32(A) on the lower triangle (column j, rows j..n-1); columns are
-// strided over grid y, which the host caps below the grid-y limit.
-__global__ __launch_bounds__(256) void k_cast_lower_f64_f32(const double* __restrict__ A, int64_t lda,
-                                                            float* __restrict__ W, int64_t ldw, int64_t n) {
-    for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
-        for (int64_t i = j + (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-            W[idx(i, j, ldw)] = (float)A[idx(i, j, lda)];
+// W = A (converted to W's type) on the lower triangle (column j, rows
+// j..n-1): the binary32 working copy, and the FP64 copy of the fallback.
+// Workgroup b converts columns b and n - 1 - b (n + 1 entries together, the
+// same for every workgroup, so no launch is empty or long); workgroups are
+// strided over the (n + 1) / 2 pairs.
+template <typename D>
+__global__ __launch_bounds__(256) void k_copy_lower(const double* __restrict__ A, int64_t lda, D* __restrict__ W,
+                                                    int64_t ldw, int64_t n) {
+    for (int64_t b = blockIdx.x; b < (n + 1) / 2; b += gridDim.x) {
+        const int64_t j2 = n - 1 - b;
+        for (int64_t i = b + threadIdx.x; i < n; i += 256) W[idx(i, b, ldw)] = (D)A[idx(i, b, lda)];
+        if (j2 != b)
+            for (int64_t i = j2 + threadIdx.x; i < n; i += 256) W[idx(i, j2, ldw)] = (D)A[idx(i, j2, lda)];
+    }
 }
 
-// copy the lower triangle of A (FP64) into W (FP64), columns as above
-__global__ __launch_bounds__(256) void k_copy_lower_f64(const double* __restrict__ A, int64_t lda,
-                                                        double* __restrict__ W, int64_t ldw, int64_t n) {
-    for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
-        for (int64_t i = j + (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-            W[idx(i, j, ldw)] = A[idx(i, j, lda)];
-}
-
-// grid for the two lower-triangle kernels: x covers a column, y strides the columns
 static inline dim3 lower_grid(int64_t n) {
-    return dim3((unsigned)std::min<int64_t>(std::max<int64_t>(1, cdiv(n, 256)), 64),
-                (unsigned)std::min<int64_t>(std::max<int64_t>(1, n), 32768));
+    return dim3((unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + 1) / 2), 65535));
 }
 
 // D (n x nrhs, ld n, FP32) = fl32(S) ; S FP64 with leading dimension lds
@@ -349,7 +346,7 @@ mg_status posv_mixed_impl(mg_handle_t h, int lo, int64_t n, int64_t nrhs, const 
     h->trail_lo = (lo == MG_PREC_BF16) ? 2 : 1;
     h->bf16_panel = (lo == MG_PREC_BF16) ? (void*)(base + L.o_p16) : nullptr;
     // 1. working copy and low-precision factor
-    hipLaunchKernelGGL(k_cast_lower_f64_f32, lower_grid(n), dim3(256), 0, st, A, lda, Aw, n, n);
+    hipLaunchKernelGGL(k_copy_lower<float>, lower_grid(n), dim3(256), 0, st, A, lda, Aw, n, n);
     MG_LAUNCH_CHECK();
     rc = potrf_impl<float>(h, n, Aw, n, info_lo);
     h->trail_lo = saved_trail;
@@ -437,7 +434,7 @@ mg_status posv_mixed_impl(mg_handle_t h, int lo, int64_t n, int64_t nrhs, const 
         // 5. FP64 fallback on a copy of A (A itself is const)
         res->fell_back = 1;
         double* Ad = (double*)(base + L.o_aw);
-        hipLaunchKernelGGL(k_copy_lower_f64, lower_grid(n), dim3(256), 0, st, A, lda, Ad, n, n);
+        hipLaunchKernelGGL(k_copy_lower<double>, lower_grid(n), dim3(256), 0, st, A, lda, Ad, n, n);
         MG_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_copy_block, dim3(grid1(n * nrhs)), dim3(256), 0, st, B, ldb, X, ldx, n, nrhs);
         MG_LAUNCH_CHECK();

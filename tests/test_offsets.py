@@ -8,10 +8,10 @@ their extremes for the mixed-precision configuration's largest order
 (n = 65536: the binary32 working copy and the FP64 fallback copy, both with
 leading dimension n, block columns of 512 and their rank-128 steps), checks
 that every one stays below 2^31 and that the host guard admits these sizes
-while refusing the first sizes at which an offset would overflow.  Kernels
-that index with 64-bit element offsets (the packed bfloat16 panel copy, the
-residual, the sweeps, the diagonal factor and panel solve) are checked for
-that by reading their source."""
+while refusing the first sizes at which an offset would overflow; the same
+for the LDS-staged bfloat16 update.  Kernels that index with 64-bit element
+offsets (the packed bfloat16 panel copy, the residual, the sweeps, the
+lower-triangle copies) are checked for that by reading their source."""
 import os
 import re
 
@@ -46,6 +46,51 @@ def syrk_bf16_offsets(m, kdim, lda):
     xo = ((m - 1) * kdim + 8 * 3) * 2
     soff = (kdim // 32 - 1) * 64
     return dict(c_off=c_off, xo=xo, zo=xo, soff=soff, load=xo + soff + 16)
+
+
+def bf16l_guard_ok(m, kb):
+    """The launch guard of the LDS-staged bfloat16 update (64-k chunks)."""
+    return kb % 64 == 0 and (m + 128) * kb * 2 < LIM
+
+
+def syrk_bf16l_offsets(m, kdim, lda):
+    """k_syrk_lower_bf16l: the row-major bfloat16 panel moved in 64-k chunks
+    of 16-byte pieces (8 per row): lane offset ((tid / 8) kdim + 8 (tid % 8))
+    2 bytes, tid < 256; per-tile offset I 128 kdim 2 bytes, I < ceil(m / 128);
+    per-piece offset (32 u kdim + 64 c) 2 bytes, u < 4, c < kdim / 64; C as
+    in k_syrk_lower (interior quarters: the same entries, split into a lane
+    part (i + 4 g lda) 4 and uniform parts 16 bi 4 and (16 bj + r) lda 4)."""
+    pvo = (31 * kdim + 8 * 7) * 2
+    xso = (-(-m // 128) - 1) * 128 * kdim * 2
+    so = (32 * 3 * kdim + (kdim // 64 - 1) * 64) * 2
+    c_lane = (15 + 4 * 3 * lda) * 4
+    c_uni = 16 * 3 * 4 + (16 * 3 + 3) * lda * 4
+    return dict(pvo=pvo, xso=xso, so=so, load=pvo + xso + so + 16, c_lane=c_lane, c_uni=c_uni,
+                c_sum=c_lane + c_uni)
+
+
+@pytest.mark.parametrize("kdim", [256, 512])
+def test_bf16_lds_update_offsets_at_n65536(kdim):
+    """At the largest order the bfloat16 mode runs (its block columns are 256
+    or 512 wide), every offset of the LDS-staged update fits and the guard
+    admits the launch."""
+    n = 65536
+    for m in (n - kdim, n // 2, 129, 1):
+        assert bf16l_guard_ok(m, kdim)
+        for k, v in syrk_bf16l_offsets(m, kdim, n).items():
+            assert 0 <= v < LIM, (kdim, m, k, v)
+
+
+def test_bf16_lds_guard_is_tight():
+    """Wherever the guard admits the launch the last operand load stays
+    below 2^31 bytes; just past its edge it refuses."""
+    for kdim in (64, 256, 512, 1024):
+        m = LIM // (2 * kdim) - 128 - 1
+        assert bf16l_guard_ok(m, kdim) and syrk_bf16l_offsets(m, kdim, 1)["load"] < LIM
+        assert not bf16l_guard_ok(m + 1, kdim)
+    src = open(os.path.join(CSRC, "potrf.hip")).read()
+    assert "kb % BFL_KC == 0 && (m + 128) * kb * 2 < ((int64_t)1 << 31)" in src
+    assert "constexpr int BFL_KC = 64;" in src
 
 
 @pytest.mark.parametrize("es,label", [(4, "binary32 working copy"), (8, "FP64 fallback copy")])
@@ -105,7 +150,8 @@ def test_library_guard_matches_the_formula():
     ("mixed.hip", "k_sym_rowprod", r"\(size_t\)blockIdx\.y \* n \+ gi"),
     ("mixed.hip", "k_sym_finish", r"\(\(size_t\)sp \* n \+ gi\)"),
     ("potrs.hip", "k_sweep", r"L\[idx\(rwc, c0 \+ c, lda\)\]"),
-    ("mixed.hip", "k_cast_lower_f64_f32", r"W\[idx\(i, j, ldw\)\]"),
+    ("mixed.hip", "k_copy_lower", r"W\[idx\(i, b, ldw\)\] = \(D\)A\[idx\(i, b, lda\)\]"),
+    ("mixed.hip", "k_copy_lower", r"W\[idx\(i, j2, ldw\)\] = \(D\)A\[idx\(i, j2, lda\)\]"),
 ])
 def test_other_kernels_use_64_bit_offsets(fname, kname, pattern):
     assert re.search(pattern, _kernel_text(fname, kname)), (fname, kname)
@@ -116,10 +162,10 @@ def test_idx_is_64_bit():
     assert "return (size_t)i + (size_t)j * (size_t)ld;" in src
 
 
-def test_lower_triangle_kernels_grid_y_capped():
-    """The cast and copy kernels of the mixed path stride columns over grid
-    y instead of launching one row of workgroups per column (n = 65536 would
-    sit on the grid-y limit)."""
+def test_lower_triangle_kernels_grid_capped():
+    """The cast and copy kernel of the mixed path strides pairs of columns
+    over a one-dimensional grid capped at 65535 workgroups (one workgroup per
+    column would sit on the grid-y limit at n = 65536)."""
     src = open(os.path.join(CSRC, "mixed.hip")).read()
-    assert "for (int64_t j = blockIdx.y; j < n; j += gridDim.y)" in src
-    assert "(unsigned)std::min<int64_t>(std::max<int64_t>(1, n), 32768)" in src
+    assert "for (int64_t b = blockIdx.x; b < (n + 1) / 2; b += gridDim.x)" in src
+    assert "dim3((unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + 1) / 2), 65535))" in src
