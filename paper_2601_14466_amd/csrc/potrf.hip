@@ -207,6 +207,17 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) voi
     }
 }
 
+// bfloat16 rounding (nearest-even on the bit pattern) of a binary32 value,
+// widened back to binary32; used for the BF16 trailing-update operands.
+__device__ __forceinline__ float round_bf16(float x) {
+    unsigned u = __builtin_bit_cast(unsigned, x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return x;
+    u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    return __builtin_bit_cast(float, u);
+}
+__device__ __forceinline__ double lo_round(double x, int) { return x; }
+__device__ __forceinline__ float lo_round(float x, int bf16) { return bf16 ? round_bf16(x) : x; }
+
 // ---------------------------------------------------------------------------
 // Panel TRSM: X = P L^{-T} in place for the m x NB panel P, L = L_kk (NB x NB
 // lower, NB <= FB_MAX).  The NB/16 (NB/16 + 1)/2 lower 16 x 16 tiles of L_kk
@@ -224,7 +235,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) voi
 template <typename S, int NB, int RB>
 // (At most 256 registers per wave, for the same reason as k_factor_block.)
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_trsm_panel(S* __restrict__ P, const S* __restrict__ Lkk,
-                                                    int64_t lda, int64_t m, const int32_t* info) {
+                                                    int64_t lda, int64_t m, const int32_t* info,
+                                                    __bf16* __restrict__ Pq, int ldq) {
     constexpr int NT = NB / 16, NTT = NT * (NT + 1) / 2;
     __shared__ S Lt[NTT][16 * 17];  // tile (t, p), p <= t, at t (t + 1) / 2 + p: row r, column c at r*17 + c
     __shared__ S Pv[NT][16];        // pivots of the diagonal tiles
@@ -275,6 +287,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int t = 0; t < NT; ++t) {
         store_tile<S, S>(x[t], P, lda, R, 16 * t, m, NB, false);
         if constexpr (RB == 2) store_tile<S, S>(u[t], P, lda, R + 16, 16 * t, m, NB, false);
+    }
+    if constexpr (sizeof(S) == 4) {
+        // bfloat16 mode: the solved rows also go to the block column's
+        // row-major bfloat16 copy (a lane's four values are four consecutive
+        // columns: one 8-byte store), rounded to nearest even (round_bf16)
+        if (Pq) {
+#pragma unroll
+            for (int h2 = 0; h2 < RB; ++h2) {
+                const int64_t row = R + 16 * h2 + i;
+                if (row >= m) continue;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const V4<S>& y = h2 ? u[t] : x[t];
+                    unsigned q[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) q[r] = __builtin_bit_cast(unsigned, round_bf16(y[r])) >> 16;
+                    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+                    const u32x2 v = {q[0] | (q[1] << 16), q[2] | (q[3] << 16)};
+                    *(u32x2*)(Pq + row * ldq + 16 * t + tcol<S>(g, 0)) = v;
+                }
+            }
+        }
     }
 }
 
@@ -379,16 +413,6 @@ __device__ __forceinline__ void trailing_tile(int64_t t, int64_t T, int64_t j0, 
     J = __builtin_amdgcn_readfirstlane((int)c.J);
 }
 
-// bfloat16 rounding (nearest-even on the bit pattern) of a binary32 value,
-// widened back to binary32; used for the BF16 trailing-update operands.
-__device__ __forceinline__ float round_bf16(float x) {
-    unsigned u = __builtin_bit_cast(unsigned, x);
-    if ((u & 0x7f800000u) == 0x7f800000u) return x;
-    u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
-    return __builtin_bit_cast(float, u);
-}
-__device__ __forceinline__ double lo_round(double x, int) { return x; }
-__device__ __forceinline__ float lo_round(float x, int bf16) { return bf16 ? round_bf16(x) : x; }
 
 // Raw buffer access: a 128-bit resource (base, byte extent) that the compiler
 // keeps in scalar registers, plus a 32-bit per-lane byte offset.  Loads at or
@@ -535,7 +559,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk_lower(S* __restrict__ Cm, const
 // ---------------------------------------------------------------------------
 // bfloat16 trailing update (mixed precision, bfloat16 mode): lower(C) -= P P^T
 // with C in binary32 and P given as a row-major bfloat16 copy Pt (m x kdim,
-// leading dimension kdim, kdim % 128 == 0), products of bfloat16 inputs
+// row stride ldp, kdim % 32 == 0), products of bfloat16 inputs
 // accumulated in FP32 on the 16x16x32 bfloat16 matrix instruction.  Same
 // tiling, tile order, buffer-resource addressing and four-slot operand ring
 // as k_syrk_lower; each lane loads 8 consecutive k of one row (16 bytes) per
@@ -573,8 +597,8 @@ constexpr int BFL_U = 128 * BFL_PC / 256;    // pieces per thread and operand
 constexpr int BFL_RS = 256 / BFL_PC;         // rows between a thread's pieces
 
 __global__ __launch_bounds__(256, 3) void k_syrk_lower_bf16l(float* __restrict__ Cm, const __bf16* __restrict__ Pt,
-                                                             int64_t lda, int64_t m, int kdim, int64_t j0, int64_t wj,
-                                                             const int32_t* info) {
+                                                             int64_t lda, int64_t m, int kdim, int ldp, int64_t j0,
+                                                             int64_t wj, const int32_t* info) {
     __shared__ __attribute__((aligned(16))) unsigned char Xs[128 * BFL_LD];
     __shared__ __attribute__((aligned(16))) unsigned char Zs[128 * BFL_LD];
     if (*info != 0) return;
@@ -593,14 +617,14 @@ __global__ __launch_bounds__(256, 3) void k_syrk_lower_bf16l(float* __restrict__
     // chunk c: thread tid moves piece tid % BFL_PC of rows tid / BFL_PC +
     // BFL_RS u of both blocks; rows at or past m lie beyond the resource and
     // read 0
-    const __amdgpu_buffer_rsrc_t prs = buf_rsrc(Pt, m * kdim * 2);
-    const int pvo = ((tid / BFL_PC) * kdim + (tid % BFL_PC) * 8) * 2;
-    const int xso = (int)(I * SY_BM) * kdim * 2, zso = (int)(J * SY_BM) * kdim * 2;
+    const __amdgpu_buffer_rsrc_t prs = buf_rsrc(Pt, m * ldp * 2);
+    const int pvo = ((tid / BFL_PC) * ldp + (tid % BFL_PC) * 8) * 2;
+    const int xso = (int)(I * SY_BM) * ldp * 2, zso = (int)(J * SY_BM) * ldp * 2;
     u32x4 sx[BFL_U], sz[BFL_U];
     auto gload = [&](int c) {
 #pragma unroll
         for (int u = 0; u < BFL_U; ++u) {
-            const int so = (BFL_RS * u * kdim + c * BFL_KC) * 2;
+            const int so = (BFL_RS * u * ldp + c * BFL_KC) * 2;
             sx[u] = __builtin_amdgcn_raw_buffer_load_b128(prs, pvo, xso + so, 0);
             sz[u] = __builtin_amdgcn_raw_buffer_load_b128(prs, pvo, zso + so, 0);
         }
@@ -702,28 +726,9 @@ __global__ __launch_bounds__(256, 3) void k_syrk_lower_bf16l(float* __restrict__
     }
 }
 
-// Row-major bfloat16 copy of the m x kb panel P (column-major, lda): thread
-// per (row, 8 columns), reading down columns (coalesced) and writing 16
-// contiguous bytes; rounding to nearest even as round_bf16.
-__global__ __launch_bounds__(256) void k_pack_bf16(const float* __restrict__ P, int64_t lda, int64_t m, int kb,
-                                                   __bf16* __restrict__ Pt, const int32_t* info) {
-    if (*info != 0) return;
-    const int64_t groups = kb / 8, tot = m * groups;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
-        const int64_t row = e % m, gq = e / m;
-        bf16x8 v;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const float r = round_bf16(P[idx(row, gq * 8 + c, lda)]);
-            v[c] = __builtin_bit_cast(__bf16, (unsigned short)(__builtin_bit_cast(unsigned, r) >> 16));
-        }
-        *(bf16x8*)(Pt + row * kb + gq * 8) = v;
-    }
-}
-
 __global__ __launch_bounds__(256, 2) void k_syrk_lower_bf16(float* __restrict__ Cm, const __bf16* __restrict__ Pt,
-                                                            int64_t lda, int64_t m, int kdim, int64_t j0, int64_t wj,
-                                                            const int32_t* info) {
+                                                            int64_t lda, int64_t m, int kdim, int ldp, int64_t j0,
+                                                            int64_t wj, const int32_t* info) {
     if (*info != 0) return;
     const int64_t T = (m + SY_BM - 1) / SY_BM;
     const int64_t ntiles = slab_tiles(T, j0, wj);
@@ -767,8 +772,8 @@ __global__ __launch_bounds__(256, 2) void k_syrk_lower_bf16(float* __restrict__ 
     int xo[4], zo[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        xo[b] = (((int)sr0 + min(16 * b + i, rmax)) * kdim + 8 * g) * 2;
-        zo[b] = (((int)sc0 + min(16 * b + i, cmax)) * kdim + 8 * g) * 2;
+        xo[b] = (((int)sr0 + min(16 * b + i, rmax)) * ldp + 8 * g) * 2;
+        zo[b] = (((int)sc0 + min(16 * b + i, cmax)) * ldp + 8 * g) * 2;
     }
     const int nks = kdim / 32;
     bf16x8 xq[4][4], zq[4][4];
@@ -820,7 +825,7 @@ constexpr int64_t TRSM_TWO_ROWS = 12288;  // panel rows from which waves take tw
 
 template <typename S>
 static mg_status launch_trsm(hipStream_t st, int64_t nb, S* P, const S* Lkk, int64_t lda, int64_t m,
-                             const int32_t* info, bool latency) {
+                             const int32_t* info, bool latency, __bf16* Pq = nullptr, int ldq = 0) {
     // Tall panels (the look-ahead regime, where the solve shares the chip
     // with the trailing update) take two row blocks per wave, halving the
     // wave-time the solve holds; short ones one, for the shortest latency.
@@ -830,10 +835,10 @@ static mg_status launch_trsm(hipStream_t st, int64_t nb, S* P, const S* Lkk, int
     const dim3 block(256);
     const bool two = m >= TRSM_TWO_ROWS && !latency;
     const dim3 grid((unsigned)cdiv(m, two ? 128 : 64));
-    if (nb == 64 && two) hipLaunchKernelGGL((k_trsm_panel<S, 64, 2>), grid, block, 0, st, P, Lkk, lda, m, info);
-    else if (nb == 64) hipLaunchKernelGGL((k_trsm_panel<S, 64, 1>), grid, block, 0, st, P, Lkk, lda, m, info);
-    else if (nb == 128 && two) hipLaunchKernelGGL((k_trsm_panel<S, 128, 2>), grid, block, 0, st, P, Lkk, lda, m, info);
-    else if (nb == 128) hipLaunchKernelGGL((k_trsm_panel<S, 128, 1>), grid, block, 0, st, P, Lkk, lda, m, info);
+    if (nb == 64 && two) hipLaunchKernelGGL((k_trsm_panel<S, 64, 2>), grid, block, 0, st, P, Lkk, lda, m, info, Pq, ldq);
+    else if (nb == 64) hipLaunchKernelGGL((k_trsm_panel<S, 64, 1>), grid, block, 0, st, P, Lkk, lda, m, info, Pq, ldq);
+    else if (nb == 128 && two) hipLaunchKernelGGL((k_trsm_panel<S, 128, 2>), grid, block, 0, st, P, Lkk, lda, m, info, Pq, ldq);
+    else if (nb == 128) hipLaunchKernelGGL((k_trsm_panel<S, 128, 1>), grid, block, 0, st, P, Lkk, lda, m, info, Pq, ldq);
     else return MG_ERR_UNSUPPORTED;
     MG_LAUNCH_CHECK();
     return MG_OK;
@@ -883,6 +888,8 @@ mg_status syrk_lower_launch(hipStream_t st, S* Cm, const S* P, int64_t lda, int6
     return MG_OK;
 }
 
+constexpr int BF_LDP = 512;  // row stride of the bfloat16 panel copies (elements)
+
 // Factor of the diagonal block at k0 (width min(nb, n - k0)).
 template <typename T>
 static mg_status diag_step(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int64_t n, int64_t k0, int64_t nb,
@@ -902,24 +909,27 @@ static mg_status diag_step(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int
 // rows gives bitwise the same result.
 template <typename T>
 static mg_status panel_rows(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int64_t k0, int64_t kb, int64_t r0,
-                            int64_t m, int32_t* info) {
+                            int64_t m, int32_t* info, __bf16* Pq = nullptr) {
     if (m <= 0) return MG_OK;
     mg_status rc;
     if ((rc = prof_begin(h, MG_PROF_TRSM, st))) return rc;
-    if ((rc = launch_trsm<T>(st, kb, A + idx(r0, k0, lda), A + idx(k0, k0, lda), lda, m, info, h->trail_lo == 2)))
+    if ((rc = launch_trsm<T>(st, kb, A + idx(r0, k0, lda), A + idx(k0, k0, lda), lda, m, info, h->trail_lo == 2, Pq,
+                             BF_LDP)))
         return rc;
     const double b = (double)kb;
     return prof_end(h, MG_PROF_TRSM, (double)m * b * b, 2.0 * m * b * sizeof(T), st);
 }
 
+// Pq (bfloat16 mode): where the solved rows' bfloat16 copy goes (row stride
+// BF_LDP), or null.
 template <typename T>
 static mg_status panel_step(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int64_t n, int64_t k0, int64_t nb,
-                           int32_t* info) {
+                           int32_t* info, __bf16* Pq = nullptr) {
     // factor the diagonal block at k0 and solve the panel below it
     const int64_t kb = std::min(nb, n - k0);
     mg_status rc;
     if ((rc = diag_step<T>(h, st, A, lda, n, k0, nb, info))) return rc;
-    return panel_rows<T>(h, st, A, lda, k0, kb, k0 + kb, n - k0 - kb, info);
+    return panel_rows<T>(h, st, A, lda, k0, kb, k0 + kb, n - k0 - kb, info, Pq);
 }
 
 template <typename T>
@@ -927,18 +937,43 @@ static mg_status trailing(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int6
                          const int32_t* info, int64_t j0, int64_t wj);
 
 // bfloat16 mode: the row-major bfloat16 copy of block column k0's panel
-// (block columns of 256 or 512 only), or null.  Three buffers rotate over
-// consecutive block columns: the chain stream packs column k + 3 only after
-// waiting for the update stream's rest_a(k + 1), which that stream runs after
-// rest_b(k), the last reader of column k's copy.
+// (block columns of 256 or 512 only), or null.  Row r >= k0 of the block
+// column sits at row r - k0 of the copy, whose row stride is BF_LDP; each
+// 128-wide step of the column packs its columns for the rows below its
+// diagonal block as soon as they are solved.  Three buffers rotate over
+// consecutive block columns: the chain stream writes column k + 3's only
+// after waiting for the update stream's rest_a(k + 1), which that stream
+// runs after rest_b(k), the last reader of column k's copy.
 template <typename T>
-static const __bf16* bf16_panel_of(mg_handle_t h, int64_t n, int64_t k0, int64_t nb, int64_t kb) {
+static __bf16* bf16_panel(mg_handle_t h, int64_t n, int64_t k0, int64_t nb) {
     if constexpr (sizeof(T) != 4) {
         return nullptr;
     } else {
-        if (h->trail_lo != 2 || !h->bf16_panel || kb != nb || nb % 256 != 0 || nb > 512) return nullptr;
-        return (const __bf16*)h->bf16_panel + (size_t)((k0 / nb) % 3) * (size_t)n * 512;
+        if (h->trail_lo != 2 || !h->bf16_panel || nb % 256 != 0 || nb > BF_LDP) return nullptr;
+        return (__bf16*)h->bf16_panel + (size_t)((k0 / nb) % 3) * (size_t)n * BF_LDP;
     }
+}
+
+// lower(C) -= P P^T over tile columns [j0, j0 + wj) of the m x m binary32
+// matrix C (lda), P the m x kdim row-major bfloat16 copy at Pt (row stride
+// ldp): the LDS-staged kernel, or the register-ring one where a rank or size
+// does not fit its chunks and offsets.
+static mg_status bf16_update(hipStream_t st, float* C, int64_t lda, const __bf16* Pt, int ldp, int64_t m,
+                             int64_t kdim, int64_t j0, int64_t wj, const int32_t* info) {
+    const int64_t T_ = cdiv(m, SY_BM);
+    if (wj < 0) wj = T_ - j0;
+    if (m <= 0 || j0 >= T_ || wj <= 0) return MG_OK;
+    const int64_t ntiles = slab_tiles(T_, j0, wj);
+    const dim3 grid((unsigned)(8 * cdiv(ntiles, 8)));
+    if ((m + (kdim + 64) * lda) * 4 >= ((int64_t)1 << 31) - 65536 || kdim % 32 != 0) return MG_ERR_UNSUPPORTED;
+    if (kdim % BFL_KC == 0 && (m + 128) * ldp * 2 < ((int64_t)1 << 31))
+        hipLaunchKernelGGL(k_syrk_lower_bf16l, grid, dim3(256), 0, st, C, Pt, lda, m, (int)kdim, ldp, j0, wj, info);
+    else if ((m + 1) * ldp * 2 < ((int64_t)1 << 31))
+        hipLaunchKernelGGL(k_syrk_lower_bf16, grid, dim3(256), 0, st, C, Pt, lda, m, (int)kdim, ldp, j0, wj, info);
+    else
+        return MG_ERR_UNSUPPORTED;
+    MG_LAUNCH_CHECK();
+    return MG_OK;
 }
 
 // Block column [k0, k0 + nb) factored completely (diagonal block and the
@@ -947,24 +982,36 @@ static const __bf16* bf16_panel_of(mg_handle_t h, int64_t n, int64_t k0, int64_t
 // sub-step receive its update (a 128-wide slab of the trailing update)
 // before their own panel step.  The caller then applies the whole panel to
 // the trailing matrix in one rank-nb update, which divides the passes over
-// the trailing matrix's HBM-resident entries by nb / 128.
+// the trailing matrix's HBM-resident entries by nb / 128.  In bfloat16 mode
+// each sub-step's solved columns are packed into the block column's
+// bfloat16 copy (rows below its diagonal block) and its slab runs on the
+// bfloat16 matrix instruction from that copy.
 template <typename T>
 static mg_status panel_block(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int64_t n, int64_t k0, int64_t nb,
                              int32_t* info) {
     const int64_t nbi = std::min<int64_t>(nb, FB_MAX), end = std::min(n, k0 + nb);
+    __bf16* Pb = bf16_panel<T>(h, n, k0, nb);
     mg_status rc;
     for (int64_t k1 = k0; k1 < end; k1 += nbi) {
-        if ((rc = panel_step<T>(h, st, A, lda, n, k1, nbi, info))) return rc;
-        const int64_t rest = end - (k1 + nbi);
-        if (rest > 0 && (rc = trailing<T>(h, st, A, lda, n, k1, nbi, info, 0, cdiv(rest, SY_BM)))) return rc;
-    }
-    const __bf16* Pt = bf16_panel_of<T>(h, n, k0, nb, end - k0);
-    const int64_t m = n - end;
-    if (Pt && m > 0) {
-        const unsigned grid = (unsigned)std::min<int64_t>(cdiv(m * (nb / 8), 256), 8192);
-        hipLaunchKernelGGL(k_pack_bf16, dim3(grid), dim3(256), 0, st, (const float*)(A + idx(end, k0, lda)), lda, m,
-                           (int)nb, (__bf16*)Pt, info);
-        MG_LAUNCH_CHECK();
+        const int64_t e = k1 + nbi, rest = end - e;
+        // bfloat16 mode: the panel solve also writes this step's columns,
+        // rows e .. n - 1, into the copy (a step with rows below it is a
+        // full 128 columns)
+        __bf16* Pq = (Pb && e < n) ? Pb + (size_t)(e - k0) * BF_LDP + (size_t)(k1 - k0) : nullptr;
+        if ((rc = panel_step<T>(h, st, A, lda, n, k1, nbi, info, Pq))) return rc;
+        if (!Pb) {
+            if (rest > 0 && (rc = trailing<T>(h, st, A, lda, n, k1, nbi, info, 0, cdiv(rest, SY_BM)))) return rc;
+            continue;
+        }
+        if (rest <= 0) continue;
+        const int64_t mq = n - e;
+        if ((rc = prof_begin(h, MG_PROF_TRAILING_NARROW, st))) return rc;
+        const int64_t wj = cdiv(rest, SY_BM);
+        if ((rc = bf16_update(st, (float*)(A + idx(e, e, lda)), lda, Pq, BF_LDP, mq, nbi, 0, wj, info))) return rc;
+        const double c1 = (double)std::min(mq, wj * SY_BM), md = (double)mq, b = (double)nbi;
+        const double elems = c1 * md - c1 * (c1 - 1) / 2;
+        if ((rc = prof_end(h, MG_PROF_TRAILING_NARROW, 2.0 * b * elems, (2.0 * elems + md * b) * sizeof(T), st)))
+            return rc;
     }
     return MG_OK;
 }
@@ -981,18 +1028,13 @@ static mg_status trailing(mg_handle_t h, hipStream_t st, T* A, int64_t lda, int6
     // rank-256/512 updates run the C-folding kernel variant, narrower ones the other
     const int kind = (kb % 256 == 0) ? MG_PROF_TRAILING : MG_PROF_TRAILING_NARROW;
     if ((rc = prof_begin(h, kind, st))) return rc;
-    const __bf16* Pt = bf16_panel_of<T>(h, n, k0, nb, kb);
-    if (Pt) {
-        // bfloat16 mode, full block column: the panel was packed by panel_block
-        const int64_t ntiles = slab_tiles(T_, j0, wj);
-        if ((m + (int64_t)(kb + 64) * lda) * 4 >= ((int64_t)1 << 31) - 65536) return MG_ERR_UNSUPPORTED;
-        if (kb % BFL_KC == 0 && (m + 128) * kb * 2 < ((int64_t)1 << 31))
-            hipLaunchKernelGGL(k_syrk_lower_bf16l, dim3((unsigned)(8 * cdiv(ntiles, 8))), dim3(256), 0, st,
-                               (float*)(A + idx(e, e, lda)), Pt, lda, m, (int)kb, j0, wj, info);
-        else
-            hipLaunchKernelGGL(k_syrk_lower_bf16, dim3((unsigned)(8 * cdiv(ntiles, 8))), dim3(256), 0, st,
-                               (float*)(A + idx(e, e, lda)), Pt, lda, m, (int)kb, j0, wj, info);
-        MG_LAUNCH_CHECK();
+    const __bf16* Pb = kb == nb ? bf16_panel<T>(h, n, k0, nb) : nullptr;
+    if (Pb) {
+        // bfloat16 mode, full block column: its rows below the block were
+        // packed by panel_block
+        if ((rc = bf16_update(st, (float*)(A + idx(e, e, lda)), lda, Pb + (size_t)kb * BF_LDP, BF_LDP, m, kb, j0, wj,
+                              info)))
+            return rc;
     } else if ((rc = syrk_lower_launch<T>(st, A + idx(e, e, lda), A + idx(e, k0, lda), lda, m, kb, info, j0, wj,
                                           h->trail_lo == 2 ? 1 : 0))) {
         return rc;

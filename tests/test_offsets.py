@@ -10,8 +10,8 @@ leading dimension n, block columns of 512 and their rank-128 steps), checks
 that every one stays below 2^31 and that the host guard admits these sizes
 while refusing the first sizes at which an offset would overflow; the same
 for the LDS-staged bfloat16 update.  Kernels that index with 64-bit element
-offsets (the packed bfloat16 panel copy, the residual, the sweeps, the
-lower-triangle copies) are checked for that by reading their source."""
+offsets (the bfloat16 panel copy the panel solve writes, the residual, the
+sweeps, the lower-triangle copies) are checked for that by reading their source."""
 import os
 import re
 
@@ -38,42 +38,60 @@ def syrk_offsets(m, kdim, lda, es):
     return dict(c_off=c_off, xo=xo, zo=xo, soff=soff, load=xo + soff + es)
 
 
-def syrk_bf16_offsets(m, kdim, lda):
+def syrk_bf16_offsets(m, kdim, lda, ldp=512):
     """k_syrk_lower_bf16: C in binary32 as above; the row-major bfloat16
-    panel (leading dimension kdim) read 16 bytes at a time: lane offset
-    ((row) kdim + 8 g) 2 bytes, step offset kn 64 bytes, kn < kdim / 32."""
+    panel (row stride ldp: the block column's copy is 512 wide) read 16 bytes
+    at a time: lane offset ((row) ldp + 8 g) 2 bytes, step offset kn 64
+    bytes, kn < kdim / 32."""
     c_off = (63 + 63 * lda) * 4
-    xo = ((m - 1) * kdim + 8 * 3) * 2
+    xo = ((m - 1) * ldp + 8 * 3) * 2
     soff = (kdim // 32 - 1) * 64
     return dict(c_off=c_off, xo=xo, zo=xo, soff=soff, load=xo + soff + 16)
 
 
-def bf16l_guard_ok(m, kb):
+def bf16_ring_guard_ok(m, ldp=512):
+    """The copy's own guard for the register-ring bfloat16 update."""
+    return (m + 1) * ldp * 2 < LIM
+
+
+def test_bf16_ring_guard_is_tight():
+    """Where the copy's guard admits the register-ring kernel its last
+    operand load stays below 2^31 bytes; one row more and it refuses."""
+    ldp = 512
+    m = LIM // (2 * ldp) - 2
+    assert bf16_ring_guard_ok(m, ldp) and not bf16_ring_guard_ok(m + 1, ldp)
+    assert syrk_bf16_offsets(m, 512, 1, ldp)["load"] < LIM
+    src = open(os.path.join(CSRC, "potrf.hip")).read()
+    assert "(m + 1) * ldp * 2 < ((int64_t)1 << 31)" in src
+
+
+def bf16l_guard_ok(m, kdim, ldp=512):
     """The launch guard of the LDS-staged bfloat16 update (64-k chunks)."""
-    return kb % 64 == 0 and (m + 128) * kb * 2 < LIM
+    return kdim % 64 == 0 and (m + 128) * ldp * 2 < LIM
 
 
-def syrk_bf16l_offsets(m, kdim, lda):
-    """k_syrk_lower_bf16l: the row-major bfloat16 panel moved in 64-k chunks
-    of 16-byte pieces (8 per row): lane offset ((tid / 8) kdim + 8 (tid % 8))
-    2 bytes, tid < 256; per-tile offset I 128 kdim 2 bytes, I < ceil(m / 128);
-    per-piece offset (32 u kdim + 64 c) 2 bytes, u < 4, c < kdim / 64; C as
+def syrk_bf16l_offsets(m, kdim, lda, ldp=512):
+    """k_syrk_lower_bf16l: the row-major bfloat16 panel (row stride ldp)
+    moved in 64-k chunks of 16-byte pieces (8 per row): lane offset
+    ((tid / 8) ldp + 8 (tid % 8)) 2 bytes, tid < 256; per-tile offset
+    I 128 ldp 2 bytes, I < ceil(m / 128); per-piece offset
+    (32 u ldp + 64 c) 2 bytes, u < 4, c < kdim / 64; C as
     in k_syrk_lower (interior quarters: the same entries, split into a lane
     part (i + 4 g lda) 4 and uniform parts 16 bi 4 and (16 bj + r) lda 4)."""
-    pvo = (31 * kdim + 8 * 7) * 2
-    xso = (-(-m // 128) - 1) * 128 * kdim * 2
-    so = (32 * 3 * kdim + (kdim // 64 - 1) * 64) * 2
+    pvo = (31 * ldp + 8 * 7) * 2
+    xso = (-(-m // 128) - 1) * 128 * ldp * 2
+    so = (32 * 3 * ldp + (kdim // 64 - 1) * 64) * 2
     c_lane = (15 + 4 * 3 * lda) * 4
     c_uni = 16 * 3 * 4 + (16 * 3 + 3) * lda * 4
     return dict(pvo=pvo, xso=xso, so=so, load=pvo + xso + so + 16, c_lane=c_lane, c_uni=c_uni,
                 c_sum=c_lane + c_uni)
 
 
-@pytest.mark.parametrize("kdim", [256, 512])
+@pytest.mark.parametrize("kdim", [128, 256, 512])
 def test_bf16_lds_update_offsets_at_n65536(kdim):
-    """At the largest order the bfloat16 mode runs (its block columns are 256
-    or 512 wide), every offset of the LDS-staged update fits and the guard
-    admits the launch."""
+    """At the largest order the bfloat16 mode runs (block columns 256 or 512
+    wide, their rank-128 steps; the copy's rows are 512 wide), every offset
+    of the LDS-staged update fits and the guard admits the launch."""
     n = 65536
     for m in (n - kdim, n // 2, 129, 1):
         assert bf16l_guard_ok(m, kdim)
@@ -84,13 +102,15 @@ def test_bf16_lds_update_offsets_at_n65536(kdim):
 def test_bf16_lds_guard_is_tight():
     """Wherever the guard admits the launch the last operand load stays
     below 2^31 bytes; just past its edge it refuses."""
-    for kdim in (64, 256, 512, 1024):
-        m = LIM // (2 * kdim) - 128 - 1
-        assert bf16l_guard_ok(m, kdim) and syrk_bf16l_offsets(m, kdim, 1)["load"] < LIM
-        assert not bf16l_guard_ok(m + 1, kdim)
+    for kdim in (64, 128, 256, 512):
+        ldp = 512
+        m = LIM // (2 * ldp) - 128 - 1
+        assert bf16l_guard_ok(m, kdim, ldp) and syrk_bf16l_offsets(m, kdim, 1, ldp)["load"] < LIM
+        assert not bf16l_guard_ok(m + 1, kdim, ldp)
     src = open(os.path.join(CSRC, "potrf.hip")).read()
-    assert "kb % BFL_KC == 0 && (m + 128) * kb * 2 < ((int64_t)1 << 31)" in src
+    assert "kdim % BFL_KC == 0 && (m + 128) * ldp * 2 < ((int64_t)1 << 31)" in src
     assert "constexpr int BFL_KC = 64;" in src
+    assert "constexpr int BF_LDP = 512;" in src
 
 
 @pytest.mark.parametrize("es,label", [(4, "binary32 working copy"), (8, "FP64 fallback copy")])
@@ -122,7 +142,7 @@ def test_host_guard_implies_every_offset_fits(es, kdim):
             last_ok = m
             for v in syrk_offsets(m, kdim, m, es).values():
                 assert v < LIM
-            if es == 4:
+            if es == 4 and bf16_ring_guard_ok(m):
                 for v in syrk_bf16_offsets(m, kdim, m).values():
                     assert v < LIM
         m = m * 2 if m < 4096 else m + 4096
@@ -141,12 +161,12 @@ def test_library_guard_matches_the_formula():
     """The launch guard in the source is the formula this test evaluates."""
     src = open(os.path.join(CSRC, "potrf.hip")).read()
     assert "(m + (kdim + 64) * lda) * (int64_t)sizeof(S) >= ((int64_t)1 << 31) - 65536" in src
-    assert "(m + (int64_t)(kb + 64) * lda) * 4 >= ((int64_t)1 << 31) - 65536" in src
+    assert "(m + (kdim + 64) * lda) * 4 >= ((int64_t)1 << 31) - 65536" in src
 
 
 @pytest.mark.parametrize("fname,kname,pattern", [
-    ("potrf.hip", "k_pack_bf16", r"const int64_t groups = kb / 8, tot = m \* groups;"),
-    ("potrf.hip", "k_pack_bf16", r"const int64_t row = e % m, gq = e / m;"),
+    ("potrf.hip", "k_trsm_panel", r"const int64_t row = R \+ 16 \* h2 \+ i;"),
+    ("potrf.hip", "k_trsm_panel", r"\(Pq \+ row \* ldq \+ 16 \* t \+ tcol<S>\(g, 0\)\)"),
     ("mixed.hip", "k_sym_rowprod", r"\(size_t\)blockIdx\.y \* n \+ gi"),
     ("mixed.hip", "k_sym_finish", r"\(\(size_t\)sp \* n \+ gi\)"),
     ("potrs.hip", "k_sweep", r"L\[idx\(rwc, c0 \+ c, lda\)\]"),
