@@ -441,22 +441,47 @@ __global__ __launch_bounds__(256) void k_sweep_check(T* Out, int64_t ld, int64_t
     for (int64_t e = threadIdx.x; e < tot; e += 256) Out[idx(e % n, e / n, ld)] = (T)NAN;
 }
 
+// Many right-hand sides (an inverse, a gradient): passes of 64 instead of
+// 16 (RT = 4; one workgroup per CU instead of two), so that the factor is
+// streamed a quarter as many times.  Each right-hand side sees the same
+// products in the same order either way.
+constexpr int64_t SW_WIDE = 256;  // right-hand sides from which passes take 64
+static int64_t wide_passes(int64_t nrhs) { return cdiv(nrhs, 4 * SW_NR); }
+
+template <typename T, bool FWD, bool INV>
+static void launch_sweep(hipStream_t st, bool wide, dim3 grid, const T* L, int64_t lda, int64_t n, int64_t nrhs,
+                         const T* In, int64_t ldi, T* Out, int64_t ldo, SweepSync* sy, int32_t* info, int spin_limit) {
+    if constexpr (sizeof(T) == 8) {
+        if (wide) {
+            hipLaunchKernelGGL((k_sweep<T, 4, FWD, INV>), grid, dim3(256), 0, st, L, lda, n, nrhs, In, ldi, Out, ldo,
+                               sy, info, spin_limit, (const int32_t*)nullptr);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_sweep<T, 1, FWD, INV>), grid, dim3(256), 0, st, L, lda, n, nrhs, In, ldi, Out, ldo, sy, info,
+                       spin_limit, (const int32_t*)nullptr);
+}
+
+// the wide passes (binary64 only: binary32 at 64 right-hand sides per pass
+// would spill under the kernel's two-workgroup register cap)
+template <typename T>
+static bool use_wide(int64_t nrhs) { return sizeof(T) == 8 && nrhs >= SW_WIDE; }
+
 template <typename T, bool INV>
 static mg_status sweep(hipStream_t st, int64_t n, int64_t nrhs, const T* L, int64_t lda, T* B, int64_t ldb, T* Y,
                        SweepSync* sy, int32_t* info, int spin_limit) {
-    const int64_t np = sweep_passes(nrhs);
+    const bool wide = use_wide<T>(nrhs);
+    const int64_t np = wide ? wide_passes(nrhs) : sweep_passes(nrhs);
     const dim3 grid((unsigned)cdiv(n, JB), (unsigned)np);
     const unsigned gfill = (unsigned)std::min<int64_t>(std::max<int64_t>(1, cdiv(n * nrhs, 256)), 2048);
     hipLaunchKernelGGL((k_sweep_init<T>), dim3(gfill), dim3(256), 0, st, Y, n, n, nrhs, sy, info);
     MG_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_sweep<T, 1, true, INV>), grid, dim3(256), 0, st, L, lda, n, nrhs, (const T*)B, ldb, Y, n, sy,
-                       info, spin_limit, (const int32_t*)nullptr);
+    launch_sweep<T, true, INV>(st, wide, grid, L, lda, n, nrhs, (const T*)B, ldb, Y, n, sy, info, spin_limit);
     MG_LAUNCH_CHECK();
     // B has been read; it now receives X
     hipLaunchKernelGGL((k_sweep_init<T>), dim3(gfill), dim3(256), 0, st, B, ldb, n, nrhs, sy + np, info);
     MG_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_sweep<T, 1, false, INV>), grid, dim3(256), 0, st, L, lda, n, nrhs, (const T*)Y, n, B, ldb,
-                       sy + np, info, spin_limit, (const int32_t*)nullptr);
+    launch_sweep<T, false, INV>(st, wide, grid, L, lda, n, nrhs, (const T*)Y, n, B, ldb, sy + np, info, spin_limit);
     MG_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_sweep_check<T>), dim3(1), dim3(256), 0, st, B, ldb, n, nrhs, (const SweepSync*)sy,
                        (int)(2 * np), info);
@@ -494,17 +519,16 @@ mg_status trsm_lt_impl(mg_handle_t h, int64_t n, int64_t nrhs, const T* L, int64
     hipStream_t st = h->stream;
     SweepSync* sy = (SweepSync*)words;
     const int lim = h->spin_limit < 0 ? SWEEP_SPIN_LIMIT : h->spin_limit;
-    const int64_t np = sweep_passes(nrhs);
+    const bool wide = use_wide<T>(nrhs);
+    const int64_t np = wide ? wide_passes(nrhs) : sweep_passes(nrhs);
     const dim3 grid((unsigned)cdiv(n, JB), (unsigned)np);
     const unsigned gfill = (unsigned)std::min<int64_t>(std::max<int64_t>(1, cdiv(n * nrhs, 256)), 2048);
     hipLaunchKernelGGL((k_sweep_init<T>), dim3(gfill), dim3(256), 0, st, Out, ldo, n, nrhs, sy, info);
     MG_LAUNCH_CHECK();
     if (h->solve_mode == MG_SOLVE_SUBSTITUTION)
-        hipLaunchKernelGGL((k_sweep<T, 1, false, false>), grid, dim3(256), 0, st, L, lda, n, nrhs, In, ldi, Out, ldo,
-                           sy, info, lim, (const int32_t*)nullptr);
+        launch_sweep<T, false, false>(st, wide, grid, L, lda, n, nrhs, In, ldi, Out, ldo, sy, info, lim);
     else
-        hipLaunchKernelGGL((k_sweep<T, 1, false, true>), grid, dim3(256), 0, st, L, lda, n, nrhs, In, ldi, Out, ldo,
-                           sy, info, lim, (const int32_t*)nullptr);
+        launch_sweep<T, false, true>(st, wide, grid, L, lda, n, nrhs, In, ldi, Out, ldo, sy, info, lim);
     MG_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_sweep_check<T>), dim3(1), dim3(256), 0, st, Out, ldo, n, nrhs, (const SweepSync*)sy,
                        (int)np, info);

@@ -89,6 +89,31 @@ def test_solve_modes(mg, orc, n, nrhs):
         assert err <= 4 * kappa * (e1[j] + e2[j] + EPS), (j, err)
 
 
+@pytest.mark.parametrize("mode", ["inverse", "substitution"])
+@pytest.mark.parametrize("n,nrhs", [(700, 300), (1100, 520)])
+def test_many_rhs_passes_match_narrow_passes_bitwise(mg, orc, mode, n, nrhs):
+    """From 256 right-hand sides on, an FP64 sweep takes them 64 per pass
+    (16 below); every right-hand side sees the same products in the same
+    order either way, so solving a slice of columns alone (16 or fewer: the
+    narrow passes) gives those columns bit for bit.  Ragged orders and a
+    ragged last pass; eta <= 1e-12 against the oracle."""
+    A = synth.gram_spd_cond(n, 79 + n, 1e4)
+    B = synth.normal((n, nrhs), 80 + n)
+    h = mg.handle()
+    h.set_solve_mode(mode)
+    try:
+        print(f"[potrs] wide passes n={n} nrhs={nrhs} {mode}", flush=True)
+        L, info = mg.potrf(torch.from_numpy(A).cuda())
+        assert int(info) == 0
+        X = mg.potrs(L, torch.from_numpy(B).cuda(), info=info).cpu().numpy()
+        for c0, c1 in ((0, 16), (nrhs - 13, nrhs), (nrhs // 2, nrhs // 2 + 7)):
+            Xs = mg.potrs(L, torch.from_numpy(np.ascontiguousarray(B[:, c0:c1])).cuda(), info=info).cpu().numpy()
+            assert np.array_equal(Xs, X[:, c0:c1]), (c0, c1)
+    finally:
+        h.set_solve_mode("inverse")
+    assert np.all(orc.backward_error(A, X, B) <= 1e-12)
+
+
 @pytest.mark.parametrize("n", [64, 1000])
 def test_inverse_mode_closed_forms(mg, n):
     """Default (inverse) sweeps on closed forms: diag(1..n) with b = ones
