@@ -300,8 +300,11 @@ mg_status mg_posv_backward(mg_handle_t handle, int64_t n, int64_t nrhs, const do
  * only its lower triangle is read.  gA: ldga x n output (also used as
  * scratch: every entry of its n x n block may be written).  work: device
  * scratch of mg_potrf_backward_buffer_size bytes (an n x n FP64 matrix and
- * the sweep words).  The two triangular solves it performs (n right-hand
- * sides each) follow mg_set_solve_mode.  info: optional device int32 of the
+ * the sweep words or the 64 x 64 diagonal inverses).  The two triangular
+ * solves it performs (n right-hand sides each) are, when n is a multiple of
+ * 64, blocked right solves with L (each 64-column block multiplied by its
+ * diagonal block's inverse, then a rank-64 update on the matrix pipe);
+ * otherwise sweeps that follow mg_set_solve_mode.  info: optional device int32 of the
  * factorisation, in/out; when it is non-zero the entries of gA the mode
  * writes are NaN; a sweep that gives up sets it to MG_INFO_SOLVE_ABORTED
  * (with the same NaN outputs).

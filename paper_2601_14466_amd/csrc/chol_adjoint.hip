@@ -21,6 +21,10 @@
 //   4. gA <- R = L^{-T} Q^T = S^T by the backward sweep;
 //   5. gA <- sym(R) in place (k_sym_pairs: one thread per pair (i, j), so
 //      the two halves are written from the same two values).
+// Where n is a multiple of 64 (and the offsets fit), steps 2-4 are done as
+// right solves with L by 64-column blocks on the matrix pipe instead of
+// sweeps: gA <- P^T, gA <- gA L^-1 = Q^T, W <- Q, W <- W L^-1 = R^T,
+// gA <- R (the transposes tile-wise through LDS).
 #include <algorithm>
 
 #include "mg_internal.h"
@@ -130,8 +134,20 @@ __global__ __launch_bounds__(256) void k_sym_pairs(double* R, int64_t ldr, int64
         }
 }
 
+// D = S^T for n x n FP64 matrices (skipped when *info != 0).
+mg_status transpose_f64(hipStream_t st, const double* S, int64_t lds, double* D, int64_t ldd, int64_t n,
+                        const int32_t* info) {
+    if (n <= 0) return MG_OK;
+    const int64_t T = cdiv(n, PT);
+    hipLaunchKernelGGL(k_transpose, dim3((unsigned)(T * T)), dim3(256), 0, st, S, lds, D, ldd, n, info);
+    MG_LAUNCH_CHECK();
+    return MG_OK;
+}
+
 size_t potrf_backward_work_bytes(int64_t n) {
-    return n == 0 ? 0 : align_up((size_t)n * (size_t)n * 8, 256) + 2 * sweep_words_bytes(n);
+    return n == 0 ? 0
+                  : align_up((size_t)n * (size_t)n * 8, 256) +
+                        std::max(2 * sweep_words_bytes(n), right_solve_lower_work_bytes(n));
 }
 
 mg_status potrf_backward_impl(mg_handle_t h, int64_t n, const double* L, int64_t lda, const double* GL,
@@ -144,11 +160,27 @@ mg_status potrf_backward_impl(mg_handle_t h, int64_t n, const double* L, int64_t
     hipLaunchKernelGGL(k_phi_ltgl, dim3((unsigned)(T * T)), dim3(256), 0, st, L, lda, GL, ldgl, n, W, n, info);
     MG_LAUNCH_CHECK();
     mg_status rc;
-    if ((rc = trsm_lt_impl<double>(h, n, n, L, lda, W, n, GA, ldga, words, info))) return rc;  // Q = L^-T P
-    hipLaunchKernelGGL(k_transpose, dim3((unsigned)(T * T)), dim3(256), 0, st, GA, ldga, W, n, n, info);
-    MG_LAUNCH_CHECK();
-    if ((rc = trsm_lt_impl<double>(h, n, n, L, lda, W, n, GA, ldga, words + sweep_words_bytes(n), info)))
-        return rc;  // R = L^-T Q^T = S^T
+    if (right_solve_lower_ok(n, n, lda, std::max<int64_t>(n, ldga))) {
+        // Blocked: the two solves as right solves with L on the matrix pipe,
+        // Q^T = P^T L^-1 and R^T = Q L^-1 (the gradient is symmetric in S and
+        // S^T = R, so R^T serves as well as R).
+        double* Zw = (double*)words;
+        const dim3 tg((unsigned)(T * T));
+        hipLaunchKernelGGL(k_transpose, tg, dim3(256), 0, st, W, n, GA, ldga, n, info);  // GA = P^T
+        MG_LAUNCH_CHECK();
+        if ((rc = right_solve_lower(st, n, n, L, lda, GA, ldga, Zw))) return rc;          // GA = Q^T
+        hipLaunchKernelGGL(k_transpose, tg, dim3(256), 0, st, GA, ldga, W, n, n, info);  // W = Q
+        MG_LAUNCH_CHECK();
+        if ((rc = right_solve_lower(st, n, n, L, lda, W, n, Zw))) return rc;              // W = R^T
+        hipLaunchKernelGGL(k_transpose, tg, dim3(256), 0, st, W, n, GA, ldga, n, info);  // GA = R
+        MG_LAUNCH_CHECK();
+    } else {
+        if ((rc = trsm_lt_impl<double>(h, n, n, L, lda, W, n, GA, ldga, words, info))) return rc;  // Q = L^-T P
+        hipLaunchKernelGGL(k_transpose, dim3((unsigned)(T * T)), dim3(256), 0, st, GA, ldga, W, n, n, info);
+        MG_LAUNCH_CHECK();
+        if ((rc = trsm_lt_impl<double>(h, n, n, L, lda, W, n, GA, ldga, words + sweep_words_bytes(n), info)))
+            return rc;  // R = L^-T Q^T = S^T
+    }
     const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 256), 64));
     const unsigned gy = (unsigned)std::min<int64_t>(std::max<int64_t>(1, n), 4096);
     hipLaunchKernelGGL(k_sym_pairs, dim3(gx, gy), dim3(256), 0, st, GA, ldga, n, mode, info);

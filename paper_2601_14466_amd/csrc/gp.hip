@@ -115,7 +115,8 @@ __global__ __launch_bounds__(256) void k_gp_grad_y(const double* __restrict__ Al
 
 static size_t gp_grad_work_bytes(int64_t n) {
     if (n == 0) return 0;
-    return align_up((size_t)n * (size_t)n * 8, 256) + potrs_work_bytes(n, n, 8);  // A^{-1}, then the sweeps' space
+    // A^{-1}, then the sweeps' space, then the blocked solves' diagonal inverses
+    return align_up((size_t)n * (size_t)n * 8, 256) + potrs_work_bytes(n, n, 8) + right_solve_lower_work_bytes(n);
 }
 
 static size_t gp_work_bytes(int64_t n, int64_t nrhs) {
@@ -218,8 +219,19 @@ mg_status mg_gp_loglik_grad(mg_handle_t h, int64_t n, int64_t nrhs, const double
     hipLaunchKernelGGL(k_gp_eye, dim3(gsq), dim3(256), 0, st, Ainv, n);
     MG_LAUNCH_CHECK();
     mg_status rc;
-    if ((rc = potrs_impl<double>(h, n, n, L, lda, Ainv, n, Yw, info))) return rc;  // A^{-1} = L^{-T} L^{-1} I
-    hipLaunchKernelGGL(k_gp_grad_a, dim3(gsq), dim3(256), 0, st, Ainv, n, Alpha, ldalpha, nrhs, g, gA, ldga, info);
+    const double* Ai = Ainv;
+    if (right_solve_lower_ok(n, n, lda, n)) {
+        // blocked right solves with L on the matrix pipe: I L^-1 = L^-1, then
+        // L^-T L^-1 = A^{-1} from its transpose
+        double* Zw = (double*)((char*)Yw + potrs_work_bytes(n, n, 8));
+        if ((rc = right_solve_lower(st, n, n, L, lda, Ainv, n, Zw))) return rc;
+        if ((rc = transpose_f64(st, Ainv, n, Yw, n, n, info))) return rc;
+        if ((rc = right_solve_lower(st, n, n, L, lda, Yw, n, Zw))) return rc;
+        Ai = Yw;
+    } else if ((rc = potrs_impl<double>(h, n, n, L, lda, Ainv, n, Yw, info))) {  // A^{-1} = L^{-T} L^{-1} I
+        return rc;
+    }
+    hipLaunchKernelGGL(k_gp_grad_a, dim3(gsq), dim3(256), 0, st, Ai, n, Alpha, ldalpha, nrhs, g, gA, ldga, info);
     MG_LAUNCH_CHECK();
     if (any) {
         const unsigned gy = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (n * nrhs + 255) / 256), 4096);

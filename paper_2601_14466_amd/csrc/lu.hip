@@ -672,6 +672,16 @@ static mg_status gemm_sub(hipStream_t st, double* C, int64_t ldc, const double* 
     return MG_OK;
 }
 
+// C (m x nn, ldc) -= X (m x kdim, ldx) Z (kdim x nn, ldz), kdim % 16 == 0 (a
+// multiple of 256: the C-folding variant); the caller keeps every byte
+// offset below 2^31.
+mg_status gemm_sub_f64(hipStream_t st, double* C, int64_t ldc, const double* X, int64_t ldx, const double* Z,
+                       int64_t ldz, int64_t m, int64_t nn, int64_t kdim) {
+    if (kdim % 16 != 0) return MG_ERR_UNSUPPORTED;
+    return kdim % 256 == 0 ? gemm_sub<true>(st, C, ldc, X, ldx, Z, ldz, m, nn, (int)kdim)
+                           : gemm_sub<false>(st, C, ldc, X, ldx, Z, ldz, m, nn, (int)kdim);
+}
+
 mg_status getrf_impl(mg_handle_t h, int64_t n, double* A, int64_t lda, int32_t* ipiv, void* work, int32_t* info) {
     hipStream_t st = h->stream;
     mg_status rc = set_info_zero(st, info);

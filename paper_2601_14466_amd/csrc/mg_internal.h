@@ -52,6 +52,19 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 mg_status prof_begin(mg_handle_t h, int kind, hipStream_t st);
 mg_status prof_end(mg_handle_t h, int kind, double flops, double bytes, hipStream_t st);
 
+// D = S^T, n x n FP64, 64 x 64 tiles through LDS; skipped when *info != 0.
+mg_status transpose_f64(hipStream_t st, const double* S, int64_t lds, double* D, int64_t ldd, int64_t n,
+                        const int32_t* info);
+// C -= X Z on the FP64 matrix pipe (the general update kernel of the LU).
+mg_status gemm_sub_f64(hipStream_t st, double* C, int64_t ldc, const double* X, int64_t ldx, const double* Z,
+                       int64_t ldz, int64_t m, int64_t nn, int64_t kdim);
+// Y L = C in place (C m x n, L lower n x n, n % 64 == 0) by 64-column blocks;
+// Zw: right_solve_lower_work_bytes(n) of device scratch.
+bool right_solve_lower_ok(int64_t m, int64_t n, int64_t lda, int64_t ldc);
+size_t right_solve_lower_work_bytes(int64_t n);
+mg_status right_solve_lower(hipStream_t st, int64_t m, int64_t n, const double* L, int64_t lda, double* C,
+                            int64_t ldc, double* Zw);
+
 // Block size used by potrf for order n and element size es.
 int64_t potrf_block_size(mg_handle_t h, int64_t n, int es);
 

@@ -441,6 +441,103 @@ __global__ __launch_bounds__(256) void k_sweep_check(T* Out, int64_t ld, int64_t
     for (int64_t e = threadIdx.x; e < tot; e += 256) Out[idx(e % n, e / n, ld)] = (T)NAN;
 }
 
+// ---------------------------------------------------------------------------
+// Y L = C in place for a wide C (m x n, column-major) and L lower n x n,
+// n % 64 == 0: blocked from the right in 64-column blocks.  With all the
+// diagonal inverses Z_b = L_bb^{-1} formed first (one workgroup per block,
+// stage_inverse), block b's columns become Y_b = C_b Z_b (k_right_mul, in
+// place, a 64-row strip per workgroup on the FP64 matrix pipe) and the
+// columns to its left receive C[:, 0:c0] -= Y_b L[c0:c0+64, 0:c0] on the
+// general update kernel, by groups of four blocks (rank 256).  The substitution chain of the
+// sweeps becomes n / 64 steps of matrix products, for problems with as many
+// right-hand sides as rows (the adjoint of the factorisation).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_diag_inverse(const double* __restrict__ L, int64_t lda, int64_t n,
+                                                      double* __restrict__ Zw) {
+    __shared__ double Ls[JB * LDP];
+    __shared__ double rp[JB];
+    const int64_t r0 = (int64_t)blockIdx.x * JB;
+    const int jb = (int)(n - r0 < JB ? n - r0 : JB);
+    stage_inverse<double, 0>(Ls, rp, L, lda, r0, jb);
+    double* Z = Zw + (size_t)blockIdx.x * JB * JB;  // column-major, leading dimension 64
+    for (int e = threadIdx.x; e < JB * JB; e += 256) {
+        const int r = e & (JB - 1), c = e >> 6;
+        Z[r + c * JB] = Ls[r * LDP + c];
+    }
+}
+
+// Cb (m x 64, ldc) <- Cb Z for Z 64 x 64 (column-major, leading dimension
+// 64): wave w of workgroup s takes rows 64 s + 16 w .. + 15, all 64 columns,
+// reading its rows completely before it writes them.
+__global__ __launch_bounds__(256) void k_right_mul(double* __restrict__ Cb, int64_t ldc, int64_t m,
+                                                   const double* __restrict__ Z) {
+    __shared__ double Zs[JB][LDP];  // Zs[k][j] = Z(k, j)
+    for (int e = threadIdx.x; e < JB * JB; e += 256) {
+        const int k = e & (JB - 1), j = e >> 6;
+        Zs[k][j] = Z[k + j * JB];
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+    const int64_t row = (int64_t)blockIdx.x * JB + 16 * w + i;
+    const bool rok = row < m;
+    double x[JB / 4];
+#pragma unroll
+    for (int ks = 0; ks < JB / 4; ++ks) x[ks] = rok ? Cb[idx(row, 4 * ks + g, ldc)] : 0.0;
+    V4<double> acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = V4<double>{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < JB / 4; ++ks)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = mma_xzt(acc[t], x[ks], Zs[4 * ks + g][16 * t + i]);
+    if (!rok) return;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Cb[idx(row, 16 * t + tcol<double>(g, r), ldc)] = acc[t][r];
+}
+
+constexpr int64_t RS_GROUP = 4;  // 64-column blocks per rank-256 update
+
+bool right_solve_lower_ok(int64_t m, int64_t n, int64_t lda, int64_t ldc) {
+    // the update kernel's 32-bit byte offsets (C, the group's Y columns and
+    // the L block rows, from their bases)
+    const int64_t ld = std::max(lda, ldc);
+    return n > 0 && n % JB == 0 && (std::max(m, n) + (RS_GROUP + 1) * JB) * ld * 8 < ((int64_t)1 << 31);
+}
+
+size_t right_solve_lower_work_bytes(int64_t n) { return align_up((size_t)n * JB * 8, 256); }
+
+mg_status right_solve_lower(hipStream_t st, int64_t m, int64_t n, const double* L, int64_t lda, double* C,
+                            int64_t ldc, double* Zw) {
+    if (m <= 0 || n <= 0) return MG_OK;
+    if (!right_solve_lower_ok(m, n, lda, ldc)) return MG_ERR_UNSUPPORTED;
+    const int64_t nblk = n / JB;
+    hipLaunchKernelGGL(k_diag_inverse, dim3((unsigned)nblk), dim3(256), 0, st, L, lda, n, Zw);
+    MG_LAUNCH_CHECK();
+    mg_status rc;
+    // groups of RS_GROUP blocks from the right: inside a group each block
+    // updates the group's blocks to its left (rank 64); the finished group
+    // then updates everything to its left at once (rank 256), which moves C
+    // a quarter as many times as rank-64 updates would
+    for (int64_t bh = nblk - 1; bh >= 0; bh -= RS_GROUP) {
+        const int64_t bl = std::max<int64_t>(0, bh - RS_GROUP + 1), g0 = bl * JB;
+        for (int64_t b = bh; b >= bl; --b) {
+            const int64_t c0 = b * JB;
+            hipLaunchKernelGGL(k_right_mul, dim3((unsigned)cdiv(m, JB)), dim3(256), 0, st, C + idx(0, c0, ldc), ldc,
+                               m, (const double*)(Zw + (size_t)b * JB * JB));
+            MG_LAUNCH_CHECK();
+            if (c0 > g0 && (rc = gemm_sub_f64(st, C + idx(0, g0, ldc), ldc, C + idx(0, c0, ldc), ldc,
+                                              L + idx(c0, g0, lda), lda, m, c0 - g0, JB)))
+                return rc;
+        }
+        if (g0 > 0 && (rc = gemm_sub_f64(st, C, ldc, C + idx(0, g0, ldc), ldc, L + g0, lda, m, g0,
+                                         (bh - bl + 1) * JB)))
+            return rc;
+    }
+    return MG_OK;
+}
+
 // Many right-hand sides (an inverse, a gradient): passes of 64 instead of
 // 16 (RT = 4; one workgroup per CU instead of two), so that the factor is
 // streamed a quarter as many times.  Each right-hand side sees the same

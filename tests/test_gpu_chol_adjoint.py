@@ -28,8 +28,10 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-@pytest.mark.parametrize("n", [1, 2, 17, 64, 65, 200, 513])
+@pytest.mark.parametrize("n", [1, 2, 17, 64, 65, 128, 200, 512, 513, 1024])
 def test_matches_oracle(mg, orc, n):
+    """Orders that are multiples of 64 take the blocked right solves, the
+    others the sweeps."""
     A = synth.gram_spd(n, 300 + n)
     W = synth.normal((n, n), 301 + n)
     L, info = mg.potrf(torch.from_numpy(A).cuda())
@@ -45,10 +47,10 @@ def test_matches_oracle(mg, orc, n):
             assert np.array_equal(g, g.T)
 
 
-def test_substitution_mode_and_strict_upper_never_read(mg, orc, substitution):
-    """Substitution sweeps; NaN poison in the strict upper triangles of L and
-    gL changes nothing."""
-    n = 150
+@pytest.mark.parametrize("n", [150, 256])
+def test_substitution_mode_and_strict_upper_never_read(mg, orc, substitution, n):
+    """Substitution sweeps (n = 150) or the blocked right solves (n = 256);
+    NaN poison in the strict upper triangles of L and gL changes nothing."""
     A = synth.gram_spd(n, 17)
     W = synth.normal((n, n), 18)
     L, info = mg.potrf(torch.from_numpy(A).cuda())
@@ -82,8 +84,8 @@ def test_gradcheck(mg):
     assert torch.autograd.gradcheck(f, (A,), eps=1e-6, atol=1e-7, rtol=1e-6)
 
 
-def test_failed_factor_gives_nan(mg):
-    n = 70
+@pytest.mark.parametrize("n", [70, 128])
+def test_failed_factor_gives_nan(mg, n):
     A = synth.gram_spd(n, 9)
     A[30, 30] = -5.0
     L, info = mg.potrf(torch.from_numpy(A).cuda())

@@ -108,11 +108,12 @@ def test_not_spd_and_edges(mg):
 
 
 # ------------------------------------------------------------------ gradient
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (65, 3), (300, 1), (300, 4)])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (65, 3), (300, 1), (300, 4), (64, 2), (256, 3), (512, 1)])
 def test_gradient_parity(mg, orc, n, nrhs):
     """gA = sum_j g_j (alpha_j alpha_j^T - A^{-1}) / 2 against the oracle
     (relative Frobenius error <= 1e-11; A is well conditioned), gY and gM
-    element by element, gA exactly symmetric."""
+    element by element, gA exactly symmetric.  Orders that are multiples of
+    64 form A^{-1} by the blocked right solves, the others by the sweeps."""
     A = synth.gram_spd(n, 70 + n)
     Y = synth.normal((n, nrhs), 71 + n)
     M = synth.normal((n, nrhs), 72 + n)
@@ -156,8 +157,8 @@ def test_autograd_and_finite_differences(mg, orc):
         assert fd == pytest.approx(want, rel=1e-6, abs=1e-8)
 
 
-def test_gradient_after_failed_factor_is_nan(mg):
-    n = 50
+@pytest.mark.parametrize("n", [50, 128])
+def test_gradient_after_failed_factor_is_nan(mg, n):
     A = np.eye(n)
     A[10, 10] = -1.0
     y = synth.normal(n, 90)
