@@ -14,8 +14,9 @@
 //                   upper triangle of gA is not written.
 // Steps on the GPU (W: an n x n workspace):
 //   1. W = P (lower, zeros above) by k_phi_ltgl: 64 x 64 output tiles, the
-//      16-row k-slices of L and gL staged through LDS, products on the FP64
-//      matrix pipe;
+//      32-row k-slices of L and gL staged through LDS (the next slice fetched
+//      into registers during the products), products on the FP64 matrix
+//      pipe;
 //   2. gA <- Q = L^{-T} P by the backward sweep with n right-hand sides;
 //   3. W <- Q^T (k_transpose, 64 x 64 tiles through LDS);
 //   4. gA <- R = L^{-T} Q^T = S^T by the backward sweep;
@@ -33,7 +34,7 @@
 namespace mg {
 
 constexpr int PT = 64;        // output tile of P
-constexpr int PK = 16;        // k rows staged per step
+constexpr int PK = 32;        // k rows staged per step
 constexpr int PLD = PT + 1;   // LDS leading dimension
 
 // W(r, c) = Phi(L^T gL)(r, c) for the PT x PT tile (I, J) of an n x n grid:
@@ -59,16 +60,30 @@ __global__ __launch_bounds__(256) void k_phi_ltgl(const double* __restrict__ L, 
     f64x4 acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = f64x4{0, 0, 0, 0};
+    // the k-slices are software-pipelined: slice kb + PK is fetched into
+    // registers while slice kb is multiplied from LDS
+    constexpr int QN = PK * PT / 256;
+    double lv[QN], gv[QN];
+    auto fetch = [&](int64_t kb) {
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            const int e = tid + 256 * q, kk = e % PK, c = e / PK;
+            const int64_t k = kb + kk, rr = r0 + c, cc = c0 + c;
+            lv[q] = (k < n && rr < n && k >= rr) ? L[idx(k, rr, lda)] : 0.0;
+            gv[q] = (k < n && cc < n && k >= cc) ? GL[idx(k, cc, ldgl)] : 0.0;
+        }
+    };
     // rows k < r0 contribute nothing (L(k, r) = 0 for k < r)
+    fetch(r0);
     for (int64_t kb = r0; kb < n; kb += PK) {
 #pragma unroll
-        for (int q = 0; q < PK * PT / 256; ++q) {
-            const int e = tid + 256 * q, kk = e & (PK - 1), c = e >> 4;
-            const int64_t k = kb + kk, rr = r0 + c, cc = c0 + c;
-            Ls[kk][c] = (k < n && rr < n && k >= rr) ? L[idx(k, rr, lda)] : 0.0;
-            Gs[kk][c] = (k < n && cc < n && k >= cc) ? GL[idx(k, cc, ldgl)] : 0.0;
+        for (int q = 0; q < QN; ++q) {
+            const int e = tid + 256 * q, kk = e % PK, c = e / PK;
+            Ls[kk][c] = lv[q];
+            Gs[kk][c] = gv[q];
         }
         __syncthreads();
+        if (kb + PK < n) fetch(kb + PK);
         // wave w: rows 16 w .. 16 w + 15 of the tile, all 64 columns
 #pragma unroll
         for (int ks = 0; ks < PK / 4; ++ks) {
