@@ -448,7 +448,7 @@ __global__ __launch_bounds__(256) void k_sweep_check(T* Out, int64_t ld, int64_t
 // stage_inverse), block b's columns become Y_b = C_b Z_b (k_right_mul, in
 // place, a 64-row strip per workgroup on the FP64 matrix pipe) and the
 // columns to its left receive C[:, 0:c0] -= Y_b L[c0:c0+64, 0:c0] on the
-// general update kernel, by groups of four blocks (rank 256).  The substitution chain of the
+// general update kernel, by groups of eight blocks (rank 512).  The substitution chain of the
 // sweeps becomes n / 64 steps of matrix products, for problems with as many
 // right-hand sides as rows (the adjoint of the factorisation).
 // ---------------------------------------------------------------------------
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(256) void k_right_mul(double* __restrict__ Cb, int6
         for (int r = 0; r < 4; ++r) Cb[idx(row, 16 * t + tcol<double>(g, r), ldc)] = acc[t][r];
 }
 
-constexpr int64_t RS_GROUP = 4;  // 64-column blocks per rank-256 update
+constexpr int64_t RS_GROUP = 8;  // 64-column blocks per rank-512 update
 
 bool right_solve_lower_ok(int64_t m, int64_t n, int64_t lda, int64_t ldc) {
     // the update kernel's 32-bit byte offsets (C, the group's Y columns and
@@ -518,8 +518,8 @@ mg_status right_solve_lower(hipStream_t st, int64_t m, int64_t n, const double* 
     mg_status rc;
     // groups of RS_GROUP blocks from the right: inside a group each block
     // updates the group's blocks to its left (rank 64); the finished group
-    // then updates everything to its left at once (rank 256), which moves C
-    // a quarter as many times as rank-64 updates would
+    // then updates everything to its left at once (rank 512), which moves C
+    // an eighth as many times as rank-64 updates would
     for (int64_t bh = nblk - 1; bh >= 0; bh -= RS_GROUP) {
         const int64_t bl = std::max<int64_t>(0, bh - RS_GROUP + 1), g0 = bl * JB;
         for (int64_t b = bh; b >= bl; --b) {
