@@ -24,8 +24,9 @@
 //      the two halves are written from the same two values).
 // Where n is a multiple of 64 (and the offsets fit), steps 2-4 are done as
 // right solves with L by 64-column blocks on the matrix pipe instead of
-// sweeps: gA <- P^T, gA <- gA L^-1 = Q^T, W <- Q, W <- W L^-1 = R^T,
-// gA <- R (the transposes tile-wise through LDS).
+// sweeps: gA <- P^T, gA <- gA L^-1 = Q^T, W <- Q, W <- W L^-1 = R^T, and gA
+// is formed from R^T by k_sym_tiles (transposes and pairs tile-wise through
+// LDS).
 #include <algorithm>
 
 #include "mg_internal.h"
@@ -149,6 +150,45 @@ __global__ __launch_bounds__(256) void k_sym_pairs(double* R, int64_t ldr, int64
         }
 }
 
+// gA from R^T (W, n x n) without the transpose: tile pair (I, J), I >= J,
+// of a T x T grid per workgroup, both tiles of W staged through LDS so that
+// every read and write is coalesced.  Mode 0 writes (R_ij + R_ji)/2 to both
+// (i, j) and (j, i); mode 1 writes R_ij + R_ji below the diagonal and R_ii
+// on it and leaves the strict upper triangle alone (the expressions are
+// symmetric in R and R^T).  NaN wherever it writes when info != 0.
+__global__ __launch_bounds__(256) void k_sym_tiles(const double* __restrict__ W, int64_t ldw, double* __restrict__ G,
+                                                   int64_t ldg, int64_t n, int mode, const int32_t* info) {
+    __shared__ double a[PT][PLD], b[PT][PLD];  // a[c][r] = W(I*PT + r, J*PT + c); b[c][r] = W(J*PT + r, I*PT + c)
+    const int64_t T = (n + PT - 1) / PT;
+    const int64_t I = blockIdx.x % T, J = blockIdx.x / T;
+    if (I < J) return;
+    const bool bad = info && *info != 0;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < PT * PT; e += 256) {
+        const int rr = e & (PT - 1), cc = e >> 6;
+        const int64_t r1 = I * PT + rr, c1 = J * PT + cc, r2 = J * PT + rr, c2 = I * PT + cc;
+        a[cc][rr] = (r1 < n && c1 < n) ? W[idx(r1, c1, ldw)] : 0.0;
+        b[cc][rr] = (r2 < n && c2 < n) ? W[idx(r2, c2, ldw)] : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < PT * PT; e += 256) {
+        const int rr = e & (PT - 1), cc = e >> 6;
+        // entry (i, j) = (I*PT + rr, J*PT + cc) of the lower tile: W(i, j) = a[cc][rr], W(j, i) = b[rr][cc]
+        const int64_t i = I * PT + rr, j = J * PT + cc;
+        if (i < n && j < n && i >= j) {
+            const double v = a[cc][rr], t = b[rr][cc];
+            if (bad) G[idx(i, j, ldg)] = (double)NAN;
+            else if (i == j) G[idx(i, j, ldg)] = v;
+            else G[idx(i, j, ldg)] = mode == 0 ? 0.5 * (v + t) : v + t;
+        }
+        // entry (j', i') = (J*PT + rr, I*PT + cc) of the upper tile (mode 0): W(j', i') = b[cc][rr],
+        // W(i', j') = a[rr][cc]
+        const int64_t j2 = J * PT + rr, i2 = I * PT + cc;
+        if (mode == 0 && j2 < n && i2 < n && i2 > j2)
+            G[idx(j2, i2, ldg)] = bad ? (double)NAN : 0.5 * (a[rr][cc] + b[cc][rr]);
+    }
+}
+
 // D = S^T for n x n FP64 matrices (skipped when *info != 0).
 mg_status transpose_f64(hipStream_t st, const double* S, int64_t lds, double* D, int64_t ldd, int64_t n,
                         const int32_t* info) {
@@ -187,8 +227,9 @@ mg_status potrf_backward_impl(mg_handle_t h, int64_t n, const double* L, int64_t
         hipLaunchKernelGGL(k_transpose, tg, dim3(256), 0, st, GA, ldga, W, n, n, info);  // W = Q
         MG_LAUNCH_CHECK();
         if ((rc = right_solve_lower(st, n, n, L, lda, W, n, Zw))) return rc;              // W = R^T
-        hipLaunchKernelGGL(k_transpose, tg, dim3(256), 0, st, W, n, GA, ldga, n, info);  // GA = R
+        hipLaunchKernelGGL(k_sym_tiles, tg, dim3(256), 0, st, W, n, GA, ldga, n, mode, info);  // GA from R^T
         MG_LAUNCH_CHECK();
+        return MG_OK;
     } else {
         if ((rc = trsm_lt_impl<double>(h, n, n, L, lda, W, n, GA, ldga, words, info))) return rc;  // Q = L^-T P
         hipLaunchKernelGGL(k_transpose, dim3((unsigned)(T * T)), dim3(256), 0, st, GA, ldga, W, n, n, info);
